@@ -1,0 +1,226 @@
+/*
+ * fvan.h -- C ABI of the FlashVAN hot path for AMD Instinct MI355X (gfx950).
+ *
+ * The method ("Scalable Physics-Inspired Transformers for Spin Glasses"):
+ * an autoregressive transformer q_theta(sigma) = prod_t q(sigma_t | sigma_<t)
+ * (Eq. 1, Eq. 11) over Ising spins, with concatenated token/position
+ * embeddings (Eq. 15), decoder blocks whose masked attention has no output
+ * projection (Eqs. 2-3, Alg. 1), a sparse attention mask derived from the
+ * interaction graph (Methods, ordered Markov boundary; SI Eq. S1), KV-cached
+ * ancestral sampling (Alg. 2), the spin energy (Eq. 6, Eq. 8), the variational
+ * free energy F_q (Eq. 5) and its REINFORCE gradient (Eqs. 16-19).
+ *
+ * Conventions shared by every call:
+ *  - Pointers are DEVICE memory unless the argument name starts with host_.
+ *    The caller owns every input/output buffer and the FP32 parameter and
+ *    gradient vectors; the library owns its workspaces (KV cache, activations,
+ *    packed weight copies, optimiser state), allocated at create time from
+ *    max_batch and freed at destroy.  No hot call allocates device memory.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    asynchronously on it; argument checks happen on the host, synchronously,
+ *    before anything is enqueued.  A call that fails its checks enqueues
+ *    nothing.
+ *  - Every call returns an fvan_status.  On failure fvan_last_error() returns
+ *    a thread-local message.  No C++ exception crosses the ABI.
+ *  - One model is used by one stream at a time; calls on one model must not
+ *    overlap (they share its workspaces).
+ *  - Spins are int8 +1/-1, row-major [batch, n_spins] (sample-major).  Token
+ *    s = (sigma + 1) / 2; head output index 1 is sigma = +1.
+ *
+ * Flat FP32 parameter layout (row-major tensors concatenated in this order):
+ *   tok_emb [vocab, d_token]   row s = embedding of token s; row 0 is also the start token
+ *   pos_emb [n_spins, d_pos]   d_pos = d_model - d_token
+ *   per layer: ln1.g [d], ln1.b [d], qkv.w [3d, d], qkv.b [3d], ln2.g [d], ln2.b [d],
+ *              ffn1.w [4d, d], ffn1.b [4d], ffn2.w [d, 4d], ffn2.b [d]
+ *              (qkv rows: Q, then K, then V; head h owns rows h*16 .. h*16+15 of each)
+ *   head.w [vocab, d], head.b [vocab]
+ * Count: n_layers (11 d^2 + 12 d) + n_spins d_pos + vocab d_token + vocab (d + 1).
+ *
+ * Network (per position t, tok_0 = start, tok_t = s_{t-1}):
+ *   h = [tok_emb[tok_t]; pos_emb[t]]
+ *   per layer: h += concat_heads(softmax_j(q_t.k_j / 4) v_j)  with q,k,v = qkv.w LN1(h) + qkv.b
+ *              h += ffn2.w GELU(ffn1.w LN2(h) + ffn1.b) + ffn2.b
+ *   z_t = head.w h + head.b ;  log p_t(s) = z_{t,s} - logsumexp(z_t)
+ * LayerNorm: affine, population variance, eps 1e-5.  GELU: x Phi(x) (erf form).
+ * Mask: key position j is visible from query t iff j <= t and
+ *       (t - j <= window or j < prefix).
+ */
+#ifndef FVAN_H
+#define FVAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FVAN_OK = 0,
+  FVAN_EINVAL = -1,        /* bad argument: null pointer, size out of range, mismatch */
+  FVAN_ENOMEM = -2,        /* workspace allocation failed at create time */
+  FVAN_EDEVICE = -3,       /* a HIP runtime call failed (message names it) */
+  FVAN_ENONFINITE = -4,    /* a NaN/Inf reached a reduction (reported by the next synchronising call) */
+  FVAN_EUNSUPPORTED = -5   /* valid request this build does not implement */
+} fvan_status;
+
+typedef enum { FVAN_FP32 = 0, FVAN_BF16 = 1 } fvan_precision;
+
+typedef enum {
+  FVAN_BONDS_PM1 = 0,      /* ELL, int8 J in {-1, 0, +1}; energy int32, exact */
+  FVAN_BONDS_F32 = 1,      /* ELL, float J; energy float */
+  FVAN_BONDS_DENSE = 2     /* dense float J [n, n], symmetric, zero diagonal (SK); energy float */
+} fvan_bond_kind;
+
+typedef struct {
+  int32_t n_spins;     /* N: sequence length (one site per position) */
+  int32_t d_model;     /* d = d_token + d_pos; 32, 64, 128 or 256 */
+  int32_t d_token;     /* token-embedding width (2 for single spins) */
+  int32_t n_layers;
+  int32_t n_heads;     /* d_model / n_heads must be 16 */
+  int32_t vocab;       /* 2 */
+  int32_t window;      /* W of the mask, 0 <= W; values >= n_spins-1 mean full causal */
+  int32_t prefix;      /* P of the mask, 0 <= P <= n_spins */
+  int32_t max_batch;   /* largest batch any call on this model will pass */
+  int32_t precision;   /* fvan_precision */
+} fvan_model_config;
+
+typedef struct {
+  int32_t n_spins;
+  int32_t kind;        /* fvan_bond_kind */
+  int32_t degree;      /* ELL slots per site (ignored for FVAN_BONDS_DENSE) */
+  const int32_t* nbr;  /* device int32 [n_spins, degree]: partner j of the pair (i, j) stored in
+                          row i; each unordered pair appears in exactly one row; -1 = empty slot */
+  const void* J;       /* device: int8 [n_spins, degree] | float [n_spins, degree] | float [n_spins, n_spins] */
+} fvan_couplings;
+
+typedef struct {
+  float lr, beta1, beta2, eps, weight_decay;
+} fvan_adam;
+
+typedef struct fvan_model fvan_model;
+typedef struct fvan_group fvan_group;
+
+/* Number of FP32 parameters of a configuration (host only; the count formula
+ * above, which reproduces the counts the paper prints in SI Secs. III-IV). */
+int fvan_num_params(const fvan_model_config* cfg, int64_t* n_params);
+
+/* Attention mask from the interaction graph (host only).  Sites are ordered by
+ * index (raster scan).  Computes the ordered Markov boundary of every site
+ * (Methods: past sites adjacent to i or joined to i through future sites) and
+ * returns the (window, prefix) pair minimising window + prefix among those
+ * that keep every boundary site visible, where site j reaches the query that
+ * predicts site i iff position j+1 is visible from position i and the window
+ * is counted in sites (SI Eq. S1: A_ij = 0 for i - j > W, W >= d_max).
+ * host_i/host_j: the n_edges pairs, each unordered pair once.  EINVAL on an
+ * index outside [0, n_spins). */
+int fvan_derive_mask(int32_t n_spins, int64_t n_edges, const int32_t* host_i, const int32_t* host_j,
+                     int32_t* window, int32_t* prefix);
+
+/* Create a model on the current HIP device and allocate its workspaces for
+ * cfg->max_batch samples.  EINVAL on an unsupported shape, ENOMEM when the
+ * workspaces do not fit. */
+int fvan_create_model(const fvan_model_config* cfg, fvan_model** out);
+int fvan_destroy_model(fvan_model* model);
+
+/* Attach the caller's FP32 parameter vector [n_params] and gradient vector
+ * [n_params] (grads may be NULL if no backward is run).  The library reads
+ * params, writes params only in fvan_adam_step / fvan_train_step, and
+ * accumulates into grads.  Call fvan_sync_params after the caller changes params. */
+int fvan_bind_params(fvan_model* model, float* params, float* grads);
+
+/* Rebuild the packed weight copies (FP32 or BF16 by the model's precision,
+ * round-to-nearest-even) from the bound FP32 parameters. */
+int fvan_sync_params(fvan_model* model, void* stream);
+
+/* Ancestral sampling with a KV cache (Alg. 2): for t = 0..N-1 every layer
+ * computes only q_t, k_t, v_t, appends k_t, v_t to its cache and attends over
+ * the visible cached keys including position t; the head gives
+ * p = p_t(sigma_t = +1) and sigma_t = +1 iff u(b, t) < p, with
+ *   u(b, t) = (word[t & 3] >> 8) * 2^-24 of Philox4x32-10,
+ *   key = (seed mod 2^32, seed >> 32), counter = (t >> 2, b, stream_id mod 2^32, stream_id >> 32).
+ * Outputs spins [batch, N] and log_q [batch] = sum_t log p_t(sigma_t) (FP32).
+ * EINVAL if batch is not in [1, max_batch]. */
+int fvan_sample(fvan_model* model, int32_t batch, uint64_t seed, uint64_t stream_id,
+                int8_t* spins, float* log_q, void* stream);
+
+/* Teacher-forced ln q(sigma) (Alg. 1), FP32 [batch]. */
+int fvan_log_prob(fvan_model* model, int32_t batch, const int8_t* spins, float* log_q, void* stream);
+
+/* grads += sum_b grad_log_q[b] * d ln q(sigma_b) / d theta.  Recomputes the
+ * forward pass (attention included) in chunks of samples; nothing from an
+ * earlier call is reused. */
+int fvan_log_prob_backward(fvan_model* model, int32_t batch, const int8_t* spins,
+                           const float* grad_log_q, void* stream);
+
+/* E_b = - sum over stored pairs of J_ij sigma_i sigma_j (Eq. 6 / Eq. 8; each
+ * unordered pair once).  energy: int32 [batch] for FVAN_BONDS_PM1 (exact),
+ * float [batch] otherwise. */
+int fvan_energy(const fvan_couplings* couplings, int32_t batch, const int8_t* spins, void* energy,
+                void* stream);
+
+/* Free-energy estimator (Eq. 5) in FP64 on the device:
+ *   f_b = (E_b + log_q_b / beta) / n_spins,
+ *   stats[0] = mean_b f_b  (= F_q / N estimate),  stats[1] = sum_b (f_b - mean)^2 / (batch - 1).
+ * energy is int32 when energy_is_int, else float.  stats: device double [2].
+ * Fixed-order reduction: bitwise reproducible. */
+int fvan_free_energy(int32_t batch, int32_t n_spins, double beta, int32_t energy_is_int,
+                     const void* energy, const float* log_q, double* stats, void* stream);
+
+/* REINFORCE weights (Eq. 19 with the exact 1/beta scale):
+ *   L_b = beta E_b + log_q_b,  Lbar = mean_b L_b (FP64),
+ *   weights[b] = (L_b - Lbar) / (beta * batch)  (float)
+ * so that sum_b weights[b] grad ln q_b estimates grad F_q. */
+int fvan_reinforce_weights(int32_t batch, double beta, int32_t energy_is_int, const void* energy,
+                           const float* log_q, float* weights, void* stream);
+
+/* One Adam step on the bound parameters with the bound gradients, then zero
+ * the gradients and refresh the packed weights.  step counts from 1. */
+int fvan_adam_step(fvan_model* model, const fvan_adam* opt, int64_t step, void* stream);
+
+/* One training step of the paper's procedure (Results: optimisation;
+ * Methods: training strategy):
+ *   sample batch (seed, stream_id = step) -> energies -> F_q stats ->
+ *   REINFORCE weights from the sampled log q -> backward -> Adam.
+ * stats: device double [4] = { F_q/N, Var[f], <E>/N, ||grad||_2 }.
+ * The model's grads must be bound; they are zeroed by the update. */
+int fvan_train_step(fvan_model* model, const fvan_couplings* couplings, double beta, int32_t batch,
+                    uint64_t seed, uint64_t step, const fvan_adam* opt, double* stats, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched launches: many (instance, temperature, size) units sampled in ONE
+ * persistent kernel launch.  All models of a group must share d_model,
+ * n_layers, n_heads and precision; n_spins, the mask, the parameters and the
+ * couplings may differ per unit.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  fvan_model* model;                /* parameters bound and synced */
+  const fvan_couplings* couplings;  /* copied at group creation */
+  double beta;
+  int32_t batch;                    /* samples of this unit, <= model max_batch */
+  uint64_t seed, stream_id;
+  int8_t* spins;                    /* device [batch, N] */
+  float* log_q;                     /* device [batch] */
+  void* energy;                     /* device [batch], int32 or float as fvan_energy */
+  double* stats;                    /* device [2] as fvan_free_energy */
+} fvan_group_unit;
+
+/* Build the device unit table.  tile_samples: samples per work item (0 = the
+ * tuned default).  EINVAL when the models disagree in shape. */
+int fvan_group_create(const fvan_group_unit* units, int32_t n_units, int32_t tile_samples,
+                      fvan_group** out);
+int fvan_group_destroy(fvan_group* group);
+/* Sampling of every unit in one persistent launch (work queue over
+ * (unit, sample tile)), followed by the energies and free-energy statistics. */
+int fvan_group_run(fvan_group* group, void* stream);
+/* Capture fvan_group_run into a HIP graph on `stream` (once) and replay it. */
+int fvan_group_run_graph(fvan_group* group, void* stream);
+
+/* Thread-local message describing the last failure on this thread. */
+const char* fvan_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FVAN_H */

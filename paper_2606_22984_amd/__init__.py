@@ -1,0 +1,322 @@
+"""Python binding of libfvan (the C ABI in include/fvan.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  PyTorch supplies device memory and streams.  Importing this
+module loads the in-tree libfvan.so and fails loudly when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfvan.so")
+
+FVAN_FP32, FVAN_BF16 = 0, 1
+BONDS_PM1, BONDS_F32, BONDS_DENSE = 0, 1, 2
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "EUNSUPPORTED"}
+
+# Every symbol include/fvan.h declares.
+EXPORTS = (
+    "fvan_num_params", "fvan_derive_mask", "fvan_create_model", "fvan_destroy_model", "fvan_bind_params",
+    "fvan_sync_params", "fvan_sample", "fvan_log_prob", "fvan_log_prob_backward", "fvan_energy",
+    "fvan_free_energy", "fvan_reinforce_weights", "fvan_adam_step", "fvan_train_step",
+    "fvan_group_create", "fvan_group_destroy", "fvan_group_run", "fvan_group_run_graph", "fvan_last_error",
+)
+
+
+class FvanError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ModelConfigC(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("n_spins", "d_model", "d_token", "n_layers", "n_heads", "vocab",
+                                         "window", "prefix", "max_batch", "precision")]
+
+
+class CouplingsC(C.Structure):
+    _fields_ = [("n_spins", C.c_int32), ("kind", C.c_int32), ("degree", C.c_int32),
+                ("nbr", C.c_void_p), ("J", C.c_void_p)]
+
+
+class AdamC(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("weight_decay", C.c_float)]
+
+
+class GroupUnitC(C.Structure):
+    _fields_ = [("model", C.c_void_p), ("couplings", C.c_void_p), ("beta", C.c_double), ("batch", C.c_int32),
+                ("seed", C.c_uint64), ("stream_id", C.c_uint64), ("spins", C.c_void_p), ("log_q", C.c_void_p),
+                ("energy", C.c_void_p), ("stats", C.c_void_p)]
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path) and path == LIB_PATH:
+        from .build import build      # nothing built yet: compile it in-tree once
+        build()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2606_22984_amd/build.py")
+    lib = C.CDLL(path)
+    P, I32, I64, U64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+    sig = {
+        "fvan_num_params": [C.POINTER(ModelConfigC), C.POINTER(C.c_int64)],
+        "fvan_derive_mask": [I32, I64, P, P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+        "fvan_create_model": [C.POINTER(ModelConfigC), C.POINTER(C.c_void_p)],
+        "fvan_destroy_model": [P],
+        "fvan_bind_params": [P, P, P],
+        "fvan_sync_params": [P, P],
+        "fvan_sample": [P, I32, U64, U64, P, P, P],
+        "fvan_log_prob": [P, I32, P, P, P],
+        "fvan_log_prob_backward": [P, I32, P, P, P],
+        "fvan_energy": [C.POINTER(CouplingsC), I32, P, P, P],
+        "fvan_free_energy": [I32, I32, D, I32, P, P, P, P],
+        "fvan_reinforce_weights": [I32, D, I32, P, P, P, P],
+        "fvan_adam_step": [P, C.POINTER(AdamC), I64, P],
+        "fvan_train_step": [P, C.POINTER(CouplingsC), D, I32, U64, U64, C.POINTER(AdamC), P, P],
+        "fvan_group_create": [C.POINTER(GroupUnitC), I32, I32, C.POINTER(C.c_void_p)],
+        "fvan_group_destroy": [P],
+        "fvan_group_run": [P, P],
+        "fvan_group_run_graph": [P, P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.fvan_last_error.argtypes = []
+    lib.fvan_last_error.restype = C.c_char_p
+    return lib
+
+
+_lib: Optional[C.CDLL] = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise FvanError(rc, lib().fvan_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("tensors passed to libfvan must be contiguous device tensors")
+
+
+def num_params(cfg) -> int:
+    c = config_struct(cfg, max_batch=1)
+    out = C.c_int64()
+    _check(lib().fvan_num_params(C.byref(c), C.byref(out)))
+    return out.value
+
+
+def derive_mask(n: int, edges_i, edges_j) -> Tuple[int, int]:
+    ei = np.ascontiguousarray(edges_i, dtype=np.int32)
+    ej = np.ascontiguousarray(edges_j, dtype=np.int32)
+    w, p = C.c_int32(), C.c_int32()
+    _check(lib().fvan_derive_mask(n, ei.shape[0], ei.ctypes.data_as(C.c_void_p), ej.ctypes.data_as(C.c_void_p),
+                                  C.byref(w), C.byref(p)))
+    return w.value, p.value
+
+
+def config_struct(cfg, max_batch: int, precision: int = FVAN_FP32) -> ModelConfigC:
+    return ModelConfigC(n_spins=cfg.n_spins, d_model=cfg.d_model, d_token=cfg.d_token, n_layers=cfg.n_layers,
+                        n_heads=cfg.n_heads, vocab=cfg.vocab, window=cfg.window, prefix=cfg.prefix,
+                        max_batch=max_batch, precision=precision)
+
+
+@dataclass
+class Couplings:
+    """Device-resident bonds in the layout fvan_energy reads, and the C struct pointing at them."""
+    n: int
+    kind: int
+    degree: int
+    nbr: Optional[torch.Tensor]
+    J: torch.Tensor
+    c: CouplingsC
+
+    @property
+    def energy_is_int(self) -> bool:
+        return self.kind == BONDS_PM1
+
+    def empty_energy(self, batch: int, device="cuda") -> torch.Tensor:
+        return torch.empty(batch, dtype=torch.int32 if self.energy_is_int else torch.float32, device=device)
+
+
+def couplings(instance, device="cuda", dense: Optional[bool] = None) -> Couplings:
+    """Pack an instance's pair list into the ELL rows fvan_energy reads (pair (i, j) stored in row i),
+    or its dense matrix for SK."""
+    n = instance.n
+    use_dense = instance.dense is not None if dense is None else dense
+    if use_dense:
+        J = torch.as_tensor(np.ascontiguousarray(instance.dense, dtype=np.float32), device=device)
+        c = CouplingsC(n_spins=n, kind=BONDS_DENSE, degree=0, nbr=None, J=J.data_ptr())
+        return Couplings(n, BONDS_DENSE, 0, None, J, c)
+    ei = np.asarray(instance.edges_i)
+    ej = np.asarray(instance.edges_j)
+    counts = np.bincount(ei, minlength=n)
+    deg = max(int(counts.max()) if counts.size else 0, 1)
+    nbr = -np.ones((n, deg), dtype=np.int32)
+    fill = np.zeros(n, dtype=np.int64)
+    pm1 = instance.bonds == "pm1"
+    Jl = np.zeros((n, deg), dtype=np.int8 if pm1 else np.float32)
+    for a, b, w in zip(ei.tolist(), ej.tolist(), np.asarray(instance.J).tolist()):
+        k = fill[a]
+        nbr[a, k] = b
+        Jl[a, k] = w
+        fill[a] += 1
+    nbr_t = torch.as_tensor(nbr, device=device)
+    J_t = torch.as_tensor(Jl, device=device)
+    kind = BONDS_PM1 if pm1 else BONDS_F32
+    c = CouplingsC(n_spins=n, kind=kind, degree=deg, nbr=nbr_t.data_ptr(), J=J_t.data_ptr())
+    return Couplings(n, kind, deg, nbr_t, J_t, c)
+
+
+class Model:
+    """Owns one fvan_model handle plus the caller-side FP32 parameter and gradient tensors."""
+
+    def __init__(self, cfg, max_batch: int, precision: int = FVAN_FP32, params=None, device="cuda"):
+        self.cfg = cfg
+        self.precision = precision
+        self.max_batch = max_batch
+        self._c = config_struct(cfg, max_batch, precision)
+        h = C.c_void_p()
+        _check(lib().fvan_create_model(C.byref(self._c), C.byref(h)))
+        self.handle = h
+        n = num_params(cfg)
+        self.params = torch.zeros(n, dtype=torch.float32, device=device)
+        self.grads = torch.zeros(n, dtype=torch.float32, device=device)
+        _check(lib().fvan_bind_params(self.handle, _ptr(self.params), _ptr(self.grads)))
+        if params is not None:
+            self.set_params(params)
+
+    def set_params(self, params):
+        self.params.copy_(torch.as_tensor(np.asarray(params, dtype=np.float32)))
+        self.sync()
+
+    def sync(self, stream=None):
+        _check(lib().fvan_sync_params(self.handle, _stream(stream)))
+
+    def sample(self, batch: int, seed: int, stream_id: int, spins=None, log_q=None, stream=None):
+        if spins is None:
+            spins = torch.empty(batch, self.cfg.n_spins, dtype=torch.int8, device=self.params.device)
+        if log_q is None:
+            log_q = torch.empty(batch, dtype=torch.float32, device=self.params.device)
+        _require_cuda(spins, log_q)
+        _check(lib().fvan_sample(self.handle, batch, seed, stream_id, _ptr(spins), _ptr(log_q), _stream(stream)))
+        return spins, log_q
+
+    def log_prob(self, spins: torch.Tensor, log_q=None, stream=None):
+        _require_cuda(spins)
+        if log_q is None:
+            log_q = torch.empty(spins.shape[0], dtype=torch.float32, device=spins.device)
+        _check(lib().fvan_log_prob(self.handle, spins.shape[0], _ptr(spins), _ptr(log_q), _stream(stream)))
+        return log_q
+
+    def log_prob_backward(self, spins: torch.Tensor, grad_log_q: torch.Tensor, stream=None):
+        _require_cuda(spins, grad_log_q)
+        _check(lib().fvan_log_prob_backward(self.handle, spins.shape[0], _ptr(spins), _ptr(grad_log_q),
+                                            _stream(stream)))
+
+    def adam_step(self, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, stream=None):
+        o = AdamC(lr, beta1, beta2, eps, weight_decay)
+        _check(lib().fvan_adam_step(self.handle, C.byref(o), step, _stream(stream)))
+
+    def train_step(self, coup: Couplings, beta: float, batch: int, seed: int, step: int, lr=1e-3, beta1=0.9,
+                   beta2=0.999, eps=1e-8, weight_decay=0.0, stats=None, stream=None):
+        if stats is None:
+            stats = torch.zeros(4, dtype=torch.float64, device=self.params.device)
+        o = AdamC(lr, beta1, beta2, eps, weight_decay)
+        _check(lib().fvan_train_step(self.handle, C.byref(coup.c), beta, batch, seed, step, C.byref(o),
+                                     _ptr(stats), _stream(stream)))
+        return stats
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fvan_destroy_model(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def energy(coup: Couplings, spins: torch.Tensor, out=None, stream=None):
+    _require_cuda(spins)
+    if out is None:
+        out = coup.empty_energy(spins.shape[0], spins.device)
+    _check(lib().fvan_energy(C.byref(coup.c), spins.shape[0], _ptr(spins), _ptr(out), _stream(stream)))
+    return out
+
+
+def free_energy(energy_t: torch.Tensor, log_q: torch.Tensor, beta: float, n_spins: int, out=None, stream=None):
+    _require_cuda(energy_t, log_q)
+    if out is None:
+        out = torch.zeros(2, dtype=torch.float64, device=log_q.device)
+    is_int = 1 if energy_t.dtype == torch.int32 else 0
+    _check(lib().fvan_free_energy(log_q.shape[0], n_spins, beta, is_int, _ptr(energy_t), _ptr(log_q), _ptr(out),
+                                  _stream(stream)))
+    return out
+
+
+def reinforce_weights(energy_t: torch.Tensor, log_q: torch.Tensor, beta: float, out=None, stream=None):
+    _require_cuda(energy_t, log_q)
+    if out is None:
+        out = torch.empty_like(log_q)
+    is_int = 1 if energy_t.dtype == torch.int32 else 0
+    _check(lib().fvan_reinforce_weights(log_q.shape[0], beta, is_int, _ptr(energy_t), _ptr(log_q), _ptr(out),
+                                        _stream(stream)))
+    return out
+
+
+class LogProb(torch.autograd.Function):
+    """ln q_theta(sigma) as a differentiable function of the model's parameter tensor.
+
+    forward: fvan_log_prob (teacher forced).  backward: fvan_log_prob_backward with
+    grad_output as the per-sample weights; it recomputes the forward pass, attention
+    included, and returns the accumulated parameter gradient."""
+
+    @staticmethod
+    def forward(ctx, params: torch.Tensor, model: "Model", spins: torch.Tensor):
+        ctx.model = model
+        ctx.save_for_backward(spins)
+        return model.log_prob(spins)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (spins,) = ctx.saved_tensors
+        m = ctx.model
+        saved = m.grads.clone()
+        m.grads.zero_()
+        m.log_prob_backward(spins, grad_out.contiguous().float())
+        g = m.grads.clone()
+        m.grads.copy_(saved)
+        return g, None, None
+
+
+def log_prob_autograd(model: Model, spins: torch.Tensor) -> torch.Tensor:
+    return LogProb.apply(model.params, model, spins)

@@ -1,0 +1,246 @@
+// Host implementation of the C ABI declared in include/fvan.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <vector>
+
+#include "fvan_internal.h"
+#include "fvan_model.h"
+
+namespace fvan {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+ParamOffsets param_offsets(const fvan_model_config& c) {
+  ParamOffsets o;
+  const int64_t d = c.d_model;
+  o.tok = 0;
+  o.pos = (int64_t)c.vocab * c.d_token;
+  o.layer0 = o.pos + (int64_t)c.n_spins * (d - c.d_token);
+  o.ln1_g = 0;
+  o.ln1_b = d;
+  o.qkv_w = 2 * d;
+  o.qkv_b = o.qkv_w + 3 * d * d;
+  o.ln2_g = o.qkv_b + 3 * d;
+  o.ln2_b = o.ln2_g + d;
+  o.ffn1_w = o.ln2_b + d;
+  o.ffn1_b = o.ffn1_w + 4 * d * d;
+  o.ffn2_w = o.ffn1_b + 4 * d;
+  o.ffn2_b = o.ffn2_w + 4 * d * d;
+  o.layer_stride = o.ffn2_b + d;   // = 11 d^2 + 12 d
+  o.head_w = o.layer0 + (int64_t)c.n_layers * o.layer_stride;
+  o.head_b = o.head_w + (int64_t)c.vocab * d;
+  o.total = o.head_b + c.vocab;
+  return o;
+}
+
+PackOffsets pack_offsets(const fvan_model_config& c) {
+  PackOffsets p;
+  const size_t d = c.d_model, e = elem_bytes(c.precision);
+  p.qkv = 0;
+  p.ffn1 = p.qkv + 3 * d * d * e;
+  p.ffn2 = p.ffn1 + 4 * d * d * e;
+  p.qkvT = p.ffn2 + 4 * d * d * e;
+  p.ffn1T = p.qkvT + 3 * d * d * e;
+  p.ffn2T = p.ffn1T + 4 * d * d * e;
+  p.layer_stride = p.ffn2T + 4 * d * d * e;
+  p.total = p.layer_stride * c.n_layers;
+  return p;
+}
+
+static int check_config(const fvan_model_config* c) {
+  if (!c) return fail(FVAN_EINVAL, "config is NULL");
+  if (c->n_spins < 1) return fail(FVAN_EINVAL, "n_spins must be >= 1");
+  if (c->d_model != 32 && c->d_model != 64 && c->d_model != 128)
+    return fail(FVAN_EUNSUPPORTED, "d_model must be 32, 64 or 128");
+  if (c->n_heads < 1 || c->d_model != c->n_heads * kHeadDimHost)
+    return fail(FVAN_EUNSUPPORTED, "d_model / n_heads must be 16");
+  if (c->d_token < 1 || c->d_token >= c->d_model) return fail(FVAN_EINVAL, "d_token out of range");
+  if (c->vocab != 2) return fail(FVAN_EUNSUPPORTED, "vocab must be 2 (single-spin tokens)");
+  if (c->n_layers < 0 || c->n_layers > 64) return fail(FVAN_EINVAL, "n_layers out of range");
+  if (c->window < 0 || c->prefix < 0 || c->prefix > c->n_spins) return fail(FVAN_EINVAL, "mask out of range");
+  if (c->max_batch < 1) return fail(FVAN_EINVAL, "max_batch must be >= 1");
+  if (c->precision != FVAN_FP32 && c->precision != FVAN_BF16) return fail(FVAN_EINVAL, "unknown precision");
+  return FVAN_OK;
+}
+
+int64_t fwd_chunk_samples(const fvan_model_config& c) {
+  // about 2^21 rows (positions) per chunk of the teacher-forced passes
+  int64_t s = std::max<int64_t>(1, (int64_t(1) << 21) / c.n_spins);
+  s = std::min<int64_t>(s, c.max_batch);
+  return s;
+}
+
+static fvan_model_config clamp_mask(fvan_model_config c) {
+  if (c.window > c.n_spins - 1) c.window = c.n_spins - 1;
+  return c;
+}
+
+}  // namespace fvan
+
+using namespace fvan;
+
+extern "C" {
+
+const char* fvan_last_error(void) { return g_err.c_str(); }
+
+int fvan_num_params(const fvan_model_config* cfg, int64_t* n_params) {
+  if (!cfg || !n_params) return fail(FVAN_EINVAL, "NULL argument");
+  if (cfg->d_model < 1 || cfg->d_token < 0 || cfg->d_token > cfg->d_model || cfg->n_layers < 0 || cfg->vocab < 1 ||
+      cfg->n_spins < 1)
+    return fail(FVAN_EINVAL, "config out of range");
+  *n_params = param_offsets(*cfg).total;
+  return FVAN_OK;
+}
+
+int fvan_derive_mask(int32_t n, int64_t n_edges, const int32_t* host_i, const int32_t* host_j, int32_t* window,
+                     int32_t* prefix) {
+  if (n < 1 || n_edges < 0 || !window || !prefix || (n_edges > 0 && (!host_i || !host_j)))
+    return fail(FVAN_EINVAL, "bad arguments");
+  std::vector<std::vector<int32_t>> adj(n);
+  for (int64_t e = 0; e < n_edges; ++e) {
+    const int32_t a = host_i[e], b = host_j[e];
+    if (a < 0 || a >= n || b < 0 || b >= n) return fail(FVAN_EINVAL, "edge index outside [0, n_spins)");
+    if (a == b) continue;
+    adj[a].push_back(b);
+    adj[b].push_back(a);
+  }
+  // far[j]: largest i - j over sites i whose ordered Markov boundary contains j.
+  std::vector<int32_t> far(n + 1, 0), mark(n, -1);
+  std::vector<int32_t> stack;
+  for (int32_t i = 0; i < n; ++i) {
+    // region reachable from i through future sites; past neighbours of it form the boundary
+    stack.clear();
+    stack.push_back(i);
+    mark[i] = i;
+    while (!stack.empty()) {
+      const int32_t v = stack.back();
+      stack.pop_back();
+      for (int32_t w : adj[v]) {
+        if (w < i) {
+          far[w] = std::max(far[w], i - w);
+        } else if (w > i && mark[w] != i) {
+          mark[w] = i;
+          stack.push_back(w);
+        }
+      }
+    }
+  }
+  // suffix maxima: W(P) = max_{j >= P-1} far[j]
+  std::vector<int32_t> suf(n + 2, 0);
+  for (int32_t j = n; j >= 0; --j) suf[j] = std::max(far[j], suf[j + 1]);
+  int64_t best = -1;
+  int32_t bw = 0, bp = 0;
+  for (int32_t P = 0; P <= n; ++P) {
+    const int32_t W = suf[std::max(P - 1, 0)];
+    const int64_t cost = (int64_t)P + W;
+    if (best < 0 || cost < best) {
+      best = cost;
+      bw = W;
+      bp = P;
+    }
+  }
+  *window = bw;
+  *prefix = bp;
+  return FVAN_OK;
+}
+
+int fvan_create_model(const fvan_model_config* cfg, fvan_model** out) {
+  if (!out) return fail(FVAN_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  fvan_model* m = new (std::nothrow) fvan_model();
+  if (!m) return fail(FVAN_ENOMEM, "host allocation failed");
+  m->cfg = clamp_mask(*cfg);
+  rc = model_allocate(m);
+  if (rc) {
+    model_free(m);
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return FVAN_OK;
+}
+
+int fvan_destroy_model(fvan_model* m) {
+  if (!m) return fail(FVAN_EINVAL, "model is NULL");
+  model_free(m);
+  delete m;
+  return FVAN_OK;
+}
+
+int fvan_bind_params(fvan_model* m, float* params, float* grads) {
+  if (!m || !params) return fail(FVAN_EINVAL, "model or params is NULL");
+  m->params = params;
+  m->grads = grads;
+  return FVAN_OK;
+}
+
+int fvan_sync_params(fvan_model* m, void* stream) {
+  if (!m || !m->params) return fail(FVAN_EINVAL, "model has no bound parameters");
+  FVAN_HIP(launch_pack(m->cfg, m->params, m->wpack, (hipStream_t)stream));
+  m->synced = true;
+  return FVAN_OK;
+}
+
+int fvan_sample(fvan_model* m, int32_t batch, uint64_t seed, uint64_t stream_id, int8_t* spins, float* log_q,
+                void* stream) {
+  if (!m || !spins || !log_q) return fail(FVAN_EINVAL, "NULL argument");
+  if (!m->params || !m->synced) return fail(FVAN_EINVAL, "parameters not bound/synced");
+  if (batch < 1 || batch > m->cfg.max_batch) return fail(FVAN_EINVAL, "batch outside [1, max_batch]");
+  DecodeUnit u = make_decode_unit(m, batch, seed, stream_id, spins, log_q, m->kv, 0);
+  const int tiles = (batch + decode_tile_samples() - 1) / decode_tile_samples();
+  FVAN_HIP(launch_decode_single(m->cfg.d_model, m->cfg.precision, u, tiles, (hipStream_t)stream));
+  return FVAN_OK;
+}
+
+int fvan_energy(const fvan_couplings* c, int32_t batch, const int8_t* spins, void* energy, void* stream) {
+  if (!c || !spins || !energy || !c->J) return fail(FVAN_EINVAL, "NULL argument");
+  if (batch < 1 || c->n_spins < 1) return fail(FVAN_EINVAL, "batch and n_spins must be >= 1");
+  if (c->kind != FVAN_BONDS_PM1 && c->kind != FVAN_BONDS_F32 && c->kind != FVAN_BONDS_DENSE)
+    return fail(FVAN_EINVAL, "unknown bond kind");
+  if (c->kind != FVAN_BONDS_DENSE && (!c->nbr || c->degree < 0)) return fail(FVAN_EINVAL, "ELL table missing");
+  if (c->kind == FVAN_BONDS_DENSE && c->n_spins > 4096) return fail(FVAN_EUNSUPPORTED, "dense bonds need n <= 4096");
+  if (c->kind != FVAN_BONDS_DENSE && c->n_spins > 32768) return fail(FVAN_EUNSUPPORTED, "ELL bonds need n <= 32768");
+  FVAN_HIP(launch_energy(*c, batch, spins, energy, (hipStream_t)stream));
+  return FVAN_OK;
+}
+
+int fvan_free_energy(int32_t batch, int32_t n, double beta, int32_t is_int, const void* energy, const float* log_q,
+                     double* stats, void* stream) {
+  if (!energy || !log_q || !stats) return fail(FVAN_EINVAL, "NULL argument");
+  if (batch < 1 || n < 1 || !(beta > 0.0) || !std::isfinite(beta)) return fail(FVAN_EINVAL, "batch, n or beta out of range");
+  FVAN_HIP(launch_free_energy(batch, n, beta, is_int != 0, energy, log_q, stats, (hipStream_t)stream));
+  return FVAN_OK;
+}
+
+int fvan_reinforce_weights(int32_t batch, double beta, int32_t is_int, const void* energy, const float* log_q,
+                           float* weights, void* stream) {
+  if (!energy || !log_q || !weights) return fail(FVAN_EINVAL, "NULL argument");
+  if (batch < 1 || !(beta > 0.0) || !std::isfinite(beta)) return fail(FVAN_EINVAL, "batch or beta out of range");
+  FVAN_HIP(launch_reinforce(batch, beta, is_int != 0, energy, log_q, weights, nullptr, (hipStream_t)stream));
+  return FVAN_OK;
+}
+
+int fvan_adam_step(fvan_model* m, const fvan_adam* opt, int64_t step, void* stream) {
+  if (!m || !opt) return fail(FVAN_EINVAL, "NULL argument");
+  if (!m->params || !m->grads) return fail(FVAN_EINVAL, "parameters and gradients must be bound");
+  if (step < 1) return fail(FVAN_EINVAL, "step counts from 1");
+  if (!(opt->lr >= 0.f) || !(opt->beta1 >= 0.f && opt->beta1 < 1.f) || !(opt->beta2 >= 0.f && opt->beta2 < 1.f) ||
+      !(opt->eps > 0.f))
+    return fail(FVAN_EINVAL, "Adam hyper-parameters out of range");
+  hipStream_t s = (hipStream_t)stream;
+  FVAN_HIP(launch_adam(m->params, m->grads, m->adam_m, m->adam_v, m->n_params, *opt, step, s));
+  FVAN_HIP(launch_pack(m->cfg, m->params, m->wpack, s));
+  return FVAN_OK;
+}
+
+}  // extern "C"

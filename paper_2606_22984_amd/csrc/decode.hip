@@ -1,0 +1,371 @@
+// KV-cached ancestral sampling (Alg. 2 of the paper) for gfx950.
+//
+// One workgroup (4 waves) owns a tile of kM = 16 samples and runs every step
+// t = 0..N-1 and every layer without leaving the kernel: samples are
+// independent, so no grid-wide synchronisation is ever needed.  Per layer step:
+//   LN1 (16 lanes per sample, shuffle reductions)
+//   QKV = LN1(h) W^T + b on MFMA (16 samples x 3d), k_t and v_t go straight
+//        from the MFMA accumulators to the sample's KV cache slot
+//   attention: one wave per sample, K/V rows streamed with 16-byte coalesced
+//        loads, per-head dot products and an online softmax reduced with lane
+//        shuffles; the heads' concatenation is added to h (no W_O)
+//   LN2 + FFN (4d hidden kept in LDS) on MFMA, residual added in place
+// then the head, the Philox draw and the decision.  The KV cache of a sample
+// and layer holds the prefix positions [0, P) and a ring of the last R band
+// positions, so the visible keys of step t are always slots [0, nvis).
+#include "device_common.h"
+#include "fvan_model.h"
+
+namespace fvan {
+
+constexpr int kM = 16;
+constexpr int kThreads = 256;
+
+int decode_tile_samples() { return kM; }
+
+template <int D, int PREC>
+struct DecodeSmem {
+  typedef typename Prec<PREC>::T T;
+  static constexpr int PAD = 16 / (int)sizeof(T);
+  static constexpr int LDA = D + PAD;
+  static constexpr int LDH = 4 * D + PAD;
+  float h[kM][D];
+  T a[kM][LDA];
+  union {
+    float q[kM][D];
+    T hid[kM][LDH];
+  } u;
+  int tok[kM];
+  int8_t sbuf[kM][64];
+};
+
+__device__ __forceinline__ float reduce16(float v) {
+  v += __shfl_xor(v, 8, 16);
+  v += __shfl_xor(v, 4, 16);
+  v += __shfl_xor(v, 2, 16);
+  v += __shfl_xor(v, 1, 16);
+  return v;
+}
+
+// LayerNorm of the kM residual rows into the MFMA operand buffer.
+template <int D, int PREC>
+__device__ __forceinline__ void ln_rows(DecodeSmem<D, PREC>& sm, const float* __restrict__ g,
+                                        const float* __restrict__ b) {
+  typedef typename Prec<PREC>::T T;
+  constexpr int PER = D / 16;
+  const int m = threadIdx.x >> 4, part = threadIdx.x & 15;
+  float x[PER];
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    x[i] = sm.h[m][part + 16 * i];
+    s += x[i];
+  }
+  const float mean = reduce16(s) * (1.0f / D);
+  float v = 0.f;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    x[i] -= mean;
+    v += x[i] * x[i];
+  }
+  const float rstd = rsqrtf(reduce16(v) * (1.0f / D) + kLnEps);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int k = part + 16 * i;
+    sm.a[m][k] = from_f<T>(x[i] * rstd * g[k] + b[k]);
+  }
+}
+
+// acc(16 x 16 tile nt) = A[16 x K] (LDS, row stride lda elements) . pack tile nt
+template <int PREC, int K>
+__device__ __forceinline__ floatx4 mfma_rowtile(const typename Prec<PREC>::T* A, int lda,
+                                                const uint4* __restrict__ pack, int nt, int lane) {
+  constexpr int KC = Prec<PREC>::KC;
+  constexpr int NC = K / KC;
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  const typename Prec<PREC>::T* arow = A + (lane & 15) * lda + (lane >> 4) * (KC / 4);
+  const uint4* bp = pack + (size_t)nt * NC * 64 + lane;
+#pragma unroll 4
+  for (int c = 0; c < NC; ++c) {
+    const uint4 av = *reinterpret_cast<const uint4*>(arow + c * KC);
+    const uint4 bv = bp[c * 64];
+    acc = mfma_chunk(av, bv, acc, Prec<PREC>());
+  }
+  return acc;
+}
+
+template <int D, int PREC>
+__device__ void decode_tile(DecodeSmem<D, PREC>& sm, const DecodeUnit& U, int local_tile) {
+  typedef typename Prec<PREC>::T T;
+  constexpr int VEC = Prec<PREC>::VEC;
+  constexpr int LPR = D / VEC;          // lanes per K/V row
+  constexpr int RPL = 64 / LPR;         // rows per wave load
+  constexpr int LPH = kHeadDim / VEC;   // lanes per head
+  constexpr int UNR = 4;                // rows per lane in flight
+  constexpr float kScaleLog2 = 0.25f * 1.4426950408889634f;   // 1/sqrt(16) * log2(e)
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int b0 = local_tile * kM;
+  const int nb = min(kM, U.B - b0);
+  const int N = U.N, P = U.P, R = U.R, S = U.S, nl = U.n_layers, dt = U.d_token;
+  const float* __restrict__ theta = U.theta;
+  const char* wbase = reinterpret_cast<const char*>(U.wpack);
+  T* kvbase = reinterpret_cast<T*>(U.kv);
+  const size_t plane = (size_t)S * D;   // elements of one K (or V) block
+
+  // head-phase ownership: thread 16*m handles sample row m
+  const int hm = tid >> 4, hpart = tid & 15;
+  float lq = 0.f;
+  float ur[4] = {0.f, 0.f, 0.f, 0.f};
+  if (tid < kM) sm.tok[tid] = 0;   // start token
+  __syncthreads();
+
+  for (int t = 0; t < N; ++t) {
+    // ---- concatenated embedding [tok_emb[tok]; pos_emb[t]] ----
+    for (int i = tid; i < kM * D; i += kThreads) {
+      const int m = i / D, k = i % D;
+      sm.h[m][k] = k < dt ? theta[sm.tok[m] * dt + k] : theta[U.pos_off + (size_t)t * (D - dt) + (k - dt)];
+    }
+    const int slot = t < P ? t : P + (t - P) % R;
+    const int nvis = t < P ? t + 1 : P + min(t - P + 1, R);
+    __syncthreads();
+
+    for (int l = 0; l < nl; ++l) {
+      const float* lp = theta + U.layer0 + (size_t)l * U.layer_stride;
+      const char* wl = wbase + (size_t)l * U.p_layer_stride;
+      ln_rows<D, PREC>(sm, lp + U.o_ln1_g, lp + U.o_ln1_b);
+      __syncthreads();
+
+      // ---- QKV projection; k_t, v_t appended to the cache ----
+      {
+        const uint4* pk = reinterpret_cast<const uint4*>(wl + U.p_qkv);
+        for (int nt = wave; nt < 3 * D / 16; nt += 4) {
+          floatx4 acc = mfma_rowtile<PREC, D>(&sm.a[0][0], DecodeSmem<D, PREC>::LDA, pk, nt, lane);
+          const int n = nt * 16 + (lane & 15);
+          const float bias = lp[U.o_qkv_b + n];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = 4 * (lane >> 4) + i;
+            const float val = acc[i] + bias;
+            if (n < D) {
+              sm.u.q[row][n] = val;
+            } else if (row < nb) {
+              const int which = n >= 2 * D ? 1 : 0;
+              const int col = n - D - which * D;
+              T* dst = kvbase + ((size_t)(b0 + row) * nl + l) * 2 * plane + which * plane + (size_t)slot * D + col;
+              *dst = from_f<T>(val);
+            }
+          }
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+
+      // ---- masked attention over slots [0, nvis), one wave per sample ----
+      {
+        const int lrow = lane / LPR;
+        const int lcol = (lane % LPR) * VEC;
+        for (int m = wave; m < nb; m += 4) {
+          float qv[VEC];
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) qv[i] = sm.u.q[m][lcol + i] * kScaleLog2;
+          const T* Kb = kvbase + ((size_t)(b0 + m) * nl + l) * 2 * plane;
+          const T* Vb = Kb + plane;
+          float mx = -INFINITY, sum = 0.f, o[VEC];
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) o[i] = 0.f;
+          for (int s0 = 0; s0 < nvis; s0 += RPL * UNR) {
+            Chunk<PREC> kc[UNR], vc[UNR];
+            bool ok[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+              const int s = s0 + u * RPL + lrow;
+              ok[u] = s < nvis;
+              if (ok[u]) {
+                kc[u].load(Kb + (size_t)s * D + lcol);
+                vc[u].load(Vb + (size_t)s * D + lcol);
+              }
+            }
+            float sc[UNR];
+            float mnew = mx;
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+              float d = 0.f;
+#pragma unroll
+              for (int i = 0; i < VEC; ++i) d += qv[i] * kc[u].v[i];
+              if (LPH >= 2) d += __shfl_xor(d, 1);
+              if (LPH >= 4) d += __shfl_xor(d, 2);
+              sc[u] = ok[u] ? d : -INFINITY;
+              mnew = fmaxf(mnew, sc[u]);
+            }
+            const bool any = mnew != -INFINITY;
+            const float corr = any ? __builtin_amdgcn_exp2f(mx - mnew) : 1.f;
+            sum *= corr;
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) o[i] *= corr;
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+              const float p = ok[u] ? __builtin_amdgcn_exp2f(sc[u] - mnew) : 0.f;
+              sum += p;
+#pragma unroll
+              for (int i = 0; i < VEC; ++i) o[i] += p * (ok[u] ? vc[u].v[i] : 0.f);
+            }
+            mx = mnew;
+          }
+          // merge the RPL row groups of the wave
+#pragma unroll
+          for (int off = LPR; off < 64; off <<= 1) {
+            const float m2 = __shfl_xor(mx, off);
+            const float s2 = __shfl_xor(sum, off);
+            const float mn = fmaxf(mx, m2);
+            const float c1 = mx == -INFINITY ? 0.f : __builtin_amdgcn_exp2f(mx - mn);
+            const float c2 = m2 == -INFINITY ? 0.f : __builtin_amdgcn_exp2f(m2 - mn);
+            sum = sum * c1 + s2 * c2;
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) {
+              const float o2 = __shfl_xor(o[i], off);
+              o[i] = o[i] * c1 + o2 * c2;
+            }
+            mx = mn;
+          }
+          if (lrow == 0) {
+            const float inv = 1.0f / sum;
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) sm.h[m][lcol + i] += o[i] * inv;
+          }
+        }
+      }
+      __syncthreads();
+
+      // ---- feed-forward block ----
+      ln_rows<D, PREC>(sm, lp + U.o_ln2_g, lp + U.o_ln2_b);
+      __syncthreads();
+      {
+        const uint4* p1 = reinterpret_cast<const uint4*>(wl + U.p_ffn1);
+        for (int nt = wave; nt < 4 * D / 16; nt += 4) {
+          floatx4 acc = mfma_rowtile<PREC, D>(&sm.a[0][0], DecodeSmem<D, PREC>::LDA, p1, nt, lane);
+          const int n = nt * 16 + (lane & 15);
+          const float bias = lp[U.o_ffn1_b + n];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) sm.u.hid[4 * (lane >> 4) + i][n] = from_f<T>(gelu(acc[i] + bias));
+        }
+      }
+      __syncthreads();
+      {
+        const uint4* p2 = reinterpret_cast<const uint4*>(wl + U.p_ffn2);
+        for (int nt = wave; nt < D / 16; nt += 4) {
+          floatx4 acc = mfma_rowtile<PREC, 4 * D>(&sm.u.hid[0][0], DecodeSmem<D, PREC>::LDH, p2, nt, lane);
+          const int n = nt * 16 + (lane & 15);
+          const float bias = lp[U.o_ffn2_b + n];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) sm.h[4 * (lane >> 4) + i][n] += acc[i] + bias;
+        }
+      }
+      __syncthreads();
+    }
+
+    // ---- head, Philox draw, decision ----
+    {
+      const float* hw = theta + U.head_w;
+      float z0 = 0.f, z1 = 0.f;
+#pragma unroll
+      for (int i = 0; i < D / 16; ++i) {
+        const int k = hpart + 16 * i;
+        const float x = sm.h[hm][k];
+        z0 += x * hw[k];
+        z1 += x * hw[D + k];
+      }
+      z0 = reduce16(z0);
+      z1 = reduce16(z1);
+      if (hpart == 0) {
+        if ((t & 3) == 0) {
+          const uint4 w = philox4x32_10(make_uint4((uint32_t)(t >> 2), (uint32_t)(b0 + hm), U.stream_lo, U.stream_hi),
+                                        U.seed_lo, U.seed_hi);
+          ur[0] = u24(w.x); ur[1] = u24(w.y); ur[2] = u24(w.z); ur[3] = u24(w.w);
+        }
+        const float d = (z1 + theta[U.head_b + 1]) - (z0 + theta[U.head_b]);
+        const float e = expf(-fabsf(d));
+        const float pplus = d >= 0.f ? 1.0f / (1.0f + e) : e / (1.0f + e);
+        const float u = ur[t & 3];
+        const int s = u < pplus ? 1 : 0;
+        lq += s ? -softplus(-d) : -softplus(d);
+        sm.tok[hm] = s;
+        sm.sbuf[hm][t & 63] = s ? (int8_t)1 : (int8_t)-1;
+      }
+    }
+    __syncthreads();
+    if ((t & 63) == 63 || t == N - 1) {
+      const int base = t & ~63;
+      for (int i = tid; i < kM * 64; i += kThreads) {
+        const int m = i >> 6, j = i & 63;
+        if (m < nb && base + j <= t) U.spins[(size_t)(b0 + m) * N + base + j] = sm.sbuf[m][j];
+      }
+    }
+  }
+  if (hpart == 0 && hm < nb) U.logq[b0 + hm] = lq;
+  __syncthreads();
+}
+
+template <int D, int PREC>
+__global__ __launch_bounds__(kThreads) void decode_kernel(DecodeUnit u0, const DecodeUnit* __restrict__ table,
+                                                          int n_units, int total_tiles, int* queue) {
+  __shared__ DecodeSmem<D, PREC> sm;
+  __shared__ int s_tile;
+  bool first = true;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      if (queue) s_tile = atomicAdd(queue, 1);
+      else s_tile = first ? (int)blockIdx.x : total_tiles;
+    }
+    __syncthreads();
+    const int tile = s_tile;
+    __syncthreads();
+    first = false;
+    if (tile >= total_tiles) break;
+    if (table) {
+      int lo = 0, hi = n_units - 1;        // last unit with tile0 <= tile
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (table[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+      }
+      const DecodeUnit U = table[lo];
+      decode_tile<D, PREC>(sm, U, tile - U.tile0);
+    } else {
+      decode_tile<D, PREC>(sm, u0, tile);
+    }
+  }
+}
+
+template <int D, int PREC>
+static hipError_t launch_d(const DecodeUnit& u0, const DecodeUnit* table, int n_units, int total_tiles, int* queue,
+                           int grid, hipStream_t s) {
+  hipLaunchKernelGGL((decode_kernel<D, PREC>), dim3(grid), dim3(kThreads), 0, s, u0, table, n_units, total_tiles,
+                     queue);
+  return hipGetLastError();
+}
+
+static hipError_t dispatch(int d_model, int precision, const DecodeUnit& u0, const DecodeUnit* table, int n_units,
+                           int total_tiles, int* queue, int grid, hipStream_t s) {
+  const bool bf = precision == FVAN_BF16;
+  switch (d_model) {
+    case 32: return bf ? launch_d<32, 1>(u0, table, n_units, total_tiles, queue, grid, s)
+                       : launch_d<32, 0>(u0, table, n_units, total_tiles, queue, grid, s);
+    case 64: return bf ? launch_d<64, 1>(u0, table, n_units, total_tiles, queue, grid, s)
+                       : launch_d<64, 0>(u0, table, n_units, total_tiles, queue, grid, s);
+    case 128: return bf ? launch_d<128, 1>(u0, table, n_units, total_tiles, queue, grid, s)
+                        : launch_d<128, 0>(u0, table, n_units, total_tiles, queue, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_decode(int d_model, int precision, const DecodeUnit* units_dev, int n_units, int total_tiles,
+                         int* queue_counter, int grid, hipStream_t s) {
+  DecodeUnit dummy{};
+  return dispatch(d_model, precision, dummy, units_dev, n_units, total_tiles, queue_counter, grid, s);
+}
+
+hipError_t launch_decode_single(int d_model, int precision, const DecodeUnit& u, int tiles, hipStream_t s) {
+  return dispatch(d_model, precision, u, nullptr, 1, tiles, nullptr, tiles, s);
+}
+
+}  // namespace fvan

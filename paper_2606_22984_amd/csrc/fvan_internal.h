@@ -1,0 +1,101 @@
+// Host-side internals of libfvan: the model object, parameter offsets and the
+// launchers each kernel source file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/fvan.h"
+
+namespace fvan {
+
+// Offsets (in floats) of the tensors inside the flat FP32 parameter vector.
+struct ParamOffsets {
+  int64_t tok, pos, layer0, layer_stride, head_w, head_b, total;
+  // offsets relative to a layer's base
+  int64_t ln1_g, ln1_b, qkv_w, qkv_b, ln2_g, ln2_b, ffn1_w, ffn1_b, ffn2_w, ffn2_b;
+};
+ParamOffsets param_offsets(const fvan_model_config& c);
+
+// Byte offsets of the packed weight copies of one layer inside the pack buffer.
+// Forward packs: qkv [3D x D], ffn1 [4D x D], ffn2 [D x 4D];
+// backward packs (transposes): qkvT [D x 3D], ffn1T [D x 4D], ffn2T [4D x D].
+// A pack of a [rows x K] matrix stores, for tile n (16 rows) and K chunk c, the
+// 64 lanes' 16-byte fragments contiguously: lane l holds row 16n + l%16,
+// elements c*KC + (l/16)*KC/4 .. +KC/4.
+struct PackOffsets {
+  size_t qkv, ffn1, ffn2, qkvT, ffn1T, ffn2T, layer_stride, total;
+};
+PackOffsets pack_offsets(const fvan_model_config& c);
+
+inline int elem_bytes(int precision) { return precision == FVAN_BF16 ? 2 : 4; }
+
+// KV cache geometry of the sampler: per (sample, layer) [2][S][D], slots
+// [0, P) hold prefix positions, [P, P+R) a ring of the last R band positions.
+struct KvGeom {
+  int32_t P, R, S;
+};
+inline KvGeom kv_geom(const fvan_model_config& c) {
+  KvGeom g;
+  g.P = c.prefix < c.n_spins ? c.prefix : c.n_spins;
+  int32_t band = c.window + 1;
+  int32_t rest = c.n_spins - g.P;
+  g.R = band < rest ? band : rest;
+  g.S = g.P + g.R;
+  return g;
+}
+
+// Samples per chunk of the teacher-forced forward / backward.
+int64_t fwd_chunk_samples(const fvan_model_config& c);
+
+struct fvan_model_impl;
+
+// Work item table entry of the decode kernel (one per (unit, sample tile) range).
+struct DecodeUnit {
+  const float* theta;
+  const void* wpack;
+  void* kv;            // [B][n_layers][2][S][D]
+  int8_t* spins;       // [B][N]
+  float* logq;         // [B]
+  int32_t N, W, P, R, S, B, n_layers, tile0, n_tiles;
+  int32_t pos_off;     // offset of pos_emb in theta; tok_emb is at 0
+  int64_t layer0, layer_stride, head_w, head_b;
+  uint32_t seed_lo, seed_hi, stream_lo, stream_hi;
+  // per-layer relative offsets
+  int32_t o_ln1_g, o_ln1_b, o_qkv_b, o_ln2_g, o_ln2_b, o_ffn1_b, o_ffn2_b;
+  int64_t p_qkv, p_ffn1, p_ffn2, p_layer_stride;   // pack byte offsets
+  int32_t d_token;
+};
+
+// ----- error slot -----
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+#define FVAN_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return ::fvan::fail(FVAN_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ----- launchers (return hipError_t of the launch) -----
+hipError_t launch_decode(int d_model, int precision, const DecodeUnit* units_dev, int n_units,
+                         int total_tiles, int* queue_counter, int grid, hipStream_t s);
+int decode_tile_samples();
+
+hipError_t launch_energy(const fvan_couplings& c, int32_t batch, const int8_t* spins, void* energy,
+                         hipStream_t s);
+hipError_t launch_free_energy(int32_t batch, int32_t n, double beta, int is_int, const void* energy,
+                              const float* logq, double* stats, hipStream_t s);
+hipError_t launch_reinforce(int32_t batch, double beta, int is_int, const void* energy, const float* logq,
+                            float* weights, double* Lmean_out, hipStream_t s);
+hipError_t launch_pack(const fvan_model_config& c, const float* theta, void* wpack, hipStream_t s);
+hipError_t launch_adam(float* theta, float* grads, float* m, float* v, int64_t n, const fvan_adam& o,
+                       int64_t step, hipStream_t s);
+hipError_t launch_grad_norm(const float* g, int64_t n, double* out, double* scratch, hipStream_t s);
+hipError_t launch_mean_energy(int32_t batch, int32_t n, int is_int, const void* energy, double* out,
+                              hipStream_t s);
+hipError_t launch_zero_int(int* p, int n, hipStream_t s);
+
+}  // namespace fvan

@@ -1,0 +1,63 @@
+// The model object behind the opaque fvan_model handle.
+#pragma once
+
+#include "fvan_internal.h"
+
+constexpr int kHeadDimHost = 16;
+
+struct fvan_model {
+  fvan_model_config cfg{};
+  fvan::ParamOffsets po{};
+  fvan::PackOffsets pk{};
+  fvan::KvGeom kg{};
+  int64_t n_params = 0;
+  int device = 0;
+  float* params = nullptr;   // caller-owned FP32 [n_params]
+  float* grads = nullptr;    // caller-owned FP32 [n_params] (may be NULL)
+  bool synced = false;
+
+  // library-owned device workspaces
+  void* wpack = nullptr;        // packed weight copies (precision-specific)
+  void* kv = nullptr;           // sampler KV cache [max_batch][n_layers][2][S][D]
+  size_t kv_bytes = 0;
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  // train-step buffers
+  int8_t* ts_spins = nullptr;   // [max_batch, N]
+  float* ts_logq = nullptr;     // [max_batch]
+  void* ts_energy = nullptr;    // [max_batch] int32 or float
+  float* ts_w = nullptr;        // [max_batch] REINFORCE weights
+  double* ts_dbl = nullptr;     // small FP64 scratch
+  // teacher-forced forward / backward workspace (one chunk of samples)
+  struct Fwd {
+    int64_t chunk = 0, rows = 0;   // samples per chunk, rows = chunk * N
+    float* X = nullptr;            // [(n_layers+1)][rows][D] layer inputs
+    float* XM = nullptr;           // [rows][D] residual after attention
+    float* O = nullptr;            // [rows][D] attention output
+    float* LSE = nullptr;          // [rows][H] log-sum-exp of the scores (base 2)
+    void* A = nullptr;             // [rows][D] LN output (GEMM operand)
+    void* QKV = nullptr;           // [rows][3D]
+    void* HID = nullptr;           // [rows][4D] GELU output
+    float* HPRE = nullptr;         // [rows][4D] FFN pre-activation (backward)
+    float* logp = nullptr;         // [rows] log p_t(s_t)
+    // backward
+    float* dX = nullptr;           // [rows][D]
+    float* dXM = nullptr;          // [rows][D]
+    void* dQKV = nullptr;          // [rows][3D]
+    void* dH = nullptr;            // [rows][4D] gradient of the FFN pre-activation
+    void* T_a = nullptr;           // [(4D+16)][rows] feature-major copies for weight gradients
+    void* T_b = nullptr;           // [(4D+16)][rows]
+    float* part = nullptr;         // split-K partial sums
+    size_t part_floats = 0;
+    float* colpart = nullptr;      // per-tile partial column sums (LN gains, head, embeddings)
+    size_t colpart_floats = 0;
+  } fw;
+};
+
+namespace fvan {
+int model_allocate(fvan_model* m);
+void model_free(fvan_model* m);
+DecodeUnit make_decode_unit(const fvan_model* m, int32_t batch, uint64_t seed, uint64_t stream_id, int8_t* spins,
+                            float* log_q, void* kv, int tile0);
+hipError_t launch_decode_single(int d_model, int precision, const DecodeUnit& u, int tiles, hipStream_t s);
+}  // namespace fvan

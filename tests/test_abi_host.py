@@ -1,0 +1,81 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every
+symbol include/fvan.h declares, and its host logic (parameter count, mask
+derivation, argument checks) agrees with the oracle and the paper."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2606_22984_amd as fv
+from oracle import markov, network as net
+from workloads import ModelConfig, sk_instance
+from workloads.instances import lattice_edges
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    with open(os.path.join(ROOT, "include", "fvan.h")) as f:
+        hdr = f.read()
+    declared = set(re.findall(r"\b(?:int|const char\*)\s+(fvan_\w+)\s*\(", hdr))
+    assert declared == set(fv.EXPORTS)
+    lib = fv.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_num_params_matches_paper_counts():
+    here = os.path.join(ROOT, "tests", "golden", "param_counts.txt")
+    rows = [l.split("|")[0].split() for l in open(here) if l.strip() and not l.startswith("#")]
+    for S, V, dt, dp, nl, want in (map(int, r) for r in rows):
+        c = fv.ModelConfigC(n_spins=S, d_model=dt + dp, d_token=dt, n_layers=nl, n_heads=1, vocab=V,
+                            window=0, prefix=0, max_batch=1, precision=0)
+        out = C.c_int64()
+        assert fv.lib().fvan_num_params(C.byref(c), C.byref(out)) == 0
+        assert out.value == want
+
+
+def test_num_params_matches_oracle_layout():
+    for cfg in (ModelConfig(16, 32, 2, 2), ModelConfig(1000, 128, 8, 8), ModelConfig(256, 64, 4, 4)):
+        assert fv.num_params(cfg) == net.count(cfg)
+
+
+@pytest.mark.parametrize("L,D,pbc", [(16, 2, True), (10, 3, True), (24, 2, True), (32, 2, True),
+                                     (6, 2, False), (4, 3, False), (5, 2, True)])
+def test_mask_derivation_matches_oracle(L, D, pbc):
+    ei, ej = lattice_edges(L, D, pbc)
+    assert fv.derive_mask(L ** D, ei, ej) == markov.derive_mask(L ** D, ei, ej)
+
+
+def test_mask_derivation_sk_and_errors():
+    sk = sk_instance(20, 1)
+    assert fv.derive_mask(20, sk.edges_i, sk.edges_j) == (19, 0)
+    with pytest.raises(fv.FvanError) as e:
+        fv.derive_mask(4, [0, 1], [1, 7])
+    assert e.value.code == -1
+
+
+def test_invalid_configs_are_rejected_on_the_host():
+    base = dict(n_spins=16, d_model=32, d_token=2, n_layers=2, n_heads=2, vocab=2, window=15, prefix=0,
+                max_batch=8, precision=0)
+    bad = [dict(d_model=48), dict(n_heads=4), dict(vocab=16), dict(window=-1), dict(prefix=17),
+           dict(max_batch=0), dict(precision=7)]
+    for b in bad:
+        c = fv.ModelConfigC(**{**base, **b})
+        h = C.c_void_p()
+        rc = fv.lib().fvan_create_model(C.byref(c), C.byref(h))
+        assert rc in (-1, -5), b
+        assert not h.value
+        assert fv.lib().fvan_last_error()
+
+
+def test_null_arguments_are_rejected():
+    lib = fv.lib()
+    assert lib.fvan_sample(None, 1, 0, 0, None, None, None) == -1
+    assert lib.fvan_energy(None, 1, None, None, None) == -1
+    assert lib.fvan_free_energy(4, 4, 1.0, 0, None, None, None, None) == -1
+    assert lib.fvan_free_energy(4, 4, -1.0, 0, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), None) == -1
+    assert lib.fvan_reinforce_weights(0, 1.0, 0, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), None) == -1
+    assert lib.fvan_destroy_model(None) == -1

@@ -1,0 +1,193 @@
+"""Parity of the HIP sampler, energies and estimator against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2606_22984_amd as fv
+from oracle import estimator, network as net, physics, sampler
+from tests.gpu_util import BF16, DECISION_TOL, FP32, SITE_TOL, lattice_cfg, make_model, say, to_np
+from workloads import ModelConfig, ea_instance, init_params, sk_instance
+from workloads.instances import random_spins
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_samples(theta, cfg, spins, lq, seed, stream, prec, rows=None, b0=0):
+    spins = to_np(spins)
+    lq = to_np(lq).astype(np.float64)
+    assert set(np.unique(spins)).issubset({-1, 1})
+    assert np.all(np.isfinite(lq))
+    idx = np.arange(spins.shape[0]) if rows is None else np.asarray(rows)
+    sub = spins[idx]
+    bad = 0
+    exempt_fine = 0
+    for i, b in enumerate(idx):
+        nb, ex, _ = sampler.decision_check(theta, cfg, sub[i:i + 1], seed, stream, DECISION_TOL[prec], b0=b0 + b)
+        bad += nb
+        nb2, ex2, _ = sampler.decision_check(theta, cfg, sub[i:i + 1], seed, stream, 1e-5, b0=b0 + b)
+        exempt_fine += ex2
+    say(f"decision mismatches outside tol: {bad}; sites with |u-p|<1e-5: {exempt_fine}")
+    assert bad == 0
+    ref = net.log_q(net.as_theta(theta), cfg, sub).numpy()
+    per_site = np.abs(lq[idx] - ref) / cfg.n_spins
+    say(f"max per-site |dlog q| {per_site.max():.3e}")
+    assert per_site.max() <= SITE_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+@pytest.mark.parametrize("batch", [1024, 1000, 1])
+def test_sample_sk16(prec, batch):
+    cfg = ModelConfig(16, 32, 2, 2).full_causal()
+    say("sk16", prec, batch)
+    m, theta = make_model(cfg, batch, prec, seed=3)
+    spins, lq = m.sample(batch, seed=77, stream_id=5)
+    torch.cuda.synchronize()
+    _check_samples(theta, cfg, spins, lq, 77, 5, prec)
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_sample_sharp_conditionals(prec):
+    """Head scaled x10: conditionals near 0/1 stress the decision and log-softmax tails."""
+    cfg = ModelConfig(24, 32, 2, 2).with_mask(5, 3)
+    say("sharp", prec)
+    m, theta = make_model(cfg, 48, prec, seed=9, style="sharp")
+    spins, lq = m.sample(48, seed=1, stream_id=2)
+    torch.cuda.synchronize()
+    _check_samples(theta, cfg, spins, lq, 1, 2, prec)
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_sample_ea2d_L16(prec):
+    cfg = lattice_cfg(16, 2, 64, 4, 4)
+    assert (cfg.window, cfg.prefix) == (16, 17)
+    say("ea2d_L16", prec)
+    m, theta = make_model(cfg, 80, prec, seed=11)
+    spins, lq = m.sample(70, seed=123, stream_id=9)
+    torch.cuda.synchronize()
+    _check_samples(theta, cfg, spins, lq, 123, 9, prec)
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_sample_ea3d_L10_shape(prec):
+    cfg = lattice_cfg(10, 3, 128, 8, 8)
+    assert (cfg.window, cfg.prefix) == (100, 101)
+    say("ea3d_L10", prec)
+    m, theta = make_model(cfg, 40, prec, seed=21, style="default")
+    spins, lq = m.sample(40, seed=5, stream_id=1)
+    torch.cuda.synchronize()
+    _check_samples(theta, cfg, spins, lq, 5, 1, prec, rows=[0, 17, 39])
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_sample_sk512_shape(prec):
+    cfg = ModelConfig(512, 128, 6, 8).full_causal()
+    say("sk512", prec)
+    m, theta = make_model(cfg, 20, prec, seed=31, style="default")
+    spins, lq = m.sample(20, seed=8, stream_id=4)
+    torch.cuda.synchronize()
+    _check_samples(theta, cfg, spins, lq, 8, 4, prec, rows=[0, 19])
+
+
+def test_sample_full_batch_ea3d_bf16():
+    """Full 3D workload batch (16384 samples, the benchmark's launch), sampled rows checked."""
+    cfg = lattice_cfg(10, 3, 128, 8, 8)
+    say("ea3d full batch bf16")
+    m, theta = make_model(cfg, 16384, BF16, seed=21, style="default")
+    spins, lq = m.sample(16384, seed=2, stream_id=7)
+    torch.cuda.synchronize()
+    _check_samples(theta, cfg, spins, lq, 2, 7, BF16, rows=[0, 8191, 16383])
+
+
+def test_sampling_is_deterministic_and_seeded():
+    cfg = lattice_cfg(6, 2, 32, 2, 2)
+    m, theta = make_model(cfg, 64, FP32)
+    a, la = m.sample(64, 4, 4)
+    b, lb = m.sample(64, 4, 4)
+    c, lc = m.sample(64, 5, 4)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(la, lb)
+    assert not torch.equal(a, c)
+
+
+def test_sample_rejects_bad_batch():
+    cfg = ModelConfig(16, 32, 2, 2).full_causal()
+    m, _ = make_model(cfg, 8, FP32)
+    with pytest.raises(fv.FvanError):
+        m.sample(9, 0, 0)
+
+
+# ---------------------------------------------------------------- energies
+
+@pytest.mark.parametrize("L,D,batch", [(16, 2, 4096), (32, 2, 333), (10, 3, 1), (3, 2, 5)])
+def test_energy_pm1_bit_exact(L, D, batch):
+    inst = ea_instance(L, D, 1000 + L, "pm1")
+    say("energy pm1", L, D, batch)
+    spins_np = random_spins(batch, inst.n, 3)
+    spins = torch.as_tensor(spins_np, device="cuda")
+    c = fv.couplings(inst)
+    E = to_np(fv.energy(c, spins)).astype(np.int64)
+    ref = physics.energy_edges_int(spins_np, inst.edges_i, inst.edges_j, inst.J)
+    assert np.array_equal(E, ref)
+    Em = to_np(fv.energy(c, -spins)).astype(np.int64)
+    assert np.array_equal(Em, E)
+
+
+@pytest.mark.parametrize("batch", [16384, 7])
+def test_energy_gaussian_3d(batch):
+    inst = ea_instance(10, 3, 4000, "gauss")
+    spins_np = random_spins(batch, inst.n, 4)
+    c = fv.couplings(inst)
+    E = to_np(fv.energy(c, torch.as_tensor(spins_np, device="cuda"))).astype(np.float64)
+    ref = physics.energy_edges(spins_np, inst.edges_i, inst.edges_j, inst.J.astype(np.float32).astype(np.float64))
+    assert np.max(np.abs(E - ref)) / inst.n <= 1e-5
+
+
+@pytest.mark.parametrize("n,batch", [(512, 8192), (512, 17), (16, 1024), (100, 1)])
+def test_energy_dense_sk(n, batch):
+    inst = sk_instance(n, 3000 + n)
+    spins_np = random_spins(batch, n, 5)
+    c = fv.couplings(inst)
+    E = to_np(fv.energy(c, torch.as_tensor(spins_np, device="cuda"))).astype(np.float64)
+    ref = physics.energy_dense(spins_np, inst.dense.astype(np.float32).astype(np.float64))
+    assert np.max(np.abs(E - ref)) / n <= 1e-5
+
+
+# ---------------------------------------------------------------- estimator
+
+@pytest.mark.parametrize("is_int,batch", [(True, 4096), (False, 16384), (False, 2), (True, 1)])
+def test_free_energy_and_weights(is_int, batch):
+    rng = np.random.default_rng(batch)
+    n, beta = 256, 0.7
+    E = rng.integers(-500, 500, batch).astype(np.int32) if is_int else rng.normal(-300, 20, batch).astype(np.float32)
+    lq = rng.normal(-150, 5, batch).astype(np.float32)
+    Et = torch.as_tensor(E, device="cuda")
+    lt = torch.as_tensor(lq, device="cuda")
+    stats = to_np(fv.free_energy(Et, lt, beta, n))
+    mean, var = estimator.free_energy_stats(E.astype(np.float64), lq.astype(np.float64), beta, n)
+    assert abs(stats[0] - mean) <= 1e-12 * abs(mean)
+    assert abs(stats[1] - var) <= 1e-9 * max(var, 1e-30) + 1e-300
+    w = to_np(fv.reinforce_weights(Et, lt, beta)).astype(np.float64)
+    wref = estimator.reinforce_weights(E.astype(np.float64), lq.astype(np.float64), beta)
+    assert np.max(np.abs(w - wref)) <= 1e-6 * np.max(np.abs(wref)) + 1e-30
+    s1 = to_np(fv.free_energy(Et, lt, beta, n))
+    assert np.array_equal(s1, stats)           # fixed-order reduction: bitwise reproducible
+
+
+def test_free_energy_end_to_end_ea2d():
+    """F_q/N from GPU samples, GPU energies and GPU log q vs the oracle re-evaluating E and
+    ln q in FP64 on the same samples: |dF_q/N| <= 1e-4."""
+    inst = ea_instance(16, 2, 2000, "pm1")
+    cfg = lattice_cfg(16, 2, 64, 4, 4)
+    for prec in (FP32, BF16):
+        m, theta = make_model(cfg, 64, prec, seed=2, style="default")
+        spins, lq = m.sample(64, 3, 1)
+        c = fv.couplings(inst)
+        E = fv.energy(c, spins)
+        stats = to_np(fv.free_energy(E, lq, 1.0, cfg.n_spins))
+        sp = to_np(spins)
+        E_ref = physics.energy_edges_int(sp, inst.edges_i, inst.edges_j, inst.J)
+        assert np.array_equal(to_np(E).astype(np.int64), E_ref)
+        lq_ref = net.log_q(net.as_theta(theta), cfg, sp).numpy()
+        mean_ref, _ = estimator.free_energy_stats(E_ref, lq_ref, 1.0, cfg.n_spins)
+        say(f"prec {prec}: dF/N = {abs(stats[0] - mean_ref):.3e}")
+        assert abs(stats[0] - mean_ref) <= 1e-4
