@@ -64,7 +64,16 @@ typedef enum {
   FVAN_EUNSUPPORTED = -5   /* valid request this build does not implement */
 } fvan_status;
 
-typedef enum { FVAN_FP32 = 0, FVAN_BF16 = 1 } fvan_precision;
+/* Arithmetic of a model's kernels.  Every mode accumulates in FP32, keeps the
+ * residual stream, LayerNorm statistics, logits, log-softmax and log q in FP32,
+ * and leaves the batch reductions (F_q, variance, baseline) to FP64.
+ *   FVAN_FP32        FP32 MFMA GEMMs, FP32 K/V cache: the plain path.
+ *   FVAN_BF16        BF16 MFMA GEMMs (operands rounded to BF16), BF16 K/V cache.
+ *   FVAN_BF16_SPLIT  BF16 MFMA GEMMs on split operands (x = hi + lo, both BF16;
+ *                    three MFMAs per step: FP32-level GEMM accuracy), FP16 K/V
+ *                    cache and attention operands (the paper runs attention in
+ *                    FP16, SI Sec. II A).  Same K/V bytes as FVAN_BF16. */
+typedef enum { FVAN_FP32 = 0, FVAN_BF16 = 1, FVAN_BF16_SPLIT = 2 } fvan_precision;
 
 typedef enum {
   FVAN_BONDS_PM1 = 0,      /* ELL, int8 J in {-1, 0, +1}; energy int32, exact */
@@ -74,7 +83,7 @@ typedef enum {
 
 typedef struct {
   int32_t n_spins;     /* N: sequence length (one site per position) */
-  int32_t d_model;     /* d = d_token + d_pos; 32, 64, 128 or 256 */
+  int32_t d_model;     /* d = d_token + d_pos; 32, 64 or 128 */
   int32_t d_token;     /* token-embedding width (2 for single spins) */
   int32_t n_layers;
   int32_t n_heads;     /* d_model / n_heads must be 16 */

@@ -17,7 +17,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfvan.so")
 
-FVAN_FP32, FVAN_BF16 = 0, 1
+FVAN_FP32, FVAN_BF16, FVAN_BF16_SPLIT = 0, 1, 2
+PRECISION_NAMES = {0: "fp32", 1: "bf16", 2: "bf16split"}
 BONDS_PM1, BONDS_F32, BONDS_DENSE = 0, 1, 2
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "EUNSUPPORTED"}
 

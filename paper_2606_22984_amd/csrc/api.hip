@@ -43,7 +43,7 @@ ParamOffsets param_offsets(const fvan_model_config& c) {
 
 PackOffsets pack_offsets(const fvan_model_config& c) {
   PackOffsets p;
-  const size_t d = c.d_model, e = elem_bytes(c.precision);
+  const size_t d = c.d_model, e = w_elem_bytes(c.precision);
   p.qkv = 0;
   p.ffn1 = p.qkv + 3 * d * d * e;
   p.ffn2 = p.ffn1 + 4 * d * d * e;
@@ -67,7 +67,8 @@ static int check_config(const fvan_model_config* c) {
   if (c->n_layers < 0 || c->n_layers > 64) return fail(FVAN_EINVAL, "n_layers out of range");
   if (c->window < 0 || c->prefix < 0 || c->prefix > c->n_spins) return fail(FVAN_EINVAL, "mask out of range");
   if (c->max_batch < 1) return fail(FVAN_EINVAL, "max_batch must be >= 1");
-  if (c->precision != FVAN_FP32 && c->precision != FVAN_BF16) return fail(FVAN_EINVAL, "unknown precision");
+  if (c->precision != FVAN_FP32 && c->precision != FVAN_BF16 && c->precision != FVAN_BF16_SPLIT)
+    return fail(FVAN_EINVAL, "unknown precision");
   return FVAN_OK;
 }
 

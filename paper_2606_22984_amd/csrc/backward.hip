@@ -1,0 +1,593 @@
+// Hand-written backward pass of ln q (Alg. 1) for the REINFORCE gradient
+// (Eqs. 16-19): grads += sum_b w_b d ln q_b / d theta.
+//
+// Per chunk of samples the forward pass is run once to save every layer's
+// input; then, layer by layer from the top, the layer's forward is recomputed
+// (attention included: scores are rebuilt from Q, K and the saved
+// log-sum-exp, never stored) and differentiated:
+//   FFN:   dW2 = dy^T g, dg = dy W2, dh = dg * GELU'(h), dW1 = dh^T a2, da2 = dh W1, LN2'
+//   attn:  dQ per query tile, dK/dV per key tile (both deterministic, no atomics)
+//   QKV:   dWqkv = dqkv^T a1, da1 = dqkv Wqkv, LN1'
+// Weight gradients are split-K MFMA GEMMs over the rows, with operands stored
+// feature-major and a row of ones appended to the right operand so the bias
+// gradient falls out as one more output column; partial sums are reduced in a
+// fixed order and added to the caller's gradient vector.
+#include <algorithm>
+
+#include "device_common.h"
+#include "fvan_model.h"
+#include "passes.h"
+#include "row_kernels.h"
+
+namespace fvan {
+
+// Both operands as stored activations (not packed weights).
+template <int MODE> struct FragAB;
+template <> struct FragAB<0> {
+  static __device__ __forceinline__ floatx4 step(const float* a, const float* b, floatx4 acc) {
+    return Frag<0>::step(a, reinterpret_cast<const uint4*>(b), nullptr, acc);
+  }
+};
+template <> struct FragAB<1> {
+  static __device__ __forceinline__ floatx4 step(const __bf16* a, const __bf16* b, floatx4 acc) {
+    return mfma_bf16(*reinterpret_cast<const uint4*>(a), *reinterpret_cast<const uint4*>(b), acc);
+  }
+};
+template <> struct FragAB<2> {
+  static __device__ __forceinline__ floatx4 step(const float* a, const float* b, floatx4 acc) {
+    float x[8], y[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { x[i] = a[i]; y[i] = b[i]; }
+    uint4 ah, al, bh, bl;
+    split8(x, ah, al);
+    split8(y, bh, bl);
+    acc = mfma_bf16(al, bh, acc);
+    acc = mfma_bf16(ah, bl, acc);
+    return mfma_bf16(ah, bh, acc);
+  }
+};
+
+// ---------------------------------------------------------------- head
+// One workgroup per sample.  dz = w_b (onehot(s) - softmax(z)); dX = W_h^T dz;
+// per-sample partial sums of dW_h (2 x D) and db_h (2) into part[b].
+template <int D>
+__global__ __launch_bounds__(256) void head_bwd_kernel(const float* __restrict__ X, const float* __restrict__ theta,
+                                                       int64_t head_w, int64_t head_b, const int8_t* __restrict__ spins,
+                                                       const float* __restrict__ w, int N, float* __restrict__ dX,
+                                                       float* __restrict__ part) {
+  __shared__ float red[16][2 * D + 2];
+  const int b = blockIdx.x;
+  const int grp = threadIdx.x >> 4, part_ = threadIdx.x & 15;
+  const float* w0 = theta + head_w;
+  const float* w1 = w0 + D;
+  const float b0v = theta[head_b], b1v = theta[head_b + 1];
+  const float wb = w[b];
+  float gw0[D / 16], gw1[D / 16], gb0 = 0.f, gb1 = 0.f;
+#pragma unroll
+  for (int i = 0; i < D / 16; ++i) { gw0[i] = 0.f; gw1[i] = 0.f; }
+  for (int t = grp; t < N; t += 16) {
+    const int64_t r = (int64_t)b * N + t;
+    const float* x = X + r * D;
+    float xv[D / 16];
+    float z0 = 0.f, z1 = 0.f;
+#pragma unroll
+    for (int i = 0; i < D / 16; ++i) {
+      const int k = part_ + 16 * i;
+      xv[i] = x[k];
+      z0 += xv[i] * w0[k];
+      z1 += xv[i] * w1[k];
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) { z0 += __shfl_xor(z0, o, 16); z1 += __shfl_xor(z1, o, 16); }
+    const float d = (z1 + b1v) - (z0 + b0v);
+    const float e = expf(-fabsf(d));
+    const float p1 = d >= 0.f ? 1.0f / (1.0f + e) : e / (1.0f + e);   // softmax(z)[1]
+    const int s = spins[r] > 0;
+    const float dz1 = wb * ((float)s - p1);
+    const float dz0 = -dz1;
+#pragma unroll
+    for (int i = 0; i < D / 16; ++i) {
+      const int k = part_ + 16 * i;
+      dX[r * D + k] = dz0 * w0[k] + dz1 * w1[k];
+      gw0[i] += dz0 * xv[i];
+      gw1[i] += dz1 * xv[i];
+    }
+    gb0 += dz0;
+    gb1 += dz1;
+  }
+#pragma unroll
+  for (int i = 0; i < D / 16; ++i) {
+    red[grp][part_ + 16 * i] = gw0[i];
+    red[grp][D + part_ + 16 * i] = gw1[i];
+  }
+  if (part_ == 0) { red[grp][2 * D] = gb0; red[grp][2 * D + 1] = gb1; }
+  __syncthreads();
+  for (int k = threadIdx.x; k < 2 * D + 2; k += 256) {
+    float s = 0.f;
+    for (int g = 0; g < 16; ++g) s += red[g][k];
+    part[(size_t)b * (2 * D + 2) + k] = s;
+  }
+}
+
+// out[k] += sum_{i < n} part[i * width + k]  (fixed order); out may be strided in two pieces
+__global__ void colsum_add_kernel(const float* __restrict__ part, int n, int width, float* __restrict__ out) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < width; k += gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int i = 0; i < n; ++i) s += part[(size_t)i * width + k];
+    out[k] += s;
+  }
+}
+
+// ---------------------------------------------------------------- transpose + cast
+// dY (float, [rows x D]) -> Yrm (ActT, row-major) and YT (ActT, [D x ldT]).
+template <int D, typename AT>
+__global__ __launch_bounds__(256) void transpose_cast_kernel(const float* __restrict__ Y, int64_t rows,
+                                                             AT* __restrict__ Yrm, AT* __restrict__ YT, int64_t ldT) {
+  __shared__ float tile[64][D + 1];
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  for (int i = threadIdx.x; i < 64 * D; i += 256) {
+    const int rr = i / D, k = i % D;
+    const int64_t r = r0 + rr;
+    const float v = r < rows ? Y[r * D + k] : 0.f;
+    tile[rr][k] = v;
+    if (r < rows) Yrm[r * D + k] = from_f<AT>(v);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 64 * D; i += 256) {
+    const int k = i >> 6, rr = i & 63;
+    if (r0 + rr < rows) YT[(int64_t)k * ldT + r0 + rr] = from_f<AT>(tile[rr][k]);
+  }
+}
+
+// ---------------------------------------------------------------- weight-gradient GEMM
+// part[s][m][n] = sum_{k in split s, k < K} A[m][k] B[n][k]; A [M x lda], B [NB x ldb]
+// feature-major, K = rows of the chunk.  64 x 64 output tile per workgroup,
+// one wave per 16 rows of the tile.
+template <int MODE>
+__global__ __launch_bounds__(256) void wgrad_kernel(const typename Mode<MODE>::ActT* __restrict__ A, int64_t lda,
+                                                    const typename Mode<MODE>::ActT* __restrict__ B, int64_t ldb,
+                                                    int M, int NB, int64_t K, int64_t kper, float* __restrict__ part) {
+  typedef typename Mode<MODE>::ActT AT;
+  constexpr int KC = Mode<MODE>::KC;
+  constexpr int LK = KC / 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * 64 + wave * 16;
+  const int n0 = blockIdx.x * 64;
+  const int s = blockIdx.z;
+  if (m0 >= M) return;
+  const int64_t kb = (int64_t)s * kper;
+  const int64_t ke = std::min<int64_t>(K, kb + kper);
+  floatx4 acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const AT* arow = A + (int64_t)(m0 + (lane & 15)) * lda + (lane >> 4) * LK;
+  const int nsub = std::min(4, (NB - n0) / 16);
+  int64_t k = kb;
+  for (; k + KC <= ke; k += KC) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (j < nsub) {
+        const AT* brow = B + (int64_t)(n0 + 16 * j + (lane & 15)) * ldb + (lane >> 4) * LK;
+        acc[j] = FragAB<MODE>::step(arow + k, brow + k, acc[j]);
+      }
+    }
+  }
+  if (k < ke) {   // ragged tail of the row range: zero-fill past ke
+    alignas(16) AT av[LK], bv[LK];
+    const int64_t k0 = k + (lane >> 4) * LK;
+#pragma unroll
+    for (int i = 0; i < LK; ++i) av[i] = k0 + i < ke ? arow[k + i] : from_f<AT>(0.f);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (j < nsub) {
+        const AT* brow = B + (int64_t)(n0 + 16 * j + (lane & 15)) * ldb + (lane >> 4) * LK;
+#pragma unroll
+        for (int i = 0; i < LK; ++i) bv[i] = k0 + i < ke ? brow[k + i] : from_f<AT>(0.f);
+        acc[j] = FragAB<MODE>::step(av, bv, acc[j]);
+      }
+    }
+  }
+  float* out = part + (size_t)s * M * NB;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (j < nsub) {
+      const int n = n0 + 16 * j + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) out[(size_t)(m0 + 4 * (lane >> 4) + i) * NB + n] = acc[j][i];
+    }
+  }
+}
+
+// grads: W[m][n] += sum_s part[s][m][n] for n < Nw; bias[m] += sum_s part[s][m][Nw].
+__global__ void wgrad_reduce_kernel(const float* __restrict__ part, int S, int M, int NB, int Nw,
+                                    float* __restrict__ gW, float* __restrict__ gb) {
+  const int total = M * (Nw + 1);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int m = i / (Nw + 1), n = i % (Nw + 1);
+    float acc = 0.f;
+    for (int s = 0; s < S; ++s) acc += part[((size_t)s * M + m) * NB + n];
+    if (n < Nw) gW[(size_t)m * Nw + n] += acc;
+    else gb[m] += acc;
+  }
+}
+
+template <int MODE>
+static hipError_t wgrad(fvan_model* m, const void* A, int M, const void* B, int Nw, int64_t K, float* gW, float* gb,
+                        hipStream_t s) {
+  typedef typename Mode<MODE>::ActT AT;
+  auto& f = m->fw;
+  const int NB = Nw + 16;
+  const int tiles = ((NB + 63) / 64) * ((M + 63) / 64);
+  int S = std::max(1, std::min<int>(256, 2048 / tiles));
+  S = (int)std::min<int64_t>(S, std::max<int64_t>(1, K / 256));
+  while ((size_t)S * M * NB > f.part_floats) --S;
+  const int KC = Mode<MODE>::KC;
+  int64_t kper = (K + S - 1) / S;
+  kper = (kper + KC - 1) / KC * KC;
+  hipLaunchKernelGGL((wgrad_kernel<MODE>), dim3((NB + 63) / 64, (M + 63) / 64, S), dim3(256), 0, s,
+                     (const AT*)A, f.ldT, (const AT*)B, f.ldT, M, NB, K, kper, f.part);
+  const int total = M * (Nw + 1);
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(std::min(1024, (total + 255) / 256)), dim3(256), 0, s,
+                     (const float*)f.part, S, M, NB, Nw, gW, gb);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- LayerNorm backward
+// out[r] = resid[r] + LN'(da[r]) for y = LN(x) with gain g; per 64-row tile
+// partial sums of dg (= sum da * xhat) and db (= sum da) into part[tile][2D].
+template <int D>
+__global__ __launch_bounds__(256) void ln_bwd_kernel(const float* __restrict__ da, const float* __restrict__ X,
+                                                     const float* __restrict__ g, const float* __restrict__ resid,
+                                                     int64_t rows, float* __restrict__ out, float* __restrict__ part) {
+  constexpr int PER = D / 16;
+  __shared__ float red[16][2 * D];
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int grp = threadIdx.x >> 4, p = threadIdx.x & 15;
+  float pg[PER], pb[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) { pg[i] = 0.f; pb[i] = 0.f; }
+  for (int rr = grp; rr < 64; rr += 16) {
+    const int64_t r = r0 + rr;
+    if (r >= rows) break;
+    float x[PER], dy[PER];
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) { x[i] = X[r * D + p + 16 * i]; s += x[i]; }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+    const float mean = s * (1.0f / D);
+    float q = 0.f;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) { x[i] -= mean; q += x[i] * x[i]; }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) q += __shfl_xor(q, o, 16);
+    const float rstd = rsqrtf(q * (1.0f / D) + kLnEps);
+    float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int k = p + 16 * i;
+      const float a = da[r * D + k];
+      const float xh = x[i] * rstd;
+      x[i] = xh;
+      pg[i] += a * xh;
+      pb[i] += a;
+      dy[i] = a * g[k];
+      s1 += dy[i];
+      s2 += dy[i] * xh;
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) { s1 += __shfl_xor(s1, o, 16); s2 += __shfl_xor(s2, o, 16); }
+    s1 *= 1.0f / D;
+    s2 *= 1.0f / D;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int k = p + 16 * i;
+      out[r * D + k] = resid[r * D + k] + rstd * (dy[i] - s1 - x[i] * s2);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) { red[grp][p + 16 * i] = pg[i]; red[grp][D + p + 16 * i] = pb[i]; }
+  __syncthreads();
+  for (int k = threadIdx.x; k < 2 * D; k += 256) {
+    float s = 0.f;
+    for (int gI = 0; gI < 16; ++gI) s += red[gI][k];
+    part[(size_t)blockIdx.x * 2 * D + k] = s;
+  }
+}
+
+// ---------------------------------------------------------------- attention backward
+// dQ: one workgroup per (sample, 64 queries, 4 heads); also writes
+// DELTA[r][h] = dO_r . O_r used by the dK/dV kernel.
+template <typename KT, typename AT>
+__global__ __launch_bounds__(256) void attn_bwd_dq_kernel(const KT* __restrict__ QKV, const float* __restrict__ O,
+                                                          const float* __restrict__ dO, const float* __restrict__ LSE,
+                                                          float* __restrict__ DELTA, AT* __restrict__ dQKV,
+                                                          AT* __restrict__ T, int64_t ldT, int N, int D, int H, int W,
+                                                          int P) {
+  __shared__ float Ks[64][4][17];
+  __shared__ float Vs[64][4][17];
+  const int qi = threadIdx.x & 63, hl = threadIdx.x >> 6;
+  const int t0 = blockIdx.x * 64, h0 = blockIdx.y * 4, b = blockIdx.z;
+  const int h = h0 + hl, t = t0 + qi;
+  const bool active = t < N && h < H;
+  const int t1 = std::min(t0 + 64, N);
+  const int64_t rowbase = (int64_t)b * N;
+  const int64_t r = rowbase + t;
+  constexpr float kScaleLog2 = 0.25f * 1.4426950408889634f;
+  float q[16], go[16], dq[16];
+  float lse = 0.f, delta = 0.f;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) { q[e] = 0.f; go[e] = 0.f; dq[e] = 0.f; }
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      q[e] = to_f(QKV[r * 3 * D + h * 16 + e]) * kScaleLog2;
+      go[e] = dO[r * D + h * 16 + e];
+      delta += go[e] * O[r * D + h * 16 + e];
+    }
+    lse = LSE[r * H + h];
+    DELTA[r * H + h] = delta;
+  }
+  const int pend = std::min(P, t1);
+  const int bstart = std::max(P, t0 - W);
+  for (int range = 0; range < 2; ++range) {
+    const int ks = range == 0 ? 0 : bstart;
+    const int ke = range == 0 ? pend : t1;
+    for (int j0 = ks; j0 < ke; j0 += 64) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < 64 * 4 * 16; i += 256) {
+        const int jj = i >> 6, hh = (i >> 4) & 3, e = i & 15;
+        const int j = j0 + jj;
+        float kv = 0.f, vv = 0.f;
+        if (j < ke && h0 + hh < H) {
+          const KT* kp = QKV + (rowbase + j) * 3 * D + D + (h0 + hh) * 16 + e;
+          kv = to_f(kp[0]);
+          vv = to_f(kp[D]);
+        }
+        Ks[jj][hh][e] = kv;
+        Vs[jj][hh][e] = vv;
+      }
+      __syncthreads();
+      if (active) {
+        const int jn = std::min(64, ke - j0);
+        for (int jj = 0; jj < jn; ++jj) {
+          const int j = j0 + jj;
+          if (j > t || (t - j > W && j >= P)) continue;
+          float sc = 0.f, dp = 0.f;
+#pragma unroll
+          for (int e = 0; e < 16; ++e) { sc += q[e] * Ks[jj][hl][e]; dp += go[e] * Vs[jj][hl][e]; }
+          const float pr = __builtin_amdgcn_exp2f(sc - lse);
+          const float ds = pr * (dp - delta);
+#pragma unroll
+          for (int e = 0; e < 16; ++e) dq[e] += ds * Ks[jj][hl][e];
+        }
+      }
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const AT v = from_f<AT>(dq[e] * 0.25f);
+      dQKV[r * 3 * D + h * 16 + e] = v;
+      T[(int64_t)(h * 16 + e) * ldT + r] = v;
+    }
+  }
+}
+
+// dK, dV: one workgroup per (sample, 64 keys, 4 heads); loops over the query
+// blocks that can see the keys: [j0, j1 + W) for band keys, [j0, N) when the
+// tile holds prefix keys.
+template <typename KT, typename AT>
+__global__ __launch_bounds__(256) void attn_bwd_dkv_kernel(const KT* __restrict__ QKV, const float* __restrict__ dO,
+                                                           const float* __restrict__ LSE,
+                                                           const float* __restrict__ DELTA, AT* __restrict__ dQKV,
+                                                           AT* __restrict__ T, int64_t ldT, int N, int D, int H, int W,
+                                                           int P) {
+  __shared__ float Qs[64][4][17];
+  __shared__ float Gs[64][4][17];
+  __shared__ float Ls[64][4];
+  __shared__ float Ds[64][4];
+  const int ji = threadIdx.x & 63, hl = threadIdx.x >> 6;
+  const int j0 = blockIdx.x * 64, h0 = blockIdx.y * 4, b = blockIdx.z;
+  const int h = h0 + hl, j = j0 + ji;
+  const bool active = j < N && h < H;
+  const int j1 = std::min(j0 + 64, N);
+  const int64_t rowbase = (int64_t)b * N;
+  constexpr float kScaleLog2 = 0.25f * 1.4426950408889634f;
+  float kk[16], vv[16], dk[16], dv[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) { kk[e] = 0.f; vv[e] = 0.f; dk[e] = 0.f; dv[e] = 0.f; }
+  if (active) {
+    const KT* kp = QKV + (rowbase + j) * 3 * D + D + h * 16;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) { kk[e] = to_f(kp[e]); vv[e] = to_f(kp[D + e]); }
+  }
+  const int qend = j0 < P ? N : std::min(N, j1 + W);
+  for (int i0 = j0; i0 < qend; i0 += 64) {
+    __syncthreads();
+    for (int x = threadIdx.x; x < 64 * 4 * 16; x += 256) {
+      const int ii = x >> 6, hh = (x >> 4) & 3, e = x & 15;
+      const int i = i0 + ii;
+      float qv = 0.f, gv = 0.f;
+      if (i < qend && h0 + hh < H) {
+        qv = to_f(QKV[(rowbase + i) * 3 * D + (h0 + hh) * 16 + e]);
+        gv = dO[(rowbase + i) * D + (h0 + hh) * 16 + e];
+      }
+      Qs[ii][hh][e] = qv;
+      Gs[ii][hh][e] = gv;
+    }
+    for (int x = threadIdx.x; x < 64 * 4; x += 256) {
+      const int ii = x >> 2, hh = x & 3;
+      const int i = i0 + ii;
+      const bool ok = i < qend && h0 + hh < H;
+      Ls[ii][hh] = ok ? LSE[(rowbase + i) * H + h0 + hh] : 0.f;
+      Ds[ii][hh] = ok ? DELTA[(rowbase + i) * H + h0 + hh] : 0.f;
+    }
+    __syncthreads();
+    if (active) {
+      const int in = std::min(64, qend - i0);
+      for (int ii = 0; ii < in; ++ii) {
+        const int i = i0 + ii;
+        if (j > i || (i - j > W && j >= P)) continue;
+        float sc = 0.f, dp = 0.f;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) { sc += Qs[ii][hl][e] * kk[e]; dp += Gs[ii][hl][e] * vv[e]; }
+        const float pr = __builtin_amdgcn_exp2f(sc * kScaleLog2 - Ls[ii][hl]);
+        const float ds = pr * (dp - Ds[ii][hl]);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          dv[e] += pr * Gs[ii][hl][e];
+          dk[e] += ds * Qs[ii][hl][e];
+        }
+      }
+    }
+  }
+  if (active) {
+    const int64_t r = rowbase + j;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const AT kvv = from_f<AT>(dk[e] * 0.25f);
+      const AT vvv = from_f<AT>(dv[e]);
+      dQKV[r * 3 * D + D + h * 16 + e] = kvv;
+      dQKV[r * 3 * D + 2 * D + h * 16 + e] = vvv;
+      T[(int64_t)(D + h * 16 + e) * ldT + r] = kvv;
+      T[(int64_t)(2 * D + h * 16 + e) * ldT + r] = vvv;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- embedding
+// dP[t][k] += sum_b dX0[b*N + t][dt + k]: one thread per (t, k), samples summed in order.
+__global__ void pos_grad_kernel(const float* __restrict__ dX, int nsamp, int N, int D, int dt,
+                                float* __restrict__ gpos) {
+  const int dp = D - dt;
+  const int64_t total = (int64_t)N * dp;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(i / dp), k = (int)(i % dp);
+    float s = 0.f;
+    for (int b = 0; b < nsamp; ++b) s += dX[((int64_t)b * N + t) * D + dt + k];
+    gpos[i] += s;
+  }
+}
+
+// dT[tok][k] += sum over rows fed token tok: one workgroup per (tok, k).
+__global__ __launch_bounds__(256) void tok_grad_kernel(const float* __restrict__ dX, const int8_t* __restrict__ spins,
+                                                       int64_t rows, int N, int D, int dt, float* __restrict__ gtok) {
+  __shared__ float red[256];
+  const int tok = blockIdx.x / dt, k = blockIdx.x % dt;
+  float s = 0.f;
+  for (int64_t r = threadIdx.x; r < rows; r += 256) {
+    const int t = (int)(r % N);
+    const int tr = t == 0 ? 0 : (spins[r - 1] + 1) >> 1;
+    if (tr == tok) s += dX[r * D + k];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gtok[tok * dt + k] += red[0];
+}
+
+// ---------------------------------------------------------------- driver
+template <int MODE, int D>
+static hipError_t backward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp, const float* w, hipStream_t s) {
+  typedef typename Mode<MODE>::ActT AT;
+  typedef typename Mode<MODE>::KvT KT;
+  const fvan_model_config& c = m->cfg;
+  auto& f = m->fw;
+  const int N = c.n_spins, H = c.n_heads, L = c.n_layers;
+  const int64_t rows = (int64_t)nsamp * N;
+  const int rgrid = (int)((rows + 63) / 64);
+  float* G = m->grads;
+  hipError_t err = forward_chunk(m, spins, nsamp, nullptr, false, s);
+  if (err != hipSuccess) return err;
+
+  // head
+  hipLaunchKernelGGL((head_bwd_kernel<D>), dim3(nsamp), dim3(256), 0, s,
+                     (const float*)(f.X + (size_t)L * f.rows * D), m->params, m->po.head_w, m->po.head_b, spins, w, N,
+                     f.dX, f.colpart);
+  hipLaunchKernelGGL(colsum_add_kernel, dim3(1), dim3(256), 0, s, (const float*)f.colpart, nsamp, 2 * D + 2,
+                     G + m->po.head_w);
+
+  for (int l = L - 1; l >= 0; --l) {
+    const float* lp = m->params + m->po.layer0 + (int64_t)l * m->po.layer_stride;
+    float* gl = G + m->po.layer0 + (int64_t)l * m->po.layer_stride;
+    const char* wl = reinterpret_cast<const char*>(m->wpack) + (size_t)l * m->pk.layer_stride;
+    const float* X = f.X + (size_t)l * f.rows * D;
+    // ---- recompute the layer's forward
+    hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(rgrid), dim3(256), 0, s, X, rows, lp + m->po.ln1_g,
+                       lp + m->po.ln1_b, (AT*)f.A, (AT*)nullptr, (int64_t)0);
+    EpiArgs e{};
+    e.bias = lp + m->po.qkv_b;
+    e.out = f.QKV;
+    if ((err = gemm_rows<MODE, D, 3 * D, EPI_STORE_KV>((const AT*)f.A, rows, wl + m->pk.qkv, e, s))) return err;
+    hipLaunchKernelGGL((attn_fwd_kernel<KT>), dim3((N + 63) / 64, (H + 3) / 4, nsamp), dim3(256), 0, s,
+                       (const KT*)f.QKV, X, f.O, f.XM, f.LSE, N, D, H, c.window, m->kg.P);
+    hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(rgrid), dim3(256), 0, s, (const float*)f.XM, rows,
+                       lp + m->po.ln2_g, lp + m->po.ln2_b, (AT*)f.A, (AT*)f.T_c, f.ldT);
+    EpiArgs e1{};
+    e1.bias = lp + m->po.ffn1_b;
+    e1.out = f.HID;
+    e1.hpre_out = f.HPRE;
+    e1.outT = f.T_b;
+    e1.ldT = f.ldT;
+    if ((err = gemm_rows<MODE, D, 4 * D, EPI_GELU>((const AT*)f.A, rows, wl + m->pk.ffn1, e1, s))) return err;
+    // ---- FFN backward
+    hipLaunchKernelGGL((transpose_cast_kernel<D, AT>), dim3(rgrid), dim3(256), 0, s, (const float*)f.dX, rows,
+                       (AT*)f.DY, (AT*)f.T_a, f.ldT);
+    if ((err = wgrad<MODE>(m, f.T_a, D, f.T_b, 4 * D, rows, gl + m->po.ffn2_w, gl + m->po.ffn2_b, s))) return err;
+    EpiArgs e2{};
+    e2.hpre_in = f.HPRE;
+    e2.out = f.dH;
+    e2.outT = f.T_a;
+    e2.ldT = f.ldT;
+    if ((err = gemm_rows<MODE, D, 4 * D, EPI_DGELU>((const AT*)f.DY, rows, wl + m->pk.ffn2T, e2, s))) return err;
+    if ((err = wgrad<MODE>(m, f.T_a, 4 * D, f.T_c, D, rows, gl + m->po.ffn1_w, gl + m->po.ffn1_b, s))) return err;
+    EpiArgs e3{};
+    e3.out = f.TMP;
+    if ((err = gemm_rows<MODE, 4 * D, D, EPI_F32>((const AT*)f.dH, rows, wl + m->pk.ffn1T, e3, s))) return err;
+    hipLaunchKernelGGL((ln_bwd_kernel<D>), dim3(rgrid), dim3(256), 0, s, (const float*)f.TMP, (const float*)f.XM,
+                       lp + m->po.ln2_g, (const float*)f.dX, rows, f.dXM, f.colpart);
+    hipLaunchKernelGGL(colsum_add_kernel, dim3((2 * D + 255) / 256), dim3(256), 0, s, (const float*)f.colpart, rgrid,
+                       2 * D, gl + m->po.ln2_g);
+    // ---- attention backward (dO = dXM: the heads' output is added to the residual directly)
+    hipLaunchKernelGGL((attn_bwd_dq_kernel<KT, AT>), dim3((N + 63) / 64, (H + 3) / 4, nsamp), dim3(256), 0, s,
+                       (const KT*)f.QKV, (const float*)f.O, (const float*)f.dXM, (const float*)f.LSE, f.DELTA,
+                       (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window, m->kg.P);
+    hipLaunchKernelGGL((attn_bwd_dkv_kernel<KT, AT>), dim3((N + 63) / 64, (H + 3) / 4, nsamp), dim3(256), 0, s,
+                       (const KT*)f.QKV, (const float*)f.dXM, (const float*)f.LSE, (const float*)f.DELTA,
+                       (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window, m->kg.P);
+    // ---- QKV backward
+    hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(rgrid), dim3(256), 0, s, X, rows, lp + m->po.ln1_g,
+                       lp + m->po.ln1_b, (AT*)nullptr, (AT*)f.T_c, f.ldT);
+    if ((err = wgrad<MODE>(m, f.T_a, 3 * D, f.T_c, D, rows, gl + m->po.qkv_w, gl + m->po.qkv_b, s))) return err;
+    EpiArgs e4{};
+    e4.out = f.TMP;
+    if ((err = gemm_rows<MODE, 3 * D, D, EPI_F32>((const AT*)f.dQKV, rows, wl + m->pk.qkvT, e4, s))) return err;
+    hipLaunchKernelGGL((ln_bwd_kernel<D>), dim3(rgrid), dim3(256), 0, s, (const float*)f.TMP, X, lp + m->po.ln1_g,
+                       (const float*)f.dXM, rows, f.dX, f.colpart);
+    hipLaunchKernelGGL(colsum_add_kernel, dim3((2 * D + 255) / 256), dim3(256), 0, s, (const float*)f.colpart, rgrid,
+                       2 * D, gl + m->po.ln1_g);
+  }
+  // embeddings
+  const int64_t npos = (int64_t)N * (D - c.d_token);
+  hipLaunchKernelGGL(pos_grad_kernel, dim3((int)std::min<int64_t>((npos + 255) / 256, 4096)), dim3(256), 0, s,
+                     (const float*)f.dX, nsamp, N, D, c.d_token, G + m->po.pos);
+  hipLaunchKernelGGL(tok_grad_kernel, dim3(c.vocab * c.d_token), dim3(256), 0, s, (const float*)f.dX, spins, rows, N,
+                     D, c.d_token, G + m->po.tok);
+  return hipGetLastError();
+}
+
+hipError_t backward_chunk(fvan_model* m, const int8_t* spins, int nsamp, const float* w, hipStream_t s) {
+  const int D = m->cfg.d_model;
+#define BWD_CASE(MODE, DD) if (m->cfg.precision == MODE && D == DD) return backward_chunk_t<MODE, DD>(m, spins, nsamp, w, s);
+  BWD_CASE(0, 32) BWD_CASE(0, 64) BWD_CASE(0, 128)
+  BWD_CASE(1, 32) BWD_CASE(1, 64) BWD_CASE(1, 128)
+  BWD_CASE(2, 32) BWD_CASE(2, 64) BWD_CASE(2, 128)
+#undef BWD_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace fvan

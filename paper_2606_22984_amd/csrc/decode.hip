@@ -23,17 +23,17 @@ constexpr int kThreads = 256;
 
 int decode_tile_samples() { return kM; }
 
-template <int D, int PREC>
+template <int D, int MODE>
 struct DecodeSmem {
-  typedef typename Prec<PREC>::T T;
-  static constexpr int PAD = 16 / (int)sizeof(T);
+  typedef typename Mode<MODE>::ActT A;
+  static constexpr int PAD = 16 / (int)sizeof(A);
   static constexpr int LDA = D + PAD;
   static constexpr int LDH = 4 * D + PAD;
   float h[kM][D];
-  T a[kM][LDA];
+  A a[kM][LDA];
   union {
     float q[kM][D];
-    T hid[kM][LDH];
+    A hid[kM][LDH];
   } u;
   int tok[kM];
   int8_t sbuf[kM][64];
@@ -48,10 +48,10 @@ __device__ __forceinline__ float reduce16(float v) {
 }
 
 // LayerNorm of the kM residual rows into the MFMA operand buffer.
-template <int D, int PREC>
-__device__ __forceinline__ void ln_rows(DecodeSmem<D, PREC>& sm, const float* __restrict__ g,
+template <int D, int MODE>
+__device__ __forceinline__ void ln_rows(DecodeSmem<D, MODE>& sm, const float* __restrict__ g,
                                         const float* __restrict__ b) {
-  typedef typename Prec<PREC>::T T;
+  typedef typename Mode<MODE>::ActT T;
   constexpr int PER = D / 16;
   const int m = threadIdx.x >> 4, part = threadIdx.x & 15;
   float x[PER];
@@ -76,28 +76,26 @@ __device__ __forceinline__ void ln_rows(DecodeSmem<D, PREC>& sm, const float* __
   }
 }
 
-// acc(16 x 16 tile nt) = A[16 x K] (LDS, row stride lda elements) . pack tile nt
-template <int PREC, int K>
-__device__ __forceinline__ floatx4 mfma_rowtile(const typename Prec<PREC>::T* A, int lda,
-                                                const uint4* __restrict__ pack, int nt, int lane) {
-  constexpr int KC = Prec<PREC>::KC;
+// acc(16 x 16 tile nt) = A[16 x K] (LDS, row stride lda elements) . pack tile nt.
+// lo_u4: distance (in 16-byte units) from a split pack's hi part to its lo part.
+template <int MODE, int K>
+__device__ __forceinline__ floatx4 mfma_rowtile(const typename Mode<MODE>::ActT* A, int lda,
+                                                const uint4* __restrict__ pack, size_t lo_u4, int nt, int lane) {
+  constexpr int KC = Mode<MODE>::KC;
   constexpr int NC = K / KC;
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-  const typename Prec<PREC>::T* arow = A + (lane & 15) * lda + (lane >> 4) * (KC / 4);
+  const typename Mode<MODE>::ActT* arow = A + (lane & 15) * lda + (lane >> 4) * (KC / 4);
   const uint4* bp = pack + (size_t)nt * NC * 64 + lane;
 #pragma unroll 4
-  for (int c = 0; c < NC; ++c) {
-    const uint4 av = *reinterpret_cast<const uint4*>(arow + c * KC);
-    const uint4 bv = bp[c * 64];
-    acc = mfma_chunk(av, bv, acc, Prec<PREC>());
-  }
+  for (int c = 0; c < NC; ++c) acc = Frag<MODE>::step(arow + c * KC, bp + c * 64, bp + c * 64 + lo_u4, acc);
   return acc;
 }
 
-template <int D, int PREC>
-__device__ void decode_tile(DecodeSmem<D, PREC>& sm, const DecodeUnit& U, int local_tile) {
-  typedef typename Prec<PREC>::T T;
-  constexpr int VEC = Prec<PREC>::VEC;
+template <int D, int MODE>
+__device__ void decode_tile(DecodeSmem<D, MODE>& sm, const DecodeUnit& U, int local_tile) {
+  typedef typename Mode<MODE>::KvT T;
+  typedef DecodeSmem<D, MODE> Sm;
+  constexpr int VEC = Chunk<T>::N;
   constexpr int LPR = D / VEC;          // lanes per K/V row
   constexpr int RPL = 64 / LPR;         // rows per wave load
   constexpr int LPH = kHeadDim / VEC;   // lanes per head
@@ -133,14 +131,14 @@ __device__ void decode_tile(DecodeSmem<D, PREC>& sm, const DecodeUnit& U, int lo
     for (int l = 0; l < nl; ++l) {
       const float* lp = theta + U.layer0 + (size_t)l * U.layer_stride;
       const char* wl = wbase + (size_t)l * U.p_layer_stride;
-      ln_rows<D, PREC>(sm, lp + U.o_ln1_g, lp + U.o_ln1_b);
+      ln_rows<D, MODE>(sm, lp + U.o_ln1_g, lp + U.o_ln1_b);
       __syncthreads();
 
       // ---- QKV projection; k_t, v_t appended to the cache ----
       {
         const uint4* pk = reinterpret_cast<const uint4*>(wl + U.p_qkv);
         for (int nt = wave; nt < 3 * D / 16; nt += 4) {
-          floatx4 acc = mfma_rowtile<PREC, D>(&sm.a[0][0], DecodeSmem<D, PREC>::LDA, pk, nt, lane);
+          floatx4 acc = mfma_rowtile<MODE, D>(&sm.a[0][0], Sm::LDA, pk, (size_t)3 * D * D / 8, nt, lane);
           const int n = nt * 16 + (lane & 15);
           const float bias = lp[U.o_qkv_b + n];
 #pragma unroll
@@ -175,7 +173,7 @@ __device__ void decode_tile(DecodeSmem<D, PREC>& sm, const DecodeUnit& U, int lo
 #pragma unroll
           for (int i = 0; i < VEC; ++i) o[i] = 0.f;
           for (int s0 = 0; s0 < nvis; s0 += RPL * UNR) {
-            Chunk<PREC> kc[UNR], vc[UNR];
+            Chunk<T> kc[UNR], vc[UNR];
             bool ok[UNR];
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
@@ -238,23 +236,24 @@ __device__ void decode_tile(DecodeSmem<D, PREC>& sm, const DecodeUnit& U, int lo
       __syncthreads();
 
       // ---- feed-forward block ----
-      ln_rows<D, PREC>(sm, lp + U.o_ln2_g, lp + U.o_ln2_b);
+      ln_rows<D, MODE>(sm, lp + U.o_ln2_g, lp + U.o_ln2_b);
       __syncthreads();
       {
         const uint4* p1 = reinterpret_cast<const uint4*>(wl + U.p_ffn1);
         for (int nt = wave; nt < 4 * D / 16; nt += 4) {
-          floatx4 acc = mfma_rowtile<PREC, D>(&sm.a[0][0], DecodeSmem<D, PREC>::LDA, p1, nt, lane);
+          floatx4 acc = mfma_rowtile<MODE, D>(&sm.a[0][0], Sm::LDA, p1, (size_t)4 * D * D / 8, nt, lane);
           const int n = nt * 16 + (lane & 15);
           const float bias = lp[U.o_ffn1_b + n];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) sm.u.hid[4 * (lane >> 4) + i][n] = from_f<T>(gelu(acc[i] + bias));
+          for (int i = 0; i < 4; ++i)
+            sm.u.hid[4 * (lane >> 4) + i][n] = from_f<typename Mode<MODE>::ActT>(gelu(acc[i] + bias));
         }
       }
       __syncthreads();
       {
         const uint4* p2 = reinterpret_cast<const uint4*>(wl + U.p_ffn2);
         for (int nt = wave; nt < D / 16; nt += 4) {
-          floatx4 acc = mfma_rowtile<PREC, 4 * D>(&sm.u.hid[0][0], DecodeSmem<D, PREC>::LDH, p2, nt, lane);
+          floatx4 acc = mfma_rowtile<MODE, 4 * D>(&sm.u.hid[0][0], Sm::LDH, p2, (size_t)4 * D * D / 8, nt, lane);
           const int n = nt * 16 + (lane & 15);
           const float bias = lp[U.o_ffn2_b + n];
 #pragma unroll
@@ -306,10 +305,10 @@ __device__ void decode_tile(DecodeSmem<D, PREC>& sm, const DecodeUnit& U, int lo
   __syncthreads();
 }
 
-template <int D, int PREC>
+template <int D, int MODE>
 __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeUnit u0, const DecodeUnit* __restrict__ table,
                                                           int n_units, int total_tiles, int* queue) {
-  __shared__ DecodeSmem<D, PREC> sm;
+  __shared__ DecodeSmem<D, MODE> sm;
   __shared__ int s_tile;
   bool first = true;
   for (;;) {
@@ -329,31 +328,38 @@ __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeUnit u0, const D
         if (table[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
       }
       const DecodeUnit U = table[lo];
-      decode_tile<D, PREC>(sm, U, tile - U.tile0);
+      decode_tile<D, MODE>(sm, U, tile - U.tile0);
     } else {
-      decode_tile<D, PREC>(sm, u0, tile);
+      decode_tile<D, MODE>(sm, u0, tile);
     }
   }
 }
 
-template <int D, int PREC>
+template <int D, int MODE>
 static hipError_t launch_d(const DecodeUnit& u0, const DecodeUnit* table, int n_units, int total_tiles, int* queue,
                            int grid, hipStream_t s) {
-  hipLaunchKernelGGL((decode_kernel<D, PREC>), dim3(grid), dim3(kThreads), 0, s, u0, table, n_units, total_tiles,
+  hipLaunchKernelGGL((decode_kernel<D, MODE>), dim3(grid), dim3(kThreads), 0, s, u0, table, n_units, total_tiles,
                      queue);
   return hipGetLastError();
 }
 
+template <int D>
+static hipError_t dispatch_mode(int precision, const DecodeUnit& u0, const DecodeUnit* table, int n_units,
+                                int total_tiles, int* queue, int grid, hipStream_t s) {
+  switch (precision) {
+    case FVAN_FP32: return launch_d<D, 0>(u0, table, n_units, total_tiles, queue, grid, s);
+    case FVAN_BF16: return launch_d<D, 1>(u0, table, n_units, total_tiles, queue, grid, s);
+    case FVAN_BF16_SPLIT: return launch_d<D, 2>(u0, table, n_units, total_tiles, queue, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 static hipError_t dispatch(int d_model, int precision, const DecodeUnit& u0, const DecodeUnit* table, int n_units,
                            int total_tiles, int* queue, int grid, hipStream_t s) {
-  const bool bf = precision == FVAN_BF16;
   switch (d_model) {
-    case 32: return bf ? launch_d<32, 1>(u0, table, n_units, total_tiles, queue, grid, s)
-                       : launch_d<32, 0>(u0, table, n_units, total_tiles, queue, grid, s);
-    case 64: return bf ? launch_d<64, 1>(u0, table, n_units, total_tiles, queue, grid, s)
-                       : launch_d<64, 0>(u0, table, n_units, total_tiles, queue, grid, s);
-    case 128: return bf ? launch_d<128, 1>(u0, table, n_units, total_tiles, queue, grid, s)
-                        : launch_d<128, 0>(u0, table, n_units, total_tiles, queue, grid, s);
+    case 32: return dispatch_mode<32>(precision, u0, table, n_units, total_tiles, queue, grid, s);
+    case 64: return dispatch_mode<64>(precision, u0, table, n_units, total_tiles, queue, grid, s);
+    case 128: return dispatch_mode<128>(precision, u0, table, n_units, total_tiles, queue, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

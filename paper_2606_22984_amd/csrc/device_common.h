@@ -13,35 +13,46 @@ constexpr int kWave = 64;
 constexpr float kLnEps = 1e-5f;
 constexpr int kHeadDim = 16;
 
-// Element type of activations, KV cache and packed weights for a precision.
-template <int PREC> struct Prec;
-template <> struct Prec<0> {            // FP32
-  typedef float T;
-  static constexpr int VEC = 4;         // elements per 16-byte lane chunk
-  static constexpr int KC = 16;         // K consumed per 16-byte fragment (4 x 16x16x4 MFMA)
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
+
+// Precision modes (fvan_precision).  KvT: K/V cache element; ActT: stored GEMM
+// A operand (activations); WT: packed weight element; KC: K consumed per
+// 16x16 MFMA fragment step; SPLIT: weights and activations are carried as
+// bf16 hi + lo pairs and each step issues hi*hi + hi*lo + lo*hi.
+template <int MODE> struct Mode;
+template <> struct Mode<0> {            // FP32: FP32 MFMA, FP32 K/V
+  typedef float KvT; typedef float ActT; typedef float WT;
+  static constexpr int KC = 16; static constexpr bool SPLIT = false;
 };
-template <> struct Prec<1> {            // BF16 storage, FP32 accumulation
-  typedef __bf16 T;
-  static constexpr int VEC = 8;
-  static constexpr int KC = 32;         // one 16x16x32 MFMA
+template <> struct Mode<1> {            // BF16: BF16 MFMA (FP32 accumulation), BF16 K/V
+  typedef __bf16 KvT; typedef __bf16 ActT; typedef __bf16 WT;
+  static constexpr int KC = 32; static constexpr bool SPLIT = false;
+};
+template <> struct Mode<2> {            // BF16 split-operand MFMA, FP16 K/V
+  typedef _Float16 KvT; typedef float ActT; typedef __bf16 WT;
+  static constexpr int KC = 32; static constexpr bool SPLIT = true;
 };
 
 __device__ __forceinline__ float to_f(float x) { return x; }
 __device__ __forceinline__ float to_f(__bf16 x) { return (float)x; }
+__device__ __forceinline__ float to_f(_Float16 x) { return (float)x; }
 template <typename T> __device__ __forceinline__ T from_f(float x);
 template <> __device__ __forceinline__ float from_f<float>(float x) { return x; }
-template <> __device__ __forceinline__ __bf16 from_f<__bf16>(float x) { return (__bf16)x; }  // RNE
+template <> __device__ __forceinline__ __bf16 from_f<__bf16>(float x) { return (__bf16)x; }        // RNE
+template <> __device__ __forceinline__ _Float16 from_f<_Float16>(float x) { return (_Float16)x; }  // RNE
 
-// 16-byte chunk of VEC elements, unpacked to floats.
-template <int PREC> struct Chunk;
-template <> struct Chunk<0> {
+// A 16-byte chunk of K/V elements, unpacked to floats.
+template <typename T> struct Chunk;
+template <> struct Chunk<float> {
+  static constexpr int N = 4;
   float v[4];
   __device__ __forceinline__ void load(const float* p) {
     float4 t = *reinterpret_cast<const float4*>(p);
     v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
   }
 };
-template <> struct Chunk<1> {
+template <> struct Chunk<__bf16> {
+  static constexpr int N = 8;
   float v[8];
   __device__ __forceinline__ void load(const __bf16* p) {
     uint4 t = *reinterpret_cast<const uint4*>(p);
@@ -53,25 +64,76 @@ template <> struct Chunk<1> {
     }
   }
 };
+template <> struct Chunk<_Float16> {
+  static constexpr int N = 8;
+  float v[8];
+  __device__ __forceinline__ void load(const _Float16* p) {
+    uint4 t = *reinterpret_cast<const uint4*>(p);
+    f16x8 h;
+    __builtin_memcpy(&h, &t, 16);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = (float)h[i];
+  }
+};
 
-// One 16x16 output tile step over a K chunk of Prec<PREC>::KC elements.
-// Lane l supplies 16 bytes of A (row l%16) and of B (column l%16), both holding
-// the same K sub-range (l/16) of the chunk; any K permutation the hardware
-// applies is the same for A and B, so the product is the chunk's dot product.
-// Output layout: lane l holds C[4*(l/16)+i][l%16], i = 0..3.
-__device__ __forceinline__ floatx4 mfma_chunk(const uint4& a, const uint4& b, floatx4 acc, Prec<1>) {
+__device__ __forceinline__ floatx4 mfma_bf16(const uint4& a, const uint4& b, floatx4 acc) {
   bf16x8 av, bv;
   __builtin_memcpy(&av, &a, 16);
   __builtin_memcpy(&bv, &b, 16);
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
 }
-__device__ __forceinline__ floatx4 mfma_chunk(const uint4& a, const uint4& b, floatx4 acc, Prec<0>) {
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
-  return acc;
+
+// Split 8 floats into bf16 hi and lo parts (x = hi + lo + O(2^-16 |x|)).
+__device__ __forceinline__ void split8(const float* x, uint4& hi, uint4& lo) {
+  bf16x8 h, l;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const __bf16 b = (__bf16)x[i];
+    h[i] = b;
+    l[i] = (__bf16)(x[i] - (float)b);
+  }
+  __builtin_memcpy(&hi, &h, 16);
+  __builtin_memcpy(&lo, &l, 16);
 }
+
+// One 16x16 output tile step over a K chunk of Mode<MODE>::KC elements.
+// Lane l supplies A elements of row l%16 and B elements of column l%16, both
+// for the same K sub-range (l/16) of the chunk; whatever K permutation the
+// hardware applies is the same for A and B, so the product is the chunk's dot
+// product.  Output layout: lane l holds C[4*(l/16)+i][l%16], i = 0..3.
+// a: the lane's A elements (ActT); b / blo: the lane's 16-byte packed weight
+// fragment(s).
+template <int MODE> struct Frag;
+template <> struct Frag<0> {
+  static __device__ __forceinline__ floatx4 step(const float* a, const uint4* b, const uint4*, floatx4 acc) {
+    const float4 av = *reinterpret_cast<const float4*>(a);
+    const uint4 bv = *b;
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, __uint_as_float(bv.x), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, __uint_as_float(bv.y), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, __uint_as_float(bv.z), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, __uint_as_float(bv.w), acc, 0, 0, 0);
+    return acc;
+  }
+};
+template <> struct Frag<1> {
+  static __device__ __forceinline__ floatx4 step(const __bf16* a, const uint4* b, const uint4*, floatx4 acc) {
+    return mfma_bf16(*reinterpret_cast<const uint4*>(a), *b, acc);
+  }
+};
+template <> struct Frag<2> {
+  static __device__ __forceinline__ floatx4 step(const float* a, const uint4* b, const uint4* blo, floatx4 acc) {
+    float x[8];
+    const float4 a0 = *reinterpret_cast<const float4*>(a);
+    const float4 a1 = *reinterpret_cast<const float4*>(a + 4);
+    x[0] = a0.x; x[1] = a0.y; x[2] = a0.z; x[3] = a0.w; x[4] = a1.x; x[5] = a1.y; x[6] = a1.z; x[7] = a1.w;
+    uint4 ah, al;
+    split8(x, ah, al);
+    const uint4 bh = *b, bl = *blo;
+    acc = mfma_bf16(al, bh, acc);
+    acc = mfma_bf16(ah, bl, acc);
+    return mfma_bf16(ah, bh, acc);
+  }
+};
 
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float x) {

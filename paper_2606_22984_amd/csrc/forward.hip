@@ -1,0 +1,144 @@
+// Teacher-forced pass of the network over every position at once (Alg. 1),
+// and the row kernels the backward pass re-uses.  Rows r = b*N + t of a chunk
+// of samples are processed in parallel:
+//   embed      x0[r] = [tok_emb[tok]; pos_emb[t]]
+//   ln         a = LN(x) (row-major GEMM operand and/or a feature-major copy)
+//   gemm_rows  out = a W^T (packed weights, MFMA) with fused epilogues
+//   attn_fwd   band+prefix masked attention, online softmax; writes o, x + o
+//              and the per-(row, head) log-sum-exp the backward pass needs
+//   head_fwd   log p_t(s_t) summed per sample in a fixed order
+#include <algorithm>
+
+#include "device_common.h"
+#include "fvan_model.h"
+#include "passes.h"
+#include "row_kernels.h"
+
+namespace fvan {
+
+// ---------------------------------------------------------------- embedding
+__global__ void embed_kernel(const float* __restrict__ theta, int64_t pos_off, int dt, int D, int N,
+                             const int8_t* __restrict__ spins, int64_t rows, float* __restrict__ X) {
+  const int64_t total = rows * D;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / D;
+    const int k = (int)(i % D);
+    const int t = (int)(r % N);
+    float v;
+    if (k < dt) {
+      const int tok = t == 0 ? 0 : (spins[r - 1] + 1) >> 1;
+      v = theta[tok * dt + k];
+    } else {
+      v = theta[pos_off + (int64_t)t * (D - dt) + (k - dt)];
+    }
+    X[i] = v;
+  }
+}
+
+// ---------------------------------------------------------------- head
+// One workgroup per sample; 16 lanes per position.  logq[b] = sum_t log p_t(s_t)
+// in a fixed order.
+template <int D>
+__global__ __launch_bounds__(256) void head_fwd_kernel(const float* __restrict__ X, const float* __restrict__ theta,
+                                                       int64_t head_w, int64_t head_b, const int8_t* __restrict__ spins,
+                                                       int N, float* __restrict__ logq) {
+  __shared__ float red[16];
+  const int b = blockIdx.x;
+  const int grp = threadIdx.x >> 4, part = threadIdx.x & 15;
+  const float* w0 = theta + head_w;
+  const float* w1 = w0 + D;
+  const float b0v = theta[head_b], b1v = theta[head_b + 1];
+  float acc = 0.f;
+  for (int t = grp; t < N; t += 16) {
+    const float* x = X + ((int64_t)b * N + t) * D;
+    float z0 = 0.f, z1 = 0.f;
+#pragma unroll
+    for (int i = 0; i < D / 16; ++i) {
+      const int k = part + 16 * i;
+      z0 += x[k] * w0[k];
+      z1 += x[k] * w1[k];
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) { z0 += __shfl_xor(z0, o, 16); z1 += __shfl_xor(z1, o, 16); }
+    const float d = (z1 + b1v) - (z0 + b0v);
+    const int s = spins[(int64_t)b * N + t] > 0;
+    acc += s ? -softplus(-d) : -softplus(d);
+  }
+  if (part == 0) red[grp] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float tot = 0.f;
+    for (int i = 0; i < 16; ++i) tot += red[i];
+    logq[b] = tot;
+  }
+}
+
+// ---------------------------------------------------------------- drivers
+template <int MODE, int D>
+hipError_t forward_layer(fvan_model* m, int l, int64_t rows, int nsamp, bool for_backward, hipStream_t s) {
+  typedef typename Mode<MODE>::ActT AT;
+  typedef typename Mode<MODE>::KvT KT;
+  const fvan_model_config& c = m->cfg;
+  auto& f = m->fw;
+  const float* lp = m->params + m->po.layer0 + (int64_t)l * m->po.layer_stride;
+  const char* wl = reinterpret_cast<const char*>(m->wpack) + (size_t)l * m->pk.layer_stride;
+  const float* X = f.X + (size_t)l * f.rows * D;
+  float* Xn = f.X + (size_t)(l + 1) * f.rows * D;
+  const int lgrid = (int)((rows + 63) / 64);
+  hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(lgrid), dim3(256), 0, s, X, rows, lp + m->po.ln1_g,
+                     lp + m->po.ln1_b, (AT*)f.A, (AT*)nullptr, (int64_t)0);
+  EpiArgs e{};
+  e.bias = lp + m->po.qkv_b;
+  e.out = f.QKV;
+  hipError_t err = gemm_rows<MODE, D, 3 * D, EPI_STORE_KV>((const AT*)f.A, rows, wl + m->pk.qkv, e, s);
+  if (err != hipSuccess) return err;
+  const int H = c.n_heads;
+  hipLaunchKernelGGL((attn_fwd_kernel<KT>), dim3((c.n_spins + 63) / 64, (H + 3) / 4, nsamp), dim3(256), 0, s,
+                     (const KT*)f.QKV, X, f.O, f.XM, f.LSE, c.n_spins, D, H, c.window, m->kg.P);
+  hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(lgrid), dim3(256), 0, s, (const float*)f.XM, rows,
+                     lp + m->po.ln2_g, lp + m->po.ln2_b, (AT*)f.A, (AT*)nullptr, (int64_t)0);
+  EpiArgs e1{};
+  e1.bias = lp + m->po.ffn1_b;
+  e1.out = f.HID;
+  e1.hpre_out = for_backward ? f.HPRE : nullptr;
+  err = gemm_rows<MODE, D, 4 * D, EPI_GELU>((const AT*)f.A, rows, wl + m->pk.ffn1, e1, s);
+  if (err != hipSuccess) return err;
+  EpiArgs e2{};
+  e2.bias = lp + m->po.ffn2_b;
+  e2.resid = f.XM;
+  e2.out = Xn;
+  return gemm_rows<MODE, 4 * D, D, EPI_RESID>((const AT*)f.HID, rows, wl + m->pk.ffn2, e2, s);
+}
+
+template <int MODE, int D>
+static hipError_t forward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp, float* logq, bool for_backward,
+                                  hipStream_t s) {
+  const fvan_model_config& c = m->cfg;
+  const int64_t rows = (int64_t)nsamp * c.n_spins;
+  const int grid = (int)std::min<int64_t>((rows * D + 255) / 256, 65536);
+  hipLaunchKernelGGL(embed_kernel, dim3(grid), dim3(256), 0, s, m->params, m->po.pos, c.d_token, D, c.n_spins,
+                     spins, rows, m->fw.X);
+  for (int l = 0; l < c.n_layers; ++l) {
+    hipError_t e = forward_layer<MODE, D>(m, l, rows, nsamp, for_backward, s);
+    if (e != hipSuccess) return e;
+  }
+  if (logq) {
+    hipLaunchKernelGGL((head_fwd_kernel<D>), dim3(nsamp), dim3(256), 0, s,
+                       (const float*)(m->fw.X + (size_t)c.n_layers * m->fw.rows * D), m->params, m->po.head_w,
+                       m->po.head_b, spins, c.n_spins, logq);
+  }
+  return hipGetLastError();
+}
+
+hipError_t forward_chunk(fvan_model* m, const int8_t* spins, int nsamp, float* logq, bool for_backward,
+                         hipStream_t s) {
+  const int D = m->cfg.d_model;
+#define FWD_CASE(MODE, DD) if (m->cfg.precision == MODE && D == DD) return forward_chunk_t<MODE, DD>(m, spins, nsamp, logq, for_backward, s);
+  FWD_CASE(0, 32) FWD_CASE(0, 64) FWD_CASE(0, 128)
+  FWD_CASE(1, 32) FWD_CASE(1, 64) FWD_CASE(1, 128)
+  FWD_CASE(2, 32) FWD_CASE(2, 64) FWD_CASE(2, 128)
+#undef FWD_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace fvan

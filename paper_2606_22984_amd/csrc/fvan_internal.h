@@ -24,13 +24,16 @@ ParamOffsets param_offsets(const fvan_model_config& c);
 // backward packs (transposes): qkvT [D x 3D], ffn1T [D x 4D], ffn2T [4D x D].
 // A pack of a [rows x K] matrix stores, for tile n (16 rows) and K chunk c, the
 // 64 lanes' 16-byte fragments contiguously: lane l holds row 16n + l%16,
-// elements c*KC + (l/16)*KC/4 .. +KC/4.
+// elements c*KC + (l/16)*KC/4 .. +KC/4.  Split packs store all hi fragments,
+// then all lo fragments.
 struct PackOffsets {
   size_t qkv, ffn1, ffn2, qkvT, ffn1T, ffn2T, layer_stride, total;
 };
 PackOffsets pack_offsets(const fvan_model_config& c);
 
-inline int elem_bytes(int precision) { return precision == FVAN_BF16 ? 2 : 4; }
+// Bytes per K/V cache element and per packed weight (split packs hold hi and lo).
+inline int kv_elem_bytes(int precision) { return precision == FVAN_FP32 ? 4 : 2; }
+inline int w_elem_bytes(int precision) { return precision == FVAN_BF16 ? 2 : 4; }
 
 // KV cache geometry of the sampler: per (sample, layer) [2][S][D], slots
 // [0, P) hold prefix positions, [P, P+R) a ring of the last R band positions.

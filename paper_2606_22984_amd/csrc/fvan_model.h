@@ -35,6 +35,11 @@ struct fvan_model {
     float* XM = nullptr;           // [rows][D] residual after attention
     float* O = nullptr;            // [rows][D] attention output
     float* LSE = nullptr;          // [rows][H] log-sum-exp of the scores (base 2)
+    float* DELTA = nullptr;        // [rows][H] dO . O per head (backward)
+    float* TMP = nullptr;          // [rows][D] LayerNorm-output gradients (backward)
+    void* DY = nullptr;            // [rows][D] incoming gradient as a GEMM operand (backward)
+    void* T_c = nullptr;           // [(D+16)][ldT] feature-major LN outputs (+ ones row) for weight gradients
+    int64_t ldT = 0;               // row stride of the feature-major buffers (rows rounded up to 64)
     void* A = nullptr;             // [rows][D] LN output (GEMM operand)
     void* QKV = nullptr;           // [rows][3D]
     void* HID = nullptr;           // [rows][4D] GELU output
@@ -45,8 +50,8 @@ struct fvan_model {
     float* dXM = nullptr;          // [rows][D]
     void* dQKV = nullptr;          // [rows][3D]
     void* dH = nullptr;            // [rows][4D] gradient of the FFN pre-activation
-    void* T_a = nullptr;           // [(4D+16)][rows] feature-major copies for weight gradients
-    void* T_b = nullptr;           // [(4D+16)][rows]
+    void* T_a = nullptr;           // [4D][ldT] feature-major left operands of the weight gradients
+    void* T_b = nullptr;           // [(4D+16)][ldT] feature-major GELU outputs (+ ones row)
     float* part = nullptr;         // split-K partial sums
     size_t part_floats = 0;
     float* colpart = nullptr;      // per-tile partial column sums (LN gains, head, embeddings)
@@ -57,6 +62,7 @@ struct fvan_model {
 namespace fvan {
 int model_allocate(fvan_model* m);
 void model_free(fvan_model* m);
+void model_free_fwd(fvan_model* m);
 DecodeUnit make_decode_unit(const fvan_model* m, int32_t batch, uint64_t seed, uint64_t stream_id, int8_t* spins,
                             float* log_q, void* kv, int tile0);
 hipError_t launch_decode_single(int d_model, int precision, const DecodeUnit& u, int tiles, hipStream_t s);

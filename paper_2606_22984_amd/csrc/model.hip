@@ -26,7 +26,7 @@ int model_allocate(fvan_model* m) {
   m->n_params = m->po.total;
   if (hipGetDevice(&m->device) != hipSuccess) return fail(FVAN_EDEVICE, "hipGetDevice failed");
   const size_t B = (size_t)c.max_batch;
-  const size_t eb = elem_bytes(c.precision);
+  const size_t eb = kv_elem_bytes(c.precision);
   m->kv_bytes = B * c.n_layers * 2 * (size_t)m->kg.S * c.d_model * eb;
   int rc;
   if ((rc = dalloc(&m->wpack, std::max<size_t>(m->pk.total, 16), "packed weights"))) return rc;
@@ -50,10 +50,14 @@ static void dfree(void* p) {
 void model_free(fvan_model* m) {
   dfree(m->wpack); dfree(m->kv); dfree(m->adam_m); dfree(m->adam_v);
   dfree(m->ts_spins); dfree(m->ts_logq); dfree(m->ts_energy); dfree(m->ts_w); dfree(m->ts_dbl);
+  model_free_fwd(m);
+}
+
+void model_free_fwd(fvan_model* m) {
   auto& f = m->fw;
-  dfree(f.X); dfree(f.XM); dfree(f.O); dfree(f.LSE); dfree(f.A); dfree(f.QKV); dfree(f.HID); dfree(f.HPRE);
-  dfree(f.logp); dfree(f.dX); dfree(f.dXM); dfree(f.dQKV); dfree(f.dH); dfree(f.T_a); dfree(f.T_b);
-  dfree(f.part); dfree(f.colpart);
+  dfree(f.X); dfree(f.XM); dfree(f.O); dfree(f.LSE); dfree(f.DELTA); dfree(f.TMP); dfree(f.DY); dfree(f.A);
+  dfree(f.QKV); dfree(f.HID); dfree(f.HPRE); dfree(f.logp); dfree(f.dX); dfree(f.dXM); dfree(f.dQKV); dfree(f.dH);
+  dfree(f.T_a); dfree(f.T_b); dfree(f.T_c); dfree(f.part); dfree(f.colpart);
   m->fw = fvan_model::Fwd();
 }
 

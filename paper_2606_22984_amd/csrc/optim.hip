@@ -1,17 +1,23 @@
 // Parameter-side kernels: the packed weight copies the MFMA kernels read
 // (FP32 or round-to-nearest-even BF16, in 16-byte lane-fragment order) and the
 // Adam update of the flat FP32 parameters.
+#include <algorithm>
+#include <cmath>
+
 #include "device_common.h"
 #include "fvan_internal.h"
 
 namespace fvan {
 
 // dst = pack of the [rows x K] matrix M, M[r][k] = src[r*K + k] (or src[k*rows + r]
-// when transposed, i.e. M = W^T of a row-major W [K x rows]).
-template <int PREC>
+// when transposed, i.e. M = W^T of a row-major W [K x rows]).  Split mode
+// writes the bf16 hi parts at dst[0, rows*K) and the lo parts right after.
+template <int MODE>
 __global__ void pack_kernel(const float* __restrict__ src, int rows, int K, int transposed,
-                            typename Prec<PREC>::T* __restrict__ dst) {
-  constexpr int VEC = Prec<PREC>::VEC, KC = Prec<PREC>::KC;
+                            typename Mode<MODE>::WT* __restrict__ dst) {
+  typedef typename Mode<MODE>::WT WT;
+  constexpr int KC = Mode<MODE>::KC;
+  constexpr int VEC = KC / 4;
   const int64_t total = (int64_t)rows * K;
   const int nchunk = K / KC;
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
@@ -22,15 +28,17 @@ __global__ void pack_kernel(const float* __restrict__ src, int rows, int K, int 
     const int c = (int)(rest % nchunk);
     const int n = (int)(rest / nchunk);
     const int r = 16 * n + (l & 15);
-    const int k = c * KC + (l >> 4) * (KC / 4) + e;
+    const int k = c * KC + (l >> 4) * VEC + e;
     const float v = transposed ? src[(size_t)k * rows + r] : src[(size_t)r * K + k];
-    dst[p] = from_f<typename Prec<PREC>::T>(v);
+    const WT hi = from_f<WT>(v);
+    dst[p] = hi;
+    if (Mode<MODE>::SPLIT) dst[p + total] = from_f<WT>(v - to_f(hi));
   }
 }
 
-template <int PREC>
+template <int MODE>
 static hipError_t pack_all(const fvan_model_config& c, const float* theta, void* wpack, hipStream_t s) {
-  typedef typename Prec<PREC>::T T;
+  typedef typename Mode<MODE>::WT WT;
   const ParamOffsets po = param_offsets(c);
   const PackOffsets pk = pack_offsets(c);
   const int D = c.d_model;
@@ -44,15 +52,20 @@ static hipError_t pack_all(const fvan_model_config& c, const float* theta, void*
     for (auto& j : jobs) {
       const int64_t total = (int64_t)j.rows * j.K;
       const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
-      hipLaunchKernelGGL((pack_kernel<PREC>), dim3(grid), dim3(256), 0, s, j.src, j.rows, j.K, j.tr,
-                         reinterpret_cast<T*>(w + j.off));
+      hipLaunchKernelGGL((pack_kernel<MODE>), dim3(grid), dim3(256), 0, s, j.src, j.rows, j.K, j.tr,
+                         reinterpret_cast<WT*>(w + j.off));
     }
   }
   return hipGetLastError();
 }
 
 hipError_t launch_pack(const fvan_model_config& c, const float* theta, void* wpack, hipStream_t s) {
-  return c.precision == FVAN_BF16 ? pack_all<1>(c, theta, wpack, s) : pack_all<0>(c, theta, wpack, s);
+  switch (c.precision) {
+    case FVAN_FP32: return pack_all<0>(c, theta, wpack, s);
+    case FVAN_BF16: return pack_all<1>(c, theta, wpack, s);
+    case FVAN_BF16_SPLIT: return pack_all<2>(c, theta, wpack, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // Adam (Kingma & Ba) with L2 weight decay folded into the gradient; the
