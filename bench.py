@@ -1,0 +1,193 @@
+"""Benchmark of the FlashVAN hot path on one MI355X.
+
+Workload: 3D Edwards-Anderson L = 10 (N = 1000 spins, periodic, Gaussian
+bonds), transformer d_model = 128, 8 layers, 8 heads, batch 16384, beta = 1,
+mask (window, prefix) derived from the lattice.  One step = one training step
+of the method: KV-cached sampling of the batch, energies, F_q statistics,
+REINFORCE weights, the hand-written backward and the Adam update.  Inputs
+(couplings, parameters) are resident in HBM before timing starts.
+
+Prints ONE JSON line.  value = spin samples per second through the full
+training step in the headline precision (BF16_SPLIT: BF16 MFMA on split
+operands with an FP16 K/V cache); FP32 and plain BF16 are timed beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kv_bytes_per_sample(N, L, D, W, P, kv_elem):
+    """Algorithmic K/V traffic of one sample's decode: every visible key and value
+    read once per step and layer, plus the new key and value written."""
+    R = min(W + 1, N - P)
+    reads = 0
+    for t in range(N):
+        nvis = t + 1 if t < P else P + min(t - P + 1, R)
+        reads += nvis
+    return (reads * 2 * D + N * 2 * D) * kv_elem * L + N   # + spins
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--compare-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--profile-decode", action="store_true",
+                    help="no benchmark: one 1 GiB device copy (counter scale) then one decode launch at the "
+                         "benchmark shape, for hardware-counter runs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path shards by samples, "
+              "see the design notes for the multi-GPU layout", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2606_22984_amd as fv
+    from workloads import ea_instance, init_params, workload
+
+    torch.cuda.set_device(0)
+    wl = workload("ea3d_L10")
+    inst = ea_instance(wl.size, wl.dim, wl.instance_seed, wl.bonds)
+    W, P = fv.derive_mask(inst.n, inst.edges_i, inst.edges_j)
+    cfg = wl.model.with_mask(W, P)
+    theta = init_params(cfg, wl.param_seed, "default")
+    B, beta, seed = wl.batch, 1.0, 12345
+    N, L, D = cfg.n_spins, cfg.n_layers, cfg.d_model
+    coup = fv.couplings(inst)
+
+    if args.profile_decode:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)                       # reads and writes exactly 1 GiB
+        m = fv.Model(cfg, B, fv.FVAN_BF16_SPLIT, theta)
+        m.sample(B, seed, 1)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_decode": "done", "copy_bytes": 1 << 30,
+                          "decode_algorithmic_bytes": kv_bytes_per_sample(N, L, D, W, P, 2) * B}))
+        return
+
+    def run(prec, steps, warmup):
+        m = fv.Model(cfg, B, prec, theta)
+        stream = torch.cuda.current_stream()
+        spins = torch.empty(B, N, dtype=torch.int8, device="cuda")
+        lq = torch.empty(B, dtype=torch.float32, device="cuda")
+        E = coup.empty_energy(B)
+        stats = torch.zeros(4, dtype=torch.float64, device="cuda")
+        w = torch.empty(B, dtype=torch.float32, device="cuda")
+        ev = []
+
+        def step(k, timed):
+            if timed:
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+            m.sample(B, seed, k, spins, lq)
+            if timed:
+                b.record(stream)
+                ev.append((a, b))
+            fv.energy(coup, spins, E)
+            fv.free_energy(E, lq, beta, N, stats[:2])
+            fv.reinforce_weights(E, lq, beta, w)
+            m.log_prob_backward(spins, w)
+            m.adam_step(k, lr=1e-3)
+
+        for k in range(1, warmup + 1):
+            step(k, False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(warmup + 1, warmup + steps + 1):
+            step(k, True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        dec = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        st = stats.cpu().numpy()
+        res = dict(ms_per_step=1e3 * wall / steps, samples_per_s=B * steps / wall, decode_ms=dec,
+                   sample_only_samples_per_s=B / (dec * 1e-3), F_per_site=float(st[0]),
+                   var_f=float(st[1]))
+        m.close()
+        del m
+        torch.cuda.empty_cache()
+        return res
+
+    SPLIT, FP32, BF16 = fv.FVAN_BF16_SPLIT, fv.FVAN_FP32, fv.FVAN_BF16
+    head = run(SPLIT, args.steps, args.warmup)
+    others = {}
+    if not args.no_compare:
+        others["fp32"] = run(FP32, args.compare_steps, 1)
+        others["bf16"] = run(BF16, args.compare_steps, 1)
+    kv_elem = 2
+    bytes_launch = kv_bytes_per_sample(N, L, D, W, P, kv_elem) * B
+    achieved = bytes_launch / (head["decode_ms"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "decode_kernel<128,2>", "algorithmic_bytes_per_launch": bytes_launch}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, theta, inst, beta)
+
+    out = {
+        "metric": "spin samples/sec + train-step ms, BF16 vs FP32, 1 GPU, at |dF/N|<=1e-4",
+        "value": round(head["samples_per_s"], 2),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16-split-mfma+fp16-kv",
+        "data": "synthetic: seeded Gaussian 3D EA instance and seeded random-init parameters",
+        "config": {"workload": "3D EA L=10 PBC (N=1000), Gaussian J, beta=1, d_model=128, 8 layers, 8 heads, "
+                               "batch 16384, mask W=%d P=%d" % (W, P),
+                   "global_batch": B, "seq_len": N, "parallelism": "none (1 GPU)"},
+        "sample_only_samples_per_s": round(head["sample_only_samples_per_s"], 1),
+        "decode_ms": round(head["decode_ms"], 2),
+        "precisions": {"bf16split": _round(head), **{k: _round(v) for k, v in others.items()}},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if "fp32" in others:
+        out["speedup_vs_fp32"] = {
+            "train_step": round(head["samples_per_s"] / others["fp32"]["samples_per_s"], 3),
+            "sampling": round(head["sample_only_samples_per_s"] / others["fp32"]["sample_only_samples_per_s"], 3)}
+    print(json.dumps(out))
+
+
+def _round(d):
+    return {k: (round(v, 6) if isinstance(v, float) else v) for k, v in d.items()}
+
+
+def cpu_baseline(cfg, theta, inst, beta, n_samples=2):
+    """The FP64 oracle (as it stands) running the same training step on a bounded
+    sample: KV-cached sampling of n_samples, energies, REINFORCE weights and the
+    reverse-mode gradient.  Throughput in samples/s of that step."""
+    import torch
+    from oracle import estimator, physics, sampler
+    t0 = time.perf_counter()
+    spins, lq, _ = sampler.kv_sample(theta, cfg, n_samples, 12345, 1)
+    E = physics.energy_edges(spins, inst.edges_i, inst.edges_j, inst.J)
+    estimator.free_energy_stats(E, lq, beta, cfg.n_spins)
+    estimator.reinforce_gradient(theta, cfg, spins, E, lq, beta)
+    dt = time.perf_counter() - t0
+    return {"value": round(n_samples / dt, 5), "unit": "samples/s", "cores": torch.get_num_threads(),
+            "kind": "oracle", "sample": f"{n_samples} samples of the same workload through one FP64 training step "
+                                        f"(sampling, energy, estimator, gradient): {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()
