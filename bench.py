@@ -23,6 +23,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# first learning rate of the paper's linear warm-up (SI Sec. III B); larger first
+# Adam steps collapse this random-init model within a few steps
+LR = 1e-5
 
 
 def kv_bytes_per_sample(N, L, D, W, P, kv_elem):
@@ -34,6 +37,10 @@ def kv_bytes_per_sample(N, L, D, W, P, kv_elem):
         nvis = t + 1 if t < P else P + min(t - P + 1, R)
         reads += nvis
     return (reads * 2 * D + N * 2 * D) * kv_elem * L + N   # + spins
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -102,11 +109,12 @@ def main():
             fv.free_energy(E, lq, beta, N, stats[:2])
             fv.reinforce_weights(E, lq, beta, w)
             m.log_prob_backward(spins, w)
-            m.adam_step(k, lr=1e-3)
+            m.adam_step(k, lr=LR)
 
         for k in range(1, warmup + 1):
             step(k, False)
         torch.cuda.synchronize()
+        progress(f"precision {fv.PRECISION_NAMES[prec]}: warm-up done")
         t0 = time.perf_counter()
         for k in range(warmup + 1, warmup + steps + 1):
             step(k, True)
@@ -120,6 +128,7 @@ def main():
         m.close()
         del m
         torch.cuda.empty_cache()
+        progress(f"precision {fv.PRECISION_NAMES[prec]}: {res['ms_per_step']:.1f} ms/step, decode {dec:.1f} ms")
         return res
 
     SPLIT, FP32, BF16 = fv.FVAN_BF16_SPLIT, fv.FVAN_FP32, fv.FVAN_BF16
@@ -137,6 +146,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        progress("timing the FP64 oracle on the host")
         cpu = cpu_baseline(cfg, theta, inst, beta)
 
     out = {

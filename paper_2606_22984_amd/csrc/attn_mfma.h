@@ -1,0 +1,335 @@
+// Band+prefix masked attention on MFMA for the teacher-forced pass and its
+// backward (d_head = 16 = one 16x16 MFMA tile of K).
+//
+// Notation per (sample, head): S = Q K^T / sqrt(16) in log2 units (the scale
+// and log2(e) are folded into Q or K), P = 2^(S - LSE), O = P V.
+// Lane layouts of a 16x16 tile (l = lane): the A operand holds A[l%16][4g..4g+3]
+// and the B operand B[4g..4g+3][l%16] with g = l/16; the accumulator holds
+// C[4g+i][l%16].  Computing S^T = K Q^T therefore leaves lane l with keys 4g+i
+// of query l%16, which is the B layout P^T needs in O^T = V^T P^T and the A
+// layout dS needs in dQ = dS K; the dK/dV kernel moves P^T and dS^T through a
+// small LDS tile to reach the A layout.
+//
+// Precision: FP32 MFMA (16x16x4, four per tile) for FVAN_FP32 and
+// FVAN_BF16_SPLIT, BF16 MFMA (16x16x16) for FVAN_BF16.
+#pragma once
+
+#include <algorithm>
+
+#include "device_common.h"
+
+namespace fvan {
+
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+
+template <bool BF>
+__device__ __forceinline__ floatx4 mfma16(const float4& a, const float4& b, floatx4 acc) {
+  if constexpr (BF) {
+    bf16x4 av = {(__bf16)a.x, (__bf16)a.y, (__bf16)a.z, (__bf16)a.w};
+    bf16x4 bv = {(__bf16)b.x, (__bf16)b.y, (__bf16)b.z, (__bf16)b.w};
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+  } else {
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ float4 load4(const T* p) {
+  return make_float4(to_f(p[0]), to_f(p[1]), to_f(p[2]), to_f(p[3]));
+}
+__device__ __forceinline__ float4 load4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+
+__device__ __forceinline__ bool visible(int t, int j, int W, int P) { return j <= t && (t - j <= W || j < P); }
+
+constexpr float kScaleLog2 = 0.25f * 1.4426950408889634f;   // 1/sqrt(16) * log2(e)
+
+// Order one wave's LDS writes before its lanes read each other's values.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+constexpr int kKeyChunk = 128;                               // keys staged in LDS at a time
+
+// The keys a query tile [t0, t1) can see: [0, pend) then [bstart, t1), as one
+// virtual index v -> position.
+struct KeyRange {
+  int pend, bstart, nk;
+  __device__ KeyRange(int t0, int t1, int W, int P) {
+    pend = min(P, t1);
+    bstart = max(P, t0 - W);
+    nk = pend + max(0, t1 - bstart);
+  }
+  __device__ __forceinline__ int pos(int v) const { return v < pend ? v : bstart + (v - pend); }
+};
+
+// ---------------------------------------------------------------- forward
+// One workgroup = (64 queries, head, sample); wave w owns queries t0+16w..+15.
+// Writes XM = X + O, and LSE (log2 units).
+template <typename KT, bool BF>
+__global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV, const float* __restrict__ X,
+                                                     float* __restrict__ XM, float* __restrict__ LSE, int N, int D,
+                                                     int H, int W, int P) {
+  __shared__ float Ks[kKeyChunk][20];     // [key][dim] (padded)
+  __shared__ float VsT[16][kKeyChunk + 4]; // [dim][key]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+  const int t0 = blockIdx.x * 64, h = blockIdx.y, b = blockIdx.z;
+  const int t1 = min(t0 + 64, N);
+  const int64_t rowbase = (int64_t)b * N;
+  const int tq = t0 + 16 * wave + c;                 // this lane's query
+  const bool qok = tq < N;
+  float4 q4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (qok) {
+    q4 = load4(QKV + (rowbase + tq) * 3 * D + h * 16 + 4 * g);
+    q4.x *= kScaleLog2; q4.y *= kScaleLog2; q4.z *= kScaleLog2; q4.w *= kScaleLog2;
+  }
+  const KeyRange kr(t0, t1, W, P);
+  float mx = -INFINITY, l = 0.f;
+  floatx4 o = {0.f, 0.f, 0.f, 0.f};                 // O^T[dim 4g+i][query c]
+  for (int v0 = 0; v0 < kr.nk; v0 += kKeyChunk) {
+    const int nv = min(kKeyChunk, kr.nk - v0);
+    __syncthreads();
+    for (int x = threadIdx.x; x < kKeyChunk * 16; x += 256) {
+      const int kk = x >> 4, d = x & 15;
+      float kv = 0.f, vv = 0.f;
+      if (kk < nv) {
+        const KT* kp = QKV + (rowbase + kr.pos(v0 + kk)) * 3 * D + D + h * 16 + d;
+        kv = to_f(kp[0]);
+        vv = to_f(kp[D]);
+      }
+      Ks[kk][d] = kv;
+      VsT[d][kk] = vv;
+    }
+    __syncthreads();
+    for (int kt0 = 0; kt0 < nv; kt0 += 64) {         // 4 key tiles of 16 per softmax update
+      float s[16];
+      float bmax = -INFINITY;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kb = kt0 + 16 * u;
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        if (kb < nv) acc = mfma16<BF>(load4(&Ks[kb + c][4 * g]), q4, acc);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int kv = kb + 4 * g + i;
+          const bool ok = kv < nv && qok && visible(tq, kr.pos(v0 + kv), W, P);
+          s[4 * u + i] = ok ? acc[i] : -INFINITY;
+          bmax = fmaxf(bmax, s[4 * u + i]);
+        }
+      }
+      bmax = fmaxf(bmax, __shfl_xor(bmax, 16));
+      bmax = fmaxf(bmax, __shfl_xor(bmax, 32));
+      const float mn = fmaxf(mx, bmax);
+      const float corr = mn == -INFINITY ? 1.f : __builtin_amdgcn_exp2f(mx - mn);
+      float ps = 0.f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        s[i] = s[i] == -INFINITY ? 0.f : __builtin_amdgcn_exp2f(s[i] - mn);
+        ps += s[i];
+      }
+      ps += __shfl_xor(ps, 16);
+      ps += __shfl_xor(ps, 32);
+      l = l * corr + ps;
+      mx = mn;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) o[i] *= corr;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kb = kt0 + 16 * u;
+        if (kb < nv)
+          o = mfma16<BF>(load4(&VsT[c][kb + 4 * g]), make_float4(s[4 * u], s[4 * u + 1], s[4 * u + 2], s[4 * u + 3]), o);
+      }
+    }
+  }
+  // lane (g, c) holds O^T[dim 4g+i][query c]: query tq, dims 4g..4g+3
+  if (qok) {
+    const float inv = 1.0f / l;
+    const int64_t r = rowbase + tq;
+    const float4 xv = *reinterpret_cast<const float4*>(X + r * D + h * 16 + 4 * g);
+    float4 out = make_float4(xv.x + o[0] * inv, xv.y + o[1] * inv, xv.z + o[2] * inv, xv.w + o[3] * inv);
+    *reinterpret_cast<float4*>(XM + r * D + h * 16 + 4 * g) = out;
+    if (g == 0) LSE[r * H + h] = mx + __log2f(l);
+  }
+}
+
+// ---------------------------------------------------------------- backward: dQ
+// One workgroup = (64 queries, head, sample).  O is recovered as XM - X.
+// Writes DELTA = dO . O, dQ (scaled) into dQKV and the feature-major copy T.
+template <typename KT, typename AT, bool BF>
+__global__ __launch_bounds__(256) void attn_bwd_dq_mfma(const KT* __restrict__ QKV, const float* __restrict__ X,
+                                                        const float* __restrict__ XM, const float* __restrict__ dO,
+                                                        const float* __restrict__ LSE, float* __restrict__ DELTA,
+                                                        AT* __restrict__ dQKV, AT* __restrict__ T, int64_t ldT, int N,
+                                                        int D, int H, int W, int P) {
+  __shared__ float Ks[kKeyChunk][20];
+  __shared__ float KsT[16][kKeyChunk + 4];
+  __shared__ float Vs[kKeyChunk][20];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+  const int t0 = blockIdx.x * 64, h = blockIdx.y, b = blockIdx.z;
+  const int t1 = min(t0 + 64, N);
+  const int64_t rowbase = (int64_t)b * N;
+  const int tq = t0 + 16 * wave + c;
+  const bool qok = tq < N;
+  const int64_t r = rowbase + tq;
+  float4 q4 = make_float4(0.f, 0.f, 0.f, 0.f), g4 = q4;
+  float lse = 0.f, delta = 0.f;
+  if (qok) {
+    q4 = load4(QKV + r * 3 * D + h * 16 + 4 * g);
+    q4.x *= kScaleLog2; q4.y *= kScaleLog2; q4.z *= kScaleLog2; q4.w *= kScaleLog2;
+    g4 = *reinterpret_cast<const float4*>(dO + r * D + h * 16 + 4 * g);
+    const float4 xm = *reinterpret_cast<const float4*>(XM + r * D + h * 16 + 4 * g);
+    const float4 xx = *reinterpret_cast<const float4*>(X + r * D + h * 16 + 4 * g);
+    delta = g4.x * (xm.x - xx.x) + g4.y * (xm.y - xx.y) + g4.z * (xm.z - xx.z) + g4.w * (xm.w - xx.w);
+    lse = LSE[r * H + h];
+  }
+  delta += __shfl_xor(delta, 16);
+  delta += __shfl_xor(delta, 32);
+  if (qok && g == 0) DELTA[r * H + h] = delta;
+  const KeyRange kr(t0, t1, W, P);
+  floatx4 dq = {0.f, 0.f, 0.f, 0.f};               // dQ[query 16w+4g+i][dim c]
+  for (int v0 = 0; v0 < kr.nk; v0 += kKeyChunk) {
+    const int nv = min(kKeyChunk, kr.nk - v0);
+    __syncthreads();
+    for (int x = threadIdx.x; x < kKeyChunk * 16; x += 256) {
+      const int kk = x >> 4, d = x & 15;
+      float kv = 0.f, vv = 0.f;
+      if (kk < nv) {
+        const KT* kp = QKV + (rowbase + kr.pos(v0 + kk)) * 3 * D + D + h * 16 + d;
+        kv = to_f(kp[0]);
+        vv = to_f(kp[D]);
+      }
+      Ks[kk][d] = kv;
+      KsT[d][kk] = kv;
+      Vs[kk][d] = vv;
+    }
+    __syncthreads();
+    for (int kb = 0; kb < nv; kb += 16) {
+      floatx4 sa = {0.f, 0.f, 0.f, 0.f}, pa = {0.f, 0.f, 0.f, 0.f};
+      sa = mfma16<BF>(load4(&Ks[kb + c][4 * g]), q4, sa);     // S^T[key 4g+i][query c]
+      pa = mfma16<BF>(load4(&Vs[kb + c][4 * g]), g4, pa);     // dP^T[key 4g+i][query c]
+      float ds[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int kv = kb + 4 * g + i;
+        const bool ok = kv < nv && qok && visible(tq, kr.pos(v0 + kv), W, P);
+        const float p = ok ? __builtin_amdgcn_exp2f(sa[i] - lse) : 0.f;
+        ds[i] = p * (pa[i] - delta);
+      }
+      // dQ[query][dim] += dS[query][key] K[key][dim]; lane's dS = A layout of dS
+      dq = mfma16<BF>(make_float4(ds[0], ds[1], ds[2], ds[3]), load4(&KsT[c][kb + 4 * g]), dq);
+    }
+  }
+  // dq[i] = dQ[query 16w + 4g + i][dim c]
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int tqi = t0 + 16 * wave + 4 * g + i;
+    if (tqi < N) {
+      const int64_t ri = rowbase + tqi;
+      const AT v = from_f<AT>(dq[i] * 0.25f);
+      dQKV[ri * 3 * D + h * 16 + c] = v;
+      T[(int64_t)(h * 16 + c) * ldT + ri] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- backward: dK, dV
+// One workgroup = (64 keys, head, sample); wave w owns keys j0+16w..+15 and loops
+// over the query blocks that can see the tile ([j0, j1 + W), or [j0, N) when the
+// tile holds prefix keys).
+template <typename KT, typename AT, bool BF>
+__global__ __launch_bounds__(256) void attn_bwd_dkv_mfma(const KT* __restrict__ QKV, const float* __restrict__ dO,
+                                                         const float* __restrict__ LSE, const float* __restrict__ DELTA,
+                                                         AT* __restrict__ dQKV, AT* __restrict__ T, int64_t ldT, int N,
+                                                         int D, int H, int W, int P) {
+  __shared__ float Qs[64][20];
+  __shared__ float QsT[16][68];
+  __shared__ float Gs[64][20];
+  __shared__ float GsT[16][68];
+  __shared__ float Ls[64], Ds[64];
+  __shared__ float Tr[4][16][17];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+  const int j0 = blockIdx.x * 64, h = blockIdx.y, b = blockIdx.z;
+  const int j1 = min(j0 + 64, N);
+  const int64_t rowbase = (int64_t)b * N;
+  const int jk = j0 + 16 * wave + c;               // this lane's key (A-operand row)
+  const bool kok = jk < N;
+  float4 k4 = make_float4(0.f, 0.f, 0.f, 0.f), v4 = k4;
+  if (kok) {
+    const KT* kp = QKV + (rowbase + jk) * 3 * D + D + h * 16 + 4 * g;
+    k4 = load4(kp);
+    k4.x *= kScaleLog2; k4.y *= kScaleLog2; k4.z *= kScaleLog2; k4.w *= kScaleLog2;
+    v4 = load4(kp + D);
+  }
+  const int qend = j0 < P ? N : min(N, j1 + W);
+  floatx4 dk = {0.f, 0.f, 0.f, 0.f}, dv = {0.f, 0.f, 0.f, 0.f};   // [key 16w+4g+i][dim c]
+  for (int i0 = j0; i0 < qend; i0 += 64) {
+    const int nq = min(64, qend - i0);
+    __syncthreads();
+    for (int x = threadIdx.x; x < 64 * 16; x += 256) {
+      const int qq = x >> 4, d = x & 15;
+      float qv = 0.f, gv = 0.f;
+      if (qq < nq) {
+        const int64_t ri = rowbase + i0 + qq;
+        qv = to_f(QKV[ri * 3 * D + h * 16 + d]);
+        gv = dO[ri * D + h * 16 + d];
+      }
+      Qs[qq][d] = qv;
+      QsT[d][qq] = qv;
+      Gs[qq][d] = gv;
+      GsT[d][qq] = gv;
+    }
+    if (threadIdx.x < 64) {
+      const int qq = threadIdx.x;
+      const bool ok = qq < nq;
+      Ls[qq] = ok ? LSE[(rowbase + i0 + qq) * H + h] : 0.f;
+      Ds[qq] = ok ? DELTA[(rowbase + i0 + qq) * H + h] : 0.f;
+    }
+    __syncthreads();
+    for (int qb = 0; qb < nq; qb += 16) {
+      floatx4 sa = {0.f, 0.f, 0.f, 0.f}, pa = {0.f, 0.f, 0.f, 0.f};
+      sa = mfma16<BF>(k4, load4(&Qs[qb + c][4 * g]), sa);   // S^T[key 4g+i][query c]
+      pa = mfma16<BF>(v4, load4(&Gs[qb + c][4 * g]), pa);   // dP^T[key 4g+i][query c]
+      const int iq = i0 + qb + c;
+      float p[4], ds[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int jj = j0 + 16 * wave + 4 * g + i;
+        const bool ok = qb + c < nq && jj < N && visible(iq, jj, W, P);
+        p[i] = ok ? __builtin_amdgcn_exp2f(sa[i] - Ls[qb + c]) : 0.f;
+        ds[i] = p[i] * (pa[i] - Ds[qb + c]);
+      }
+      // transpose P^T and dS^T from (key 4g+i, query c) to (key c, queries 4g..4g+3)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Tr[wave][4 * g + i][c] = p[i];
+      wave_sync();
+      const float4 pt = make_float4(Tr[wave][c][4 * g], Tr[wave][c][4 * g + 1], Tr[wave][c][4 * g + 2],
+                                    Tr[wave][c][4 * g + 3]);
+      wave_sync();
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Tr[wave][4 * g + i][c] = ds[i];
+      wave_sync();
+      const float4 dst = make_float4(Tr[wave][c][4 * g], Tr[wave][c][4 * g + 1], Tr[wave][c][4 * g + 2],
+                                     Tr[wave][c][4 * g + 3]);
+      wave_sync();
+      dv = mfma16<BF>(pt, load4(&GsT[c][qb + 4 * g]), dv);    // dV[key][dim] += P^T[key][q] dO[q][dim]
+      dk = mfma16<BF>(dst, load4(&QsT[c][qb + 4 * g]), dk);   // dK[key][dim] += dS^T[key][q] Q[q][dim]
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int jj = j0 + 16 * wave + 4 * g + i;
+    if (jj < N) {
+      const int64_t rj = rowbase + jj;
+      const AT kvv = from_f<AT>(dk[i] * 0.25f);
+      const AT vvv = from_f<AT>(dv[i]);
+      dQKV[rj * 3 * D + D + h * 16 + c] = kvv;
+      dQKV[rj * 3 * D + 2 * D + h * 16 + c] = vvv;
+      T[(int64_t)(D + h * 16 + c) * ldT + rj] = kvv;
+      T[(int64_t)(2 * D + h * 16 + c) * ldT + rj] = vvv;
+    }
+  }
+}
+
+}  // namespace fvan

@@ -18,6 +18,7 @@
 #include "fvan_model.h"
 #include "passes.h"
 #include "row_kernels.h"
+#include "attn_mfma.h"
 
 namespace fvan {
 
@@ -109,13 +110,38 @@ __global__ __launch_bounds__(256) void head_bwd_kernel(const float* __restrict__
   }
 }
 
-// out[k] += sum_{i < n} part[i * width + k]  (fixed order); out may be strided in two pieces
-__global__ void colsum_add_kernel(const float* __restrict__ part, int n, int width, float* __restrict__ out) {
+// out[k] += sum_{i < n} part[i * width + k] in a fixed order.  Two levels: each
+// workgroup sums a fixed slice of partials for 64 columns into part2, then one
+// pass adds the slices.
+constexpr int kColSlices = 64;
+__global__ __launch_bounds__(256) void colsum_slices_kernel(const float* __restrict__ part, int n, int width,
+                                                            float* __restrict__ part2) {
+  __shared__ float red[4][64];
+  const int k = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int sub = threadIdx.x >> 6;
+  const int slice = blockIdx.y;
+  const int per = (n + kColSlices - 1) / kColSlices;
+  const int i0 = slice * per, i1 = min(n, i0 + per);
+  float s = 0.f;
+  if (k < width)
+    for (int i = i0 + sub; i < i1; i += 4) s += part[(size_t)i * width + k];
+  red[sub][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (sub == 0 && k < width)
+    part2[(size_t)slice * width + k] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+__global__ void colsum_final_kernel(const float* __restrict__ part2, int width, float* __restrict__ out) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < width; k += gridDim.x * blockDim.x) {
     float s = 0.f;
-    for (int i = 0; i < n; ++i) s += part[(size_t)i * width + k];
+    for (int i = 0; i < kColSlices; ++i) s += part2[(size_t)i * width + k];
     out[k] += s;
   }
+}
+
+static void colsum_add(const float* part, int n, int width, float* part2, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(colsum_slices_kernel, dim3((width + 63) / 64, kColSlices), dim3(256), 0, s, part, n, width, part2);
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((width + 255) / 256), dim3(256), 0, s, (const float*)part2, width, out);
 }
 
 // ---------------------------------------------------------------- transpose + cast
@@ -295,167 +321,6 @@ __global__ __launch_bounds__(256) void ln_bwd_kernel(const float* __restrict__ d
   }
 }
 
-// ---------------------------------------------------------------- attention backward
-// dQ: one workgroup per (sample, 64 queries, 4 heads); also writes
-// DELTA[r][h] = dO_r . O_r used by the dK/dV kernel.
-template <typename KT, typename AT>
-__global__ __launch_bounds__(256) void attn_bwd_dq_kernel(const KT* __restrict__ QKV, const float* __restrict__ O,
-                                                          const float* __restrict__ dO, const float* __restrict__ LSE,
-                                                          float* __restrict__ DELTA, AT* __restrict__ dQKV,
-                                                          AT* __restrict__ T, int64_t ldT, int N, int D, int H, int W,
-                                                          int P) {
-  __shared__ float Ks[64][4][17];
-  __shared__ float Vs[64][4][17];
-  const int qi = threadIdx.x & 63, hl = threadIdx.x >> 6;
-  const int t0 = blockIdx.x * 64, h0 = blockIdx.y * 4, b = blockIdx.z;
-  const int h = h0 + hl, t = t0 + qi;
-  const bool active = t < N && h < H;
-  const int t1 = std::min(t0 + 64, N);
-  const int64_t rowbase = (int64_t)b * N;
-  const int64_t r = rowbase + t;
-  constexpr float kScaleLog2 = 0.25f * 1.4426950408889634f;
-  float q[16], go[16], dq[16];
-  float lse = 0.f, delta = 0.f;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) { q[e] = 0.f; go[e] = 0.f; dq[e] = 0.f; }
-  if (active) {
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      q[e] = to_f(QKV[r * 3 * D + h * 16 + e]) * kScaleLog2;
-      go[e] = dO[r * D + h * 16 + e];
-      delta += go[e] * O[r * D + h * 16 + e];
-    }
-    lse = LSE[r * H + h];
-    DELTA[r * H + h] = delta;
-  }
-  const int pend = std::min(P, t1);
-  const int bstart = std::max(P, t0 - W);
-  for (int range = 0; range < 2; ++range) {
-    const int ks = range == 0 ? 0 : bstart;
-    const int ke = range == 0 ? pend : t1;
-    for (int j0 = ks; j0 < ke; j0 += 64) {
-      __syncthreads();
-      for (int i = threadIdx.x; i < 64 * 4 * 16; i += 256) {
-        const int jj = i >> 6, hh = (i >> 4) & 3, e = i & 15;
-        const int j = j0 + jj;
-        float kv = 0.f, vv = 0.f;
-        if (j < ke && h0 + hh < H) {
-          const KT* kp = QKV + (rowbase + j) * 3 * D + D + (h0 + hh) * 16 + e;
-          kv = to_f(kp[0]);
-          vv = to_f(kp[D]);
-        }
-        Ks[jj][hh][e] = kv;
-        Vs[jj][hh][e] = vv;
-      }
-      __syncthreads();
-      if (active) {
-        const int jn = std::min(64, ke - j0);
-        for (int jj = 0; jj < jn; ++jj) {
-          const int j = j0 + jj;
-          if (j > t || (t - j > W && j >= P)) continue;
-          float sc = 0.f, dp = 0.f;
-#pragma unroll
-          for (int e = 0; e < 16; ++e) { sc += q[e] * Ks[jj][hl][e]; dp += go[e] * Vs[jj][hl][e]; }
-          const float pr = __builtin_amdgcn_exp2f(sc - lse);
-          const float ds = pr * (dp - delta);
-#pragma unroll
-          for (int e = 0; e < 16; ++e) dq[e] += ds * Ks[jj][hl][e];
-        }
-      }
-    }
-  }
-  if (active) {
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const AT v = from_f<AT>(dq[e] * 0.25f);
-      dQKV[r * 3 * D + h * 16 + e] = v;
-      T[(int64_t)(h * 16 + e) * ldT + r] = v;
-    }
-  }
-}
-
-// dK, dV: one workgroup per (sample, 64 keys, 4 heads); loops over the query
-// blocks that can see the keys: [j0, j1 + W) for band keys, [j0, N) when the
-// tile holds prefix keys.
-template <typename KT, typename AT>
-__global__ __launch_bounds__(256) void attn_bwd_dkv_kernel(const KT* __restrict__ QKV, const float* __restrict__ dO,
-                                                           const float* __restrict__ LSE,
-                                                           const float* __restrict__ DELTA, AT* __restrict__ dQKV,
-                                                           AT* __restrict__ T, int64_t ldT, int N, int D, int H, int W,
-                                                           int P) {
-  __shared__ float Qs[64][4][17];
-  __shared__ float Gs[64][4][17];
-  __shared__ float Ls[64][4];
-  __shared__ float Ds[64][4];
-  const int ji = threadIdx.x & 63, hl = threadIdx.x >> 6;
-  const int j0 = blockIdx.x * 64, h0 = blockIdx.y * 4, b = blockIdx.z;
-  const int h = h0 + hl, j = j0 + ji;
-  const bool active = j < N && h < H;
-  const int j1 = std::min(j0 + 64, N);
-  const int64_t rowbase = (int64_t)b * N;
-  constexpr float kScaleLog2 = 0.25f * 1.4426950408889634f;
-  float kk[16], vv[16], dk[16], dv[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) { kk[e] = 0.f; vv[e] = 0.f; dk[e] = 0.f; dv[e] = 0.f; }
-  if (active) {
-    const KT* kp = QKV + (rowbase + j) * 3 * D + D + h * 16;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) { kk[e] = to_f(kp[e]); vv[e] = to_f(kp[D + e]); }
-  }
-  const int qend = j0 < P ? N : std::min(N, j1 + W);
-  for (int i0 = j0; i0 < qend; i0 += 64) {
-    __syncthreads();
-    for (int x = threadIdx.x; x < 64 * 4 * 16; x += 256) {
-      const int ii = x >> 6, hh = (x >> 4) & 3, e = x & 15;
-      const int i = i0 + ii;
-      float qv = 0.f, gv = 0.f;
-      if (i < qend && h0 + hh < H) {
-        qv = to_f(QKV[(rowbase + i) * 3 * D + (h0 + hh) * 16 + e]);
-        gv = dO[(rowbase + i) * D + (h0 + hh) * 16 + e];
-      }
-      Qs[ii][hh][e] = qv;
-      Gs[ii][hh][e] = gv;
-    }
-    for (int x = threadIdx.x; x < 64 * 4; x += 256) {
-      const int ii = x >> 2, hh = x & 3;
-      const int i = i0 + ii;
-      const bool ok = i < qend && h0 + hh < H;
-      Ls[ii][hh] = ok ? LSE[(rowbase + i) * H + h0 + hh] : 0.f;
-      Ds[ii][hh] = ok ? DELTA[(rowbase + i) * H + h0 + hh] : 0.f;
-    }
-    __syncthreads();
-    if (active) {
-      const int in = std::min(64, qend - i0);
-      for (int ii = 0; ii < in; ++ii) {
-        const int i = i0 + ii;
-        if (j > i || (i - j > W && j >= P)) continue;
-        float sc = 0.f, dp = 0.f;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) { sc += Qs[ii][hl][e] * kk[e]; dp += Gs[ii][hl][e] * vv[e]; }
-        const float pr = __builtin_amdgcn_exp2f(sc * kScaleLog2 - Ls[ii][hl]);
-        const float ds = pr * (dp - Ds[ii][hl]);
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          dv[e] += pr * Gs[ii][hl][e];
-          dk[e] += ds * Qs[ii][hl][e];
-        }
-      }
-    }
-  }
-  if (active) {
-    const int64_t r = rowbase + j;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const AT kvv = from_f<AT>(dk[e] * 0.25f);
-      const AT vvv = from_f<AT>(dv[e]);
-      dQKV[r * 3 * D + D + h * 16 + e] = kvv;
-      dQKV[r * 3 * D + 2 * D + h * 16 + e] = vvv;
-      T[(int64_t)(D + h * 16 + e) * ldT + r] = kvv;
-      T[(int64_t)(2 * D + h * 16 + e) * ldT + r] = vvv;
-    }
-  }
-}
-
 // ---------------------------------------------------------------- embedding
 // dP[t][k] += sum_b dX0[b*N + t][dt + k]: one thread per (t, k), samples summed in order.
 __global__ void pos_grad_kernel(const float* __restrict__ dX, int nsamp, int N, int D, int dt,
@@ -501,40 +366,32 @@ static hipError_t backward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp
   const int64_t rows = (int64_t)nsamp * N;
   const int rgrid = (int)((rows + 63) / 64);
   float* G = m->grads;
-  hipError_t err = forward_chunk(m, spins, nsamp, nullptr, false, s);
+  hipError_t err = forward_chunk(m, spins, nsamp, nullptr, true, s);
   if (err != hipSuccess) return err;
 
   // head
   hipLaunchKernelGGL((head_bwd_kernel<D>), dim3(nsamp), dim3(256), 0, s,
                      (const float*)(f.X + (size_t)L * f.rows * D), m->params, m->po.head_w, m->po.head_b, spins, w, N,
                      f.dX, f.colpart);
-  hipLaunchKernelGGL(colsum_add_kernel, dim3(1), dim3(256), 0, s, (const float*)f.colpart, nsamp, 2 * D + 2,
-                     G + m->po.head_w);
+  colsum_add(f.colpart, nsamp, 2 * D + 2, f.colpart2, G + m->po.head_w, s);
 
   for (int l = L - 1; l >= 0; --l) {
     const float* lp = m->params + m->po.layer0 + (int64_t)l * m->po.layer_stride;
     float* gl = G + m->po.layer0 + (int64_t)l * m->po.layer_stride;
     const char* wl = reinterpret_cast<const char*>(m->wpack) + (size_t)l * m->pk.layer_stride;
     const float* X = f.X + (size_t)l * f.rows * D;
-    // ---- recompute the layer's forward
-    hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(rgrid), dim3(256), 0, s, X, rows, lp + m->po.ln1_g,
-                       lp + m->po.ln1_b, (AT*)f.A, (AT*)nullptr, (int64_t)0);
-    EpiArgs e{};
-    e.bias = lp + m->po.qkv_b;
-    e.out = f.QKV;
-    if ((err = gemm_rows<MODE, D, 3 * D, EPI_STORE_KV>((const AT*)f.A, rows, wl + m->pk.qkv, e, s))) return err;
-    hipLaunchKernelGGL((attn_fwd_kernel<KT>), dim3((N + 63) / 64, (H + 3) / 4, nsamp), dim3(256), 0, s,
-                       (const KT*)f.QKV, X, f.O, f.XM, f.LSE, N, D, H, c.window, m->kg.P);
-    hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(rgrid), dim3(256), 0, s, (const float*)f.XM, rows,
-                       lp + m->po.ln2_g, lp + m->po.ln2_b, (AT*)f.A, (AT*)f.T_c, f.ldT);
+    const float* XM = f.XM + (size_t)l * f.rows * D;
+    const KT* QKV = reinterpret_cast<const KT*>(f.QKV) + (size_t)l * f.rows * 3 * D;
+    const float* LSE = f.LSE + (size_t)l * f.rows * H;
+    // ---- FFN: recompute LN2 and the pre-activation, then differentiate
+    hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(rgrid), dim3(256), 0, s, XM, rows, lp + m->po.ln2_g,
+                       lp + m->po.ln2_b, (AT*)f.A, (AT*)f.T_c, f.ldT);
     EpiArgs e1{};
     e1.bias = lp + m->po.ffn1_b;
-    e1.out = f.HID;
     e1.hpre_out = f.HPRE;
     e1.outT = f.T_b;
     e1.ldT = f.ldT;
     if ((err = gemm_rows<MODE, D, 4 * D, EPI_GELU>((const AT*)f.A, rows, wl + m->pk.ffn1, e1, s))) return err;
-    // ---- FFN backward
     hipLaunchKernelGGL((transpose_cast_kernel<D, AT>), dim3(rgrid), dim3(256), 0, s, (const float*)f.dX, rows,
                        (AT*)f.DY, (AT*)f.T_a, f.ldT);
     if ((err = wgrad<MODE>(m, f.T_a, D, f.T_b, 4 * D, rows, gl + m->po.ffn2_w, gl + m->po.ffn2_b, s))) return err;
@@ -548,17 +405,17 @@ static hipError_t backward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp
     EpiArgs e3{};
     e3.out = f.TMP;
     if ((err = gemm_rows<MODE, 4 * D, D, EPI_F32>((const AT*)f.dH, rows, wl + m->pk.ffn1T, e3, s))) return err;
-    hipLaunchKernelGGL((ln_bwd_kernel<D>), dim3(rgrid), dim3(256), 0, s, (const float*)f.TMP, (const float*)f.XM,
-                       lp + m->po.ln2_g, (const float*)f.dX, rows, f.dXM, f.colpart);
-    hipLaunchKernelGGL(colsum_add_kernel, dim3((2 * D + 255) / 256), dim3(256), 0, s, (const float*)f.colpart, rgrid,
-                       2 * D, gl + m->po.ln2_g);
-    // ---- attention backward (dO = dXM: the heads' output is added to the residual directly)
-    hipLaunchKernelGGL((attn_bwd_dq_kernel<KT, AT>), dim3((N + 63) / 64, (H + 3) / 4, nsamp), dim3(256), 0, s,
-                       (const KT*)f.QKV, (const float*)f.O, (const float*)f.dXM, (const float*)f.LSE, f.DELTA,
-                       (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window, m->kg.P);
-    hipLaunchKernelGGL((attn_bwd_dkv_kernel<KT, AT>), dim3((N + 63) / 64, (H + 3) / 4, nsamp), dim3(256), 0, s,
-                       (const KT*)f.QKV, (const float*)f.dXM, (const float*)f.LSE, (const float*)f.DELTA,
-                       (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window, m->kg.P);
+    hipLaunchKernelGGL((ln_bwd_kernel<D>), dim3(rgrid), dim3(256), 0, s, (const float*)f.TMP, XM, lp + m->po.ln2_g,
+                       (const float*)f.dX, rows, f.dXM, f.colpart);
+    colsum_add(f.colpart, rgrid, 2 * D, f.colpart2, gl + m->po.ln2_g, s);
+    // ---- attention backward (dO = dXM: the heads' output is added to the residual directly);
+    // probabilities are recomputed from Q, K and the saved log-sum-exp
+    hipLaunchKernelGGL((attn_bwd_dq_mfma<KT, AT, MODE == 1>), dim3((N + 63) / 64, H, nsamp), dim3(256), 0, s, QKV, X,
+                       XM, (const float*)f.dXM, LSE, f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window,
+                       m->kg.P);
+    hipLaunchKernelGGL((attn_bwd_dkv_mfma<KT, AT, MODE == 1>), dim3((N + 63) / 64, H, nsamp), dim3(256), 0, s, QKV,
+                       (const float*)f.dXM, LSE, (const float*)f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H,
+                       c.window, m->kg.P);
     // ---- QKV backward
     hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(rgrid), dim3(256), 0, s, X, rows, lp + m->po.ln1_g,
                        lp + m->po.ln1_b, (AT*)nullptr, (AT*)f.T_c, f.ldT);
@@ -568,8 +425,7 @@ static hipError_t backward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp
     if ((err = gemm_rows<MODE, 3 * D, D, EPI_F32>((const AT*)f.dQKV, rows, wl + m->pk.qkvT, e4, s))) return err;
     hipLaunchKernelGGL((ln_bwd_kernel<D>), dim3(rgrid), dim3(256), 0, s, (const float*)f.TMP, X, lp + m->po.ln1_g,
                        (const float*)f.dXM, rows, f.dX, f.colpart);
-    hipLaunchKernelGGL(colsum_add_kernel, dim3((2 * D + 255) / 256), dim3(256), 0, s, (const float*)f.colpart, rgrid,
-                       2 * D, gl + m->po.ln1_g);
+    colsum_add(f.colpart, rgrid, 2 * D, f.colpart2, gl + m->po.ln1_g, s);
   }
   // embeddings
   const int64_t npos = (int64_t)N * (D - c.d_token);

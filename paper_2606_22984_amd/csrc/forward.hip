@@ -13,6 +13,7 @@
 #include "fvan_model.h"
 #include "passes.h"
 #include "row_kernels.h"
+#include "attn_mfma.h"
 
 namespace fvan {
 
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(256) void head_fwd_kernel(const float* __restrict__
 
 // ---------------------------------------------------------------- drivers
 template <int MODE, int D>
-hipError_t forward_layer(fvan_model* m, int l, int64_t rows, int nsamp, bool for_backward, hipStream_t s) {
+hipError_t forward_layer(fvan_model* m, int l, int64_t rows, int nsamp, hipStream_t s) {
   typedef typename Mode<MODE>::ActT AT;
   typedef typename Mode<MODE>::KvT KT;
   const fvan_model_config& c = m->cfg;
@@ -84,28 +85,30 @@ hipError_t forward_layer(fvan_model* m, int l, int64_t rows, int nsamp, bool for
   const char* wl = reinterpret_cast<const char*>(m->wpack) + (size_t)l * m->pk.layer_stride;
   const float* X = f.X + (size_t)l * f.rows * D;
   float* Xn = f.X + (size_t)(l + 1) * f.rows * D;
+  float* XM = f.XM + (size_t)l * f.rows * D;
+  KT* QKV = reinterpret_cast<KT*>(f.QKV) + (size_t)l * f.rows * 3 * D;
+  float* LSE = f.LSE + (size_t)l * f.rows * c.n_heads;
   const int lgrid = (int)((rows + 63) / 64);
   hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(lgrid), dim3(256), 0, s, X, rows, lp + m->po.ln1_g,
                      lp + m->po.ln1_b, (AT*)f.A, (AT*)nullptr, (int64_t)0);
   EpiArgs e{};
   e.bias = lp + m->po.qkv_b;
-  e.out = f.QKV;
+  e.out = QKV;
   hipError_t err = gemm_rows<MODE, D, 3 * D, EPI_STORE_KV>((const AT*)f.A, rows, wl + m->pk.qkv, e, s);
   if (err != hipSuccess) return err;
   const int H = c.n_heads;
-  hipLaunchKernelGGL((attn_fwd_kernel<KT>), dim3((c.n_spins + 63) / 64, (H + 3) / 4, nsamp), dim3(256), 0, s,
-                     (const KT*)f.QKV, X, f.O, f.XM, f.LSE, c.n_spins, D, H, c.window, m->kg.P);
-  hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(lgrid), dim3(256), 0, s, (const float*)f.XM, rows,
+  hipLaunchKernelGGL((attn_fwd_mfma<KT, MODE == 1>), dim3((c.n_spins + 63) / 64, H, nsamp), dim3(256), 0, s,
+                     (const KT*)QKV, X, XM, LSE, c.n_spins, D, H, c.window, m->kg.P);
+  hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(lgrid), dim3(256), 0, s, (const float*)XM, rows,
                      lp + m->po.ln2_g, lp + m->po.ln2_b, (AT*)f.A, (AT*)nullptr, (int64_t)0);
   EpiArgs e1{};
   e1.bias = lp + m->po.ffn1_b;
   e1.out = f.HID;
-  e1.hpre_out = for_backward ? f.HPRE : nullptr;
   err = gemm_rows<MODE, D, 4 * D, EPI_GELU>((const AT*)f.A, rows, wl + m->pk.ffn1, e1, s);
   if (err != hipSuccess) return err;
   EpiArgs e2{};
   e2.bias = lp + m->po.ffn2_b;
-  e2.resid = f.XM;
+  e2.resid = XM;
   e2.out = Xn;
   return gemm_rows<MODE, 4 * D, D, EPI_RESID>((const AT*)f.HID, rows, wl + m->pk.ffn2, e2, s);
 }
@@ -119,7 +122,7 @@ static hipError_t forward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp,
   hipLaunchKernelGGL(embed_kernel, dim3(grid), dim3(256), 0, s, m->params, m->po.pos, c.d_token, D, c.n_spins,
                      spins, rows, m->fw.X);
   for (int l = 0; l < c.n_layers; ++l) {
-    hipError_t e = forward_layer<MODE, D>(m, l, rows, nsamp, for_backward, s);
+    hipError_t e = forward_layer<MODE, D>(m, l, rows, nsamp, s);
     if (e != hipSuccess) return e;
   }
   if (logq) {

@@ -38,7 +38,7 @@ template <int MODE> struct Epi<MODE, EPI_GELU> {
     const float h = v + e.bias[n];
     if (e.hpre_out) e.hpre_out[r * nout + n] = h;
     const float g = gelu(h);
-    reinterpret_cast<AT*>(e.out)[r * nout + n] = from_f<AT>(g);
+    if (e.out) reinterpret_cast<AT*>(e.out)[r * nout + n] = from_f<AT>(g);
     if (e.outT) reinterpret_cast<AT*>(e.outT)[(int64_t)n * e.ldT + r] = from_f<AT>(g);
   }
 };
@@ -61,8 +61,10 @@ template <int MODE> struct Epi<MODE, EPI_F32> {
   }
 };
 
-// Teacher-forced forward of one chunk of samples (rows = nsamp * N).  Saves the
-// layer inputs in fw.X; with for_backward also the FFN pre-activations.
+// Teacher-forced forward of one chunk of samples (rows = nsamp * N).  Saves, per
+// layer, the input X, Q/K/V, the post-attention residual XM and the attention
+// log-sum-exp (what the backward pass reads; attention probabilities are never
+// stored).
 // logq (may be NULL): per-sample ln q.
 hipError_t forward_chunk(fvan_model* m, const int8_t* spins, int nsamp, float* logq, bool for_backward,
                          hipStream_t s);

@@ -1,6 +1,6 @@
 // Row-parallel kernels shared by the teacher-forced forward and the backward
 // pass (which recomputes each layer's forward): LayerNorm, the row GEMM on
-// packed weights with fused epilogues, and band+prefix masked attention.
+// packed weights with fused epilogues.
 #pragma once
 
 #include <algorithm>
@@ -92,85 +92,6 @@ inline hipError_t gemm_rows(const typename Mode<MODE>::ActT* A, int64_t rows, co
   hipLaunchKernelGGL((gemm_rows_kernel<MODE, K, NOUT, EPI>), dim3(grid), dim3(256), 0, s, A, rows,
                      reinterpret_cast<const uint4*>(pack), e);
   return hipGetLastError();
-}
-
-// ---------------------------------------------------------------- attention
-// One workgroup = (sample, 64 query positions, 4 heads); thread = (query, head).
-// K/V blocks of 64 positions are staged in LDS as floats; the visible set of a
-// query tile is the prefix [0, min(P, t1)) plus the band [max(P, t0 - W), t1).
-template <typename KT>
-__global__ __launch_bounds__(256) void attn_fwd_kernel(const KT* __restrict__ QKV, const float* __restrict__ X,
-                                                       float* __restrict__ O, float* __restrict__ XM,
-                                                       float* __restrict__ LSE, int N, int D, int H, int W, int P) {
-  __shared__ float Ks[64][4][17];
-  __shared__ float Vs[64][4][17];
-  const int qi = threadIdx.x & 63, hl = threadIdx.x >> 6;
-  const int t0 = blockIdx.x * 64, h0 = blockIdx.y * 4, b = blockIdx.z;
-  const int h = h0 + hl, t = t0 + qi;
-  const bool active = t < N && h < H;
-  const int t1 = std::min(t0 + 64, N);
-  const int64_t rowbase = (int64_t)b * N;
-  constexpr float kScaleLog2 = 0.25f * 1.4426950408889634f;
-  float q[16], o[16];
-  float mx = -INFINITY, l = 0.f;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) { o[e] = 0.f; q[e] = 0.f; }
-  if (active) {
-    const KT* qp = QKV + (rowbase + t) * 3 * D + h * 16;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) q[e] = to_f(qp[e]) * kScaleLog2;
-  }
-  const int pend = std::min(P, t1);
-  const int bstart = std::max(P, t0 - W);
-  // two key ranges: [0, pend) and [bstart, t1)
-  for (int range = 0; range < 2; ++range) {
-    const int ks = range == 0 ? 0 : bstart;
-    const int ke = range == 0 ? pend : t1;
-    for (int j0 = ks; j0 < ke; j0 += 64) {
-      __syncthreads();
-      for (int i = threadIdx.x; i < 64 * 4 * 16; i += 256) {
-        const int jj = i >> 6, hh = (i >> 4) & 3, e = i & 15;
-        const int j = j0 + jj;
-        float kv = 0.f, vv = 0.f;
-        if (j < ke && h0 + hh < H) {
-          const KT* kp = QKV + (rowbase + j) * 3 * D + D + (h0 + hh) * 16 + e;
-          kv = to_f(kp[0]);
-          vv = to_f(kp[D]);
-        }
-        Ks[jj][hh][e] = kv;
-        Vs[jj][hh][e] = vv;
-      }
-      __syncthreads();
-      if (active) {
-        const int jn = std::min(64, ke - j0);
-        for (int jj = 0; jj < jn; ++jj) {
-          const int j = j0 + jj;
-          if (j > t || (t - j > W && j >= P)) continue;
-          float s = 0.f;
-#pragma unroll
-          for (int e = 0; e < 16; ++e) s += q[e] * Ks[jj][hl][e];
-          const float mn = fmaxf(mx, s);
-          const float c = __builtin_amdgcn_exp2f(mx - mn);
-          const float p = __builtin_amdgcn_exp2f(s - mn);
-          l = l * c + p;
-#pragma unroll
-          for (int e = 0; e < 16; ++e) o[e] = o[e] * c + p * Vs[jj][hl][e];
-          mx = mn;
-        }
-      }
-    }
-  }
-  if (active) {
-    const float inv = 1.0f / l;
-    const int64_t r = rowbase + t;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const float ov = o[e] * inv;
-      O[r * D + h * 16 + e] = ov;
-      XM[r * D + h * 16 + e] = X[r * D + h * 16 + e] + ov;
-    }
-    LSE[r * H + h] = mx + __log2f(l);
-  }
 }
 
 }  // namespace fvan
