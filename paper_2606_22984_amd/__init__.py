@@ -321,3 +321,47 @@ class LogProb(torch.autograd.Function):
 
 def log_prob_autograd(model: Model, spins: torch.Tensor) -> torch.Tensor:
     return LogProb.apply(model.params, model, spins)
+
+
+class Group:
+    """Many (model, couplings, beta) units sampled in one persistent launch (fvan_group_*).
+    Keeps references to every tensor the device tables point at."""
+
+    def __init__(self, units, tile_samples: int = 0):
+        self._keep = []
+        arr = (GroupUnitC * len(units))()
+        self.outputs = []
+        for i, u in enumerate(units):
+            model, coup, beta, batch, seed, stream_id = (u["model"], u["couplings"], u["beta"], u["batch"],
+                                                         u["seed"], u["stream_id"])
+            dev = model.params.device
+            spins = torch.empty(batch, model.cfg.n_spins, dtype=torch.int8, device=dev)
+            lq = torch.empty(batch, dtype=torch.float32, device=dev)
+            en = coup.empty_energy(batch, dev)
+            st = torch.zeros(2, dtype=torch.float64, device=dev)
+            self._keep += [spins, lq, en, st, coup, model]
+            self.outputs.append(dict(spins=spins, log_q=lq, energy=en, stats=st))
+            arr[i] = GroupUnitC(model=model.handle, couplings=C.cast(C.pointer(coup.c), C.c_void_p), beta=beta,
+                                batch=batch, seed=seed, stream_id=stream_id, spins=spins.data_ptr(),
+                                log_q=lq.data_ptr(), energy=en.data_ptr(), stats=st.data_ptr())
+        self._arr = arr
+        h = C.c_void_p()
+        _check(lib().fvan_group_create(arr, len(units), tile_samples, C.byref(h)))
+        self.handle = h
+
+    def run(self, stream=None):
+        _check(lib().fvan_group_run(self.handle, _stream(stream)))
+
+    def run_graph(self, stream=None):
+        _check(lib().fvan_group_run_graph(self.handle, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fvan_group_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

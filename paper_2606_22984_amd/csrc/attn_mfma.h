@@ -10,8 +10,10 @@
 // layout dS needs in dQ = dS K; the dK/dV kernel moves P^T and dS^T through a
 // small LDS tile to reach the A layout.
 //
-// Precision: FP32 MFMA (16x16x4, four per tile) for FVAN_FP32 and
-// FVAN_BF16_SPLIT, BF16 MFMA (16x16x16) for FVAN_BF16.
+// Precision of the tile products (mode = fvan_precision): FP32 MFMA
+// (16x16x4, four per tile) for FVAN_FP32, BF16 MFMA (16x16x16) for FVAN_BF16,
+// and for FVAN_BF16_SPLIT three BF16 MFMAs on hi/lo operand splits
+// (lo*hi + hi*lo + hi*hi; the dropped lo*lo term is below 2^-16 relative).
 #pragma once
 
 #include <algorithm>
@@ -22,17 +24,45 @@ namespace fvan {
 
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 
-template <bool BF>
+__device__ __forceinline__ bf16x4 bf4(float a, float b, float c, float d) {
+  bf16x4 v = {(__bf16)a, (__bf16)b, (__bf16)c, (__bf16)d};
+  return v;
+}
+
+template <int MODE>
 __device__ __forceinline__ floatx4 mfma16(const float4& a, const float4& b, floatx4 acc) {
-  if constexpr (BF) {
-    bf16x4 av = {(__bf16)a.x, (__bf16)a.y, (__bf16)a.z, (__bf16)a.w};
-    bf16x4 bv = {(__bf16)b.x, (__bf16)b.y, (__bf16)b.z, (__bf16)b.w};
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+  if constexpr (MODE == 1) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bf4(a.x, a.y, a.z, a.w), bf4(b.x, b.y, b.z, b.w), acc, 0, 0, 0);
+  } else if constexpr (MODE == 2) {
+    const bf16x4 ah = bf4(a.x, a.y, a.z, a.w), bh = bf4(b.x, b.y, b.z, b.w);
+    const bf16x4 al = bf4(a.x - (float)ah[0], a.y - (float)ah[1], a.z - (float)ah[2], a.w - (float)ah[3]);
+    const bf16x4 bl = bf4(b.x - (float)bh[0], b.y - (float)bh[1], b.z - (float)bh[2], b.w - (float)bh[3]);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
   } else {
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
+  }
+}
+
+// 16 consecutive elements (one head's slice of a row) as floats.
+template <typename T>
+__device__ __forceinline__ void load16(const T* p, float* out) {
+  Chunk<T> a, b;
+  a.unpack(*reinterpret_cast<const uint4*>(p));
+  b.unpack(*reinterpret_cast<const uint4*>(p + 8));
+#pragma unroll
+  for (int i = 0; i < 8; ++i) { out[i] = a.v[i]; out[8 + i] = b.v[i]; }
+}
+template <>
+__device__ __forceinline__ void load16<float>(const float* p, float* out) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float4 t = reinterpret_cast<const float4*>(p)[i];
+    out[4 * i] = t.x; out[4 * i + 1] = t.y; out[4 * i + 2] = t.z; out[4 * i + 3] = t.w;
   }
 }
 
@@ -68,7 +98,7 @@ struct KeyRange {
 // ---------------------------------------------------------------- forward
 // One workgroup = (64 queries, head, sample); wave w owns queries t0+16w..+15.
 // Writes XM = X + O, and LSE (log2 units).
-template <typename KT, bool BF>
+template <typename KT, int MODE>
 __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV, const float* __restrict__ X,
                                                      float* __restrict__ XM, float* __restrict__ LSE, int N, int D,
                                                      int H, int W, int P) {
@@ -91,16 +121,18 @@ __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV,
   for (int v0 = 0; v0 < kr.nk; v0 += kKeyChunk) {
     const int nv = min(kKeyChunk, kr.nk - v0);
     __syncthreads();
-    for (int x = threadIdx.x; x < kKeyChunk * 16; x += 256) {
-      const int kk = x >> 4, d = x & 15;
-      float kv = 0.f, vv = 0.f;
+    for (int kk = threadIdx.x; kk < kKeyChunk; kk += 256) {
+      float kv[16], vv[16];
       if (kk < nv) {
-        const KT* kp = QKV + (rowbase + kr.pos(v0 + kk)) * 3 * D + D + h * 16 + d;
-        kv = to_f(kp[0]);
-        vv = to_f(kp[D]);
+        const KT* kp = QKV + (rowbase + kr.pos(v0 + kk)) * 3 * D + D + h * 16;
+        load16(kp, kv);
+        load16(kp + D, vv);
+      } else {
+#pragma unroll
+        for (int d = 0; d < 16; ++d) { kv[d] = 0.f; vv[d] = 0.f; }
       }
-      Ks[kk][d] = kv;
-      VsT[d][kk] = vv;
+#pragma unroll
+      for (int d = 0; d < 16; ++d) { Ks[kk][d] = kv[d]; VsT[d][kk] = vv[d]; }
     }
     __syncthreads();
     for (int kt0 = 0; kt0 < nv; kt0 += 64) {         // 4 key tiles of 16 per softmax update
@@ -110,7 +142,7 @@ __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV,
       for (int u = 0; u < 4; ++u) {
         const int kb = kt0 + 16 * u;
         floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-        if (kb < nv) acc = mfma16<BF>(load4(&Ks[kb + c][4 * g]), q4, acc);
+        if (kb < nv) acc = mfma16<MODE>(load4(&Ks[kb + c][4 * g]), q4, acc);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int kv = kb + 4 * g + i;
@@ -139,7 +171,7 @@ __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV,
       for (int u = 0; u < 4; ++u) {
         const int kb = kt0 + 16 * u;
         if (kb < nv)
-          o = mfma16<BF>(load4(&VsT[c][kb + 4 * g]), make_float4(s[4 * u], s[4 * u + 1], s[4 * u + 2], s[4 * u + 3]), o);
+          o = mfma16<MODE>(load4(&VsT[c][kb + 4 * g]), make_float4(s[4 * u], s[4 * u + 1], s[4 * u + 2], s[4 * u + 3]), o);
       }
     }
   }
@@ -157,7 +189,7 @@ __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV,
 // ---------------------------------------------------------------- backward: dQ
 // One workgroup = (64 queries, head, sample).  O is recovered as XM - X.
 // Writes DELTA = dO . O, dQ (scaled) into dQKV and the feature-major copy T.
-template <typename KT, typename AT, bool BF>
+template <typename KT, typename AT, int MODE>
 __global__ __launch_bounds__(256) void attn_bwd_dq_mfma(const KT* __restrict__ QKV, const float* __restrict__ X,
                                                         const float* __restrict__ XM, const float* __restrict__ dO,
                                                         const float* __restrict__ LSE, float* __restrict__ DELTA,
@@ -192,23 +224,24 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_mfma(const KT* __restrict__ Q
   for (int v0 = 0; v0 < kr.nk; v0 += kKeyChunk) {
     const int nv = min(kKeyChunk, kr.nk - v0);
     __syncthreads();
-    for (int x = threadIdx.x; x < kKeyChunk * 16; x += 256) {
-      const int kk = x >> 4, d = x & 15;
-      float kv = 0.f, vv = 0.f;
+    for (int kk = threadIdx.x; kk < kKeyChunk; kk += 256) {
+      float kv[16], vv[16];
       if (kk < nv) {
-        const KT* kp = QKV + (rowbase + kr.pos(v0 + kk)) * 3 * D + D + h * 16 + d;
-        kv = to_f(kp[0]);
-        vv = to_f(kp[D]);
+        const KT* kp = QKV + (rowbase + kr.pos(v0 + kk)) * 3 * D + D + h * 16;
+        load16(kp, kv);
+        load16(kp + D, vv);
+      } else {
+#pragma unroll
+        for (int d = 0; d < 16; ++d) { kv[d] = 0.f; vv[d] = 0.f; }
       }
-      Ks[kk][d] = kv;
-      KsT[d][kk] = kv;
-      Vs[kk][d] = vv;
+#pragma unroll
+      for (int d = 0; d < 16; ++d) { Ks[kk][d] = kv[d]; KsT[d][kk] = kv[d]; Vs[kk][d] = vv[d]; }
     }
     __syncthreads();
     for (int kb = 0; kb < nv; kb += 16) {
       floatx4 sa = {0.f, 0.f, 0.f, 0.f}, pa = {0.f, 0.f, 0.f, 0.f};
-      sa = mfma16<BF>(load4(&Ks[kb + c][4 * g]), q4, sa);     // S^T[key 4g+i][query c]
-      pa = mfma16<BF>(load4(&Vs[kb + c][4 * g]), g4, pa);     // dP^T[key 4g+i][query c]
+      sa = mfma16<MODE>(load4(&Ks[kb + c][4 * g]), q4, sa);     // S^T[key 4g+i][query c]
+      pa = mfma16<MODE>(load4(&Vs[kb + c][4 * g]), g4, pa);     // dP^T[key 4g+i][query c]
       float ds[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -218,7 +251,7 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_mfma(const KT* __restrict__ Q
         ds[i] = p * (pa[i] - delta);
       }
       // dQ[query][dim] += dS[query][key] K[key][dim]; lane's dS = A layout of dS
-      dq = mfma16<BF>(make_float4(ds[0], ds[1], ds[2], ds[3]), load4(&KsT[c][kb + 4 * g]), dq);
+      dq = mfma16<MODE>(make_float4(ds[0], ds[1], ds[2], ds[3]), load4(&KsT[c][kb + 4 * g]), dq);
     }
   }
   // dq[i] = dQ[query 16w + 4g + i][dim c]
@@ -237,17 +270,18 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_mfma(const KT* __restrict__ Q
 // ---------------------------------------------------------------- backward: dK, dV
 // One workgroup = (64 keys, head, sample); wave w owns keys j0+16w..+15 and loops
 // over the query blocks that can see the tile ([j0, j1 + W), or [j0, N) when the
-// tile holds prefix keys).
-template <typename KT, typename AT, bool BF>
+// tile holds prefix keys).  Query rows are staged with 16-byte loads; the
+// B operands of dV and dK (four queries of one dimension) are gathered from the
+// row-major stage.
+template <typename KT, typename AT, int MODE>
 __global__ __launch_bounds__(256) void attn_bwd_dkv_mfma(const KT* __restrict__ QKV, const float* __restrict__ dO,
                                                          const float* __restrict__ LSE, const float* __restrict__ DELTA,
                                                          AT* __restrict__ dQKV, AT* __restrict__ T, int64_t ldT, int N,
                                                          int D, int H, int W, int P) {
-  __shared__ float Qs[64][20];
-  __shared__ float QsT[16][68];
-  __shared__ float Gs[64][20];
-  __shared__ float GsT[16][68];
-  __shared__ float Ls[64], Ds[64];
+  constexpr int QB = 64;
+  __shared__ float Qs[QB][20];
+  __shared__ float Gs[QB][20];
+  __shared__ float Ls[QB], Ds[QB];
   __shared__ float Tr[4][16][17];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
   const int j0 = blockIdx.x * 64, h = blockIdx.y, b = blockIdx.z;
@@ -264,33 +298,34 @@ __global__ __launch_bounds__(256) void attn_bwd_dkv_mfma(const KT* __restrict__ 
   }
   const int qend = j0 < P ? N : min(N, j1 + W);
   floatx4 dk = {0.f, 0.f, 0.f, 0.f}, dv = {0.f, 0.f, 0.f, 0.f};   // [key 16w+4g+i][dim c]
-  for (int i0 = j0; i0 < qend; i0 += 64) {
-    const int nq = min(64, qend - i0);
+  for (int i0 = j0; i0 < qend; i0 += QB) {
+    const int nq = min(QB, qend - i0);
     __syncthreads();
-    for (int x = threadIdx.x; x < 64 * 16; x += 256) {
-      const int qq = x >> 4, d = x & 15;
-      float qv = 0.f, gv = 0.f;
-      if (qq < nq) {
-        const int64_t ri = rowbase + i0 + qq;
-        qv = to_f(QKV[ri * 3 * D + h * 16 + d]);
-        gv = dO[ri * D + h * 16 + d];
-      }
-      Qs[qq][d] = qv;
-      QsT[d][qq] = qv;
-      Gs[qq][d] = gv;
-      GsT[d][qq] = gv;
-    }
-    if (threadIdx.x < 64) {
-      const int qq = threadIdx.x;
+    {
+      // threads 0..63 stage Q rows, 64..127 dO rows, 128..191 LSE and DELTA
+      const int qq = threadIdx.x & 63, role = threadIdx.x >> 6;
       const bool ok = qq < nq;
-      Ls[qq] = ok ? LSE[(rowbase + i0 + qq) * H + h] : 0.f;
-      Ds[qq] = ok ? DELTA[(rowbase + i0 + qq) * H + h] : 0.f;
+      const int64_t ri = rowbase + i0 + qq;
+      if (role == 0) {
+        float v[16];
+        if (ok) load16(QKV + ri * 3 * D + h * 16, v);
+#pragma unroll
+        for (int d = 0; d < 16; ++d) Qs[qq][d] = ok ? v[d] : 0.f;
+      } else if (role == 1) {
+        float v[16];
+        if (ok) load16(dO + ri * D + h * 16, v);
+#pragma unroll
+        for (int d = 0; d < 16; ++d) Gs[qq][d] = ok ? v[d] : 0.f;
+      } else if (role == 2) {
+        Ls[qq] = ok ? LSE[ri * H + h] : 0.f;
+        Ds[qq] = ok ? DELTA[ri * H + h] : 0.f;
+      }
     }
     __syncthreads();
     for (int qb = 0; qb < nq; qb += 16) {
       floatx4 sa = {0.f, 0.f, 0.f, 0.f}, pa = {0.f, 0.f, 0.f, 0.f};
-      sa = mfma16<BF>(k4, load4(&Qs[qb + c][4 * g]), sa);   // S^T[key 4g+i][query c]
-      pa = mfma16<BF>(v4, load4(&Gs[qb + c][4 * g]), pa);   // dP^T[key 4g+i][query c]
+      sa = mfma16<MODE>(k4, *reinterpret_cast<const float4*>(&Qs[qb + c][4 * g]), sa);   // S^T[key 4g+i][query c]
+      pa = mfma16<MODE>(v4, *reinterpret_cast<const float4*>(&Gs[qb + c][4 * g]), pa);   // dP^T[key 4g+i][query c]
       const int iq = i0 + qb + c;
       float p[4], ds[4];
 #pragma unroll
@@ -313,8 +348,11 @@ __global__ __launch_bounds__(256) void attn_bwd_dkv_mfma(const KT* __restrict__ 
       const float4 dst = make_float4(Tr[wave][c][4 * g], Tr[wave][c][4 * g + 1], Tr[wave][c][4 * g + 2],
                                      Tr[wave][c][4 * g + 3]);
       wave_sync();
-      dv = mfma16<BF>(pt, load4(&GsT[c][qb + 4 * g]), dv);    // dV[key][dim] += P^T[key][q] dO[q][dim]
-      dk = mfma16<BF>(dst, load4(&QsT[c][qb + 4 * g]), dk);   // dK[key][dim] += dS^T[key][q] Q[q][dim]
+      const int qr = qb + 4 * g;
+      const float4 go = make_float4(Gs[qr][c], Gs[qr + 1][c], Gs[qr + 2][c], Gs[qr + 3][c]);
+      const float4 qo = make_float4(Qs[qr][c], Qs[qr + 1][c], Qs[qr + 2][c], Qs[qr + 3][c]);
+      dv = mfma16<MODE>(pt, go, dv);    // dV[key][dim] += P^T[key][q] dO[q][dim]
+      dk = mfma16<MODE>(dst, qo, dk);   // dK[key][dim] += dS^T[key][q] Q[q][dim]
     }
   }
 #pragma unroll

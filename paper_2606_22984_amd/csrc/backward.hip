@@ -166,60 +166,92 @@ __global__ __launch_bounds__(256) void transpose_cast_kernel(const float* __rest
 }
 
 // ---------------------------------------------------------------- weight-gradient GEMM
-// part[s][m][n] = sum_{k in split s, k < K} A[m][k] B[n][k]; A [M x lda], B [NB x ldb]
-// feature-major, K = rows of the chunk.  64 x 64 output tile per workgroup,
-// one wave per 16 rows of the tile.
-template <int MODE>
-__global__ __launch_bounds__(256) void wgrad_kernel(const typename Mode<MODE>::ActT* __restrict__ A, int64_t lda,
+// part[s][m][n] = sum_{k in slice s, k < K} A[m][k] B[n][k]; A [M x lda] and
+// B [NB x ldb] feature-major, K = rows of the chunk.  One workgroup (8 waves)
+// owns the whole M x NB output for its K slice, so each operand element is read
+// from HBM once; K chunks are staged in LDS and every wave keeps a block of
+// RT x CT accumulator tiles (rows split over WRG wave groups, columns over WCG).
+template <int MT>
+struct WaveGrid {
+  static constexpr int WRG = (MT % 8 == 0) ? 8 : (MT % 4 == 0) ? 4 : (MT % 2 == 0) ? 2 : 1;
+  static constexpr int WCG = 8 / WRG;
+  static constexpr int RT = MT / WRG;
+};
+
+template <int MODE, int M, int NB>
+__global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::ActT* __restrict__ A, int64_t lda,
                                                     const typename Mode<MODE>::ActT* __restrict__ B, int64_t ldb,
-                                                    int M, int NB, int64_t K, int64_t kper, float* __restrict__ part) {
+                                                    int64_t K, int64_t kper, float* __restrict__ part) {
   typedef typename Mode<MODE>::ActT AT;
   constexpr int KC = Mode<MODE>::KC;
   constexpr int LK = KC / 4;
+  constexpr int PADK = KC + 16 / (int)sizeof(AT);
+  constexpr int MT = M / 16, NT = NB / 16;
+  typedef WaveGrid<MT> G;
+  constexpr int RT = G::RT, WCG = G::WCG;
+  constexpr int CT = (NT + WCG - 1) / WCG;
+  constexpr int VPL = 16 / (int)sizeof(AT);        // elements per 16-byte load
+  __shared__ __attribute__((aligned(16))) AT As[M][PADK];
+  __shared__ __attribute__((aligned(16))) AT Bs[NB][PADK];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int m0 = blockIdx.y * 64 + wave * 16;
-  const int n0 = blockIdx.x * 64;
-  const int s = blockIdx.z;
-  if (m0 >= M) return;
+  const int wr = wave / WCG, wc = wave % WCG;
+  const int s = blockIdx.x;
   const int64_t kb = (int64_t)s * kper;
   const int64_t ke = std::min<int64_t>(K, kb + kper);
-  floatx4 acc[4];
+  floatx4 acc[RT][CT];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const AT* arow = A + (int64_t)(m0 + (lane & 15)) * lda + (lane >> 4) * LK;
-  const int nsub = std::min(4, (NB - n0) / 16);
-  int64_t k = kb;
-  for (; k + KC <= ke; k += KC) {
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (j < nsub) {
-        const AT* brow = B + (int64_t)(n0 + 16 * j + (lane & 15)) * ldb + (lane >> 4) * LK;
-        acc[j] = FragAB<MODE>::step(arow + k, brow + k, acc[j]);
+    for (int j = 0; j < CT; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t k = kb; k < ke; k += KC) {
+    const bool full = k + KC <= ke;
+    // stage A[:, k:k+KC] and B[:, k:k+KC]
+    for (int x = threadIdx.x; x < (M + NB) * (KC / VPL); x += 512) {
+      const int row = x / (KC / VPL), piece = x % (KC / VPL);
+      const bool isA = row < M;
+      const AT* src = isA ? A + (int64_t)row * lda : B + (int64_t)(row - M) * ldb;
+      AT* dst = isA ? &As[row][piece * VPL] : &Bs[row - M][piece * VPL];
+      const int64_t kk = k + piece * VPL;
+      if (full) {
+        *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src + kk);
+      } else {
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) dst[i] = kk + i < ke ? src[kk + i] : from_f<AT>(0.f);
       }
     }
-  }
-  if (k < ke) {   // ragged tail of the row range: zero-fill past ke
-    alignas(16) AT av[LK], bv[LK];
-    const int64_t k0 = k + (lane >> 4) * LK;
+    __syncthreads();
+    alignas(16) AT af[RT][LK];
 #pragma unroll
-    for (int i = 0; i < LK; ++i) av[i] = k0 + i < ke ? arow[k + i] : from_f<AT>(0.f);
+    for (int i = 0; i < RT; ++i) {
+      const AT* ap = &As[(wr * RT + i) * 16 + (lane & 15)][(lane >> 4) * LK];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (j < nsub) {
-        const AT* brow = B + (int64_t)(n0 + 16 * j + (lane & 15)) * ldb + (lane >> 4) * LK;
+      for (int e = 0; e < LK; e += VPL) *reinterpret_cast<uint4*>(&af[i][e]) = *reinterpret_cast<const uint4*>(ap + e);
+    }
 #pragma unroll
-        for (int i = 0; i < LK; ++i) bv[i] = k0 + i < ke ? brow[k + i] : from_f<AT>(0.f);
-        acc[j] = FragAB<MODE>::step(av, bv, acc[j]);
+    for (int j = 0; j < CT; ++j) {
+      const int ct = wc * CT + j;
+      if (ct < NT) {
+        alignas(16) AT bf[LK];
+        const AT* bp = &Bs[ct * 16 + (lane & 15)][(lane >> 4) * LK];
+#pragma unroll
+        for (int e = 0; e < LK; e += VPL) *reinterpret_cast<uint4*>(&bf[e]) = *reinterpret_cast<const uint4*>(bp + e);
+#pragma unroll
+        for (int i = 0; i < RT; ++i) acc[i][j] = FragAB<MODE>::step(af[i], bf, acc[i][j]);
       }
     }
+    __syncthreads();
   }
   float* out = part + (size_t)s * M * NB;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    if (j < nsub) {
-      const int n = n0 + 16 * j + (lane & 15);
+  for (int i = 0; i < RT; ++i) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) out[(size_t)(m0 + 4 * (lane >> 4) + i) * NB + n] = acc[j][i];
+    for (int j = 0; j < CT; ++j) {
+      const int ct = wc * CT + j;
+      if (ct < NT) {
+        const int n = ct * 16 + (lane & 15);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[(size_t)((wr * RT + i) * 16 + 4 * (lane >> 4) + q) * NB + n] = acc[i][j][q];
+      }
     }
   }
 }
@@ -237,21 +269,19 @@ __global__ void wgrad_reduce_kernel(const float* __restrict__ part, int S, int M
   }
 }
 
-template <int MODE>
-static hipError_t wgrad(fvan_model* m, const void* A, int M, const void* B, int Nw, int64_t K, float* gW, float* gb,
-                        hipStream_t s) {
+template <int MODE, int M, int Nw>
+static hipError_t wgrad(fvan_model* m, const void* A, const void* B, int64_t K, float* gW, float* gb, hipStream_t s) {
   typedef typename Mode<MODE>::ActT AT;
+  constexpr int NB = Nw + 16;
   auto& f = m->fw;
-  const int NB = Nw + 16;
-  const int tiles = ((NB + 63) / 64) * ((M + 63) / 64);
-  int S = std::max(1, std::min<int>(256, 2048 / tiles));
-  S = (int)std::min<int64_t>(S, std::max<int64_t>(1, K / 256));
-  while ((size_t)S * M * NB > f.part_floats) --S;
   const int KC = Mode<MODE>::KC;
+  int S = (int)std::max<int64_t>(1, std::min<int64_t>(512, K / (8 * KC)));
+  while ((size_t)S * M * NB > f.part_floats) --S;
   int64_t kper = (K + S - 1) / S;
   kper = (kper + KC - 1) / KC * KC;
-  hipLaunchKernelGGL((wgrad_kernel<MODE>), dim3((NB + 63) / 64, (M + 63) / 64, S), dim3(256), 0, s,
-                     (const AT*)A, f.ldT, (const AT*)B, f.ldT, M, NB, K, kper, f.part);
+  S = (int)((K + kper - 1) / kper);
+  hipLaunchKernelGGL((wgrad_kernel<MODE, M, NB>), dim3(S), dim3(512), 0, s, (const AT*)A, f.ldT, (const AT*)B, f.ldT,
+                     K, kper, f.part);
   const int total = M * (Nw + 1);
   hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(std::min(1024, (total + 255) / 256)), dim3(256), 0, s,
                      (const float*)f.part, S, M, NB, Nw, gW, gb);
@@ -394,14 +424,14 @@ static hipError_t backward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp
     if ((err = gemm_rows<MODE, D, 4 * D, EPI_GELU>((const AT*)f.A, rows, wl + m->pk.ffn1, e1, s))) return err;
     hipLaunchKernelGGL((transpose_cast_kernel<D, AT>), dim3(rgrid), dim3(256), 0, s, (const float*)f.dX, rows,
                        (AT*)f.DY, (AT*)f.T_a, f.ldT);
-    if ((err = wgrad<MODE>(m, f.T_a, D, f.T_b, 4 * D, rows, gl + m->po.ffn2_w, gl + m->po.ffn2_b, s))) return err;
+    if ((err = wgrad<MODE, D, 4 * D>(m, f.T_a, f.T_b, rows, gl + m->po.ffn2_w, gl + m->po.ffn2_b, s))) return err;
     EpiArgs e2{};
     e2.hpre_in = f.HPRE;
     e2.out = f.dH;
     e2.outT = f.T_a;
     e2.ldT = f.ldT;
     if ((err = gemm_rows<MODE, D, 4 * D, EPI_DGELU>((const AT*)f.DY, rows, wl + m->pk.ffn2T, e2, s))) return err;
-    if ((err = wgrad<MODE>(m, f.T_a, 4 * D, f.T_c, D, rows, gl + m->po.ffn1_w, gl + m->po.ffn1_b, s))) return err;
+    if ((err = wgrad<MODE, 4 * D, D>(m, f.T_a, f.T_c, rows, gl + m->po.ffn1_w, gl + m->po.ffn1_b, s))) return err;
     EpiArgs e3{};
     e3.out = f.TMP;
     if ((err = gemm_rows<MODE, 4 * D, D, EPI_F32>((const AT*)f.dH, rows, wl + m->pk.ffn1T, e3, s))) return err;
@@ -410,16 +440,16 @@ static hipError_t backward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp
     colsum_add(f.colpart, rgrid, 2 * D, f.colpart2, gl + m->po.ln2_g, s);
     // ---- attention backward (dO = dXM: the heads' output is added to the residual directly);
     // probabilities are recomputed from Q, K and the saved log-sum-exp
-    hipLaunchKernelGGL((attn_bwd_dq_mfma<KT, AT, MODE == 1>), dim3((N + 63) / 64, H, nsamp), dim3(256), 0, s, QKV, X,
+    hipLaunchKernelGGL((attn_bwd_dq_mfma<KT, AT, MODE>), dim3((N + 63) / 64, H, nsamp), dim3(256), 0, s, QKV, X,
                        XM, (const float*)f.dXM, LSE, f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window,
                        m->kg.P);
-    hipLaunchKernelGGL((attn_bwd_dkv_mfma<KT, AT, MODE == 1>), dim3((N + 63) / 64, H, nsamp), dim3(256), 0, s, QKV,
+    hipLaunchKernelGGL((attn_bwd_dkv_mfma<KT, AT, MODE>), dim3((N + 63) / 64, H, nsamp), dim3(256), 0, s, QKV,
                        (const float*)f.dXM, LSE, (const float*)f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H,
                        c.window, m->kg.P);
     // ---- QKV backward
     hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(rgrid), dim3(256), 0, s, X, rows, lp + m->po.ln1_g,
                        lp + m->po.ln1_b, (AT*)nullptr, (AT*)f.T_c, f.ldT);
-    if ((err = wgrad<MODE>(m, f.T_a, 3 * D, f.T_c, D, rows, gl + m->po.qkv_w, gl + m->po.qkv_b, s))) return err;
+    if ((err = wgrad<MODE, 3 * D, D>(m, f.T_a, f.T_c, rows, gl + m->po.qkv_w, gl + m->po.qkv_b, s))) return err;
     EpiArgs e4{};
     e4.out = f.TMP;
     if ((err = gemm_rows<MODE, 3 * D, D, EPI_F32>((const AT*)f.dQKV, rows, wl + m->pk.qkvT, e4, s))) return err;

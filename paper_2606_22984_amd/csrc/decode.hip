@@ -86,7 +86,7 @@ __device__ __forceinline__ floatx4 mfma_rowtile(const typename Mode<MODE>::ActT*
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
   const typename Mode<MODE>::ActT* arow = A + (lane & 15) * lda + (lane >> 4) * (KC / 4);
   const uint4* bp = pack + (size_t)nt * NC * 64 + lane;
-#pragma unroll 4
+#pragma unroll 2
   for (int c = 0; c < NC; ++c) acc = Frag<MODE>::step(arow + c * KC, bp + c * 64, bp + c * 64 + lo_u4, acc);
   return acc;
 }
@@ -160,77 +160,98 @@ __device__ void decode_tile(DecodeSmem<D, MODE>& sm, const DecodeUnit& U, int lo
       __syncthreads();
 
       // ---- masked attention over slots [0, nvis), one wave per sample ----
+      // The wave's samples are walked as one stream of row batches (UNR rows per
+      // lane, RPL rows per wave load); the next batch's raw 16-byte K/V loads are
+      // issued before the current batch is reduced, across sample boundaries too.
       {
         const int lrow = lane / LPR;
         const int lcol = (lane % LPR) * VEC;
-        for (int m = wave; m < nb; m += 4) {
-          float qv[VEC];
-#pragma unroll
-          for (int i = 0; i < VEC; ++i) qv[i] = sm.u.q[m][lcol + i] * kScaleLog2;
+        const int per = (nvis + RPL * UNR - 1) / (RPL * UNR);   // batches per sample
+        const int nsw = nb > wave ? (nb - wave + 3) / 4 : 0;    // samples of this wave
+        const int total = per * nsw;
+        uint4 kr[UNR], vr[UNR];
+        auto issue = [&](int bi, uint4* kk, uint4* vv) {
+          const int m = wave + 4 * (bi / per);
+          const int s0 = (bi % per) * RPL * UNR;
           const T* Kb = kvbase + ((size_t)(b0 + m) * nl + l) * 2 * plane;
-          const T* Vb = Kb + plane;
-          float mx = -INFINITY, sum = 0.f, o[VEC];
 #pragma unroll
-          for (int i = 0; i < VEC; ++i) o[i] = 0.f;
-          for (int s0 = 0; s0 < nvis; s0 += RPL * UNR) {
-            Chunk<T> kc[UNR], vc[UNR];
-            bool ok[UNR];
+          for (int u = 0; u < UNR; ++u) {
+            const int s = s0 + u * RPL + lrow;
+            if (s < nvis) {
+              kk[u] = *reinterpret_cast<const uint4*>(Kb + (size_t)s * D + lcol);
+              vv[u] = *reinterpret_cast<const uint4*>(Kb + plane + (size_t)s * D + lcol);
+            }
+          }
+        };
+        if (total > 0) issue(0, kr, vr);
+        float qv[VEC], o[VEC];
+        float mx = -INFINITY, sum = 0.f;
+        for (int bi = 0; bi < total; ++bi) {
+          uint4 kn[UNR], vn[UNR];
+          if (bi + 1 < total) issue(bi + 1, kn, vn);
+          const int m = wave + 4 * (bi / per);
+          const int part = bi % per;
+          if (part == 0) {
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-              const int s = s0 + u * RPL + lrow;
-              ok[u] = s < nvis;
-              if (ok[u]) {
-                kc[u].load(Kb + (size_t)s * D + lcol);
-                vc[u].load(Vb + (size_t)s * D + lcol);
+            for (int i = 0; i < VEC; ++i) { qv[i] = sm.u.q[m][lcol + i] * kScaleLog2; o[i] = 0.f; }
+            mx = -INFINITY;
+            sum = 0.f;
+          }
+          const int s0 = part * RPL * UNR;
+          float sc[UNR];
+          float mnew = mx;
+#pragma unroll
+          for (int u = 0; u < UNR; ++u) {
+            Chunk<T> kc;
+            kc.unpack(kr[u]);
+            float d = 0.f;
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) d += qv[i] * kc.v[i];
+            if (LPH >= 2) d += __shfl_xor(d, 1);
+            if (LPH >= 4) d += __shfl_xor(d, 2);
+            sc[u] = s0 + u * RPL + lrow < nvis ? d : -INFINITY;
+            mnew = fmaxf(mnew, sc[u]);
+          }
+          const float corr = mnew != -INFINITY ? __builtin_amdgcn_exp2f(mx - mnew) : 1.f;
+          sum *= corr;
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) o[i] *= corr;
+#pragma unroll
+          for (int u = 0; u < UNR; ++u) {
+            const bool ok = sc[u] != -INFINITY;
+            const float p = ok ? __builtin_amdgcn_exp2f(sc[u] - mnew) : 0.f;
+            Chunk<T> vc;
+            vc.unpack(vr[u]);
+            sum += p;
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) o[i] += p * (ok ? vc.v[i] : 0.f);
+          }
+          mx = mnew;
+          if (part == per - 1) {
+            // merge the RPL row groups of the wave, then add the heads' outputs to h
+#pragma unroll
+            for (int off = LPR; off < 64; off <<= 1) {
+              const float m2 = __shfl_xor(mx, off);
+              const float s2 = __shfl_xor(sum, off);
+              const float mn = fmaxf(mx, m2);
+              const float c1 = mx == -INFINITY ? 0.f : __builtin_amdgcn_exp2f(mx - mn);
+              const float c2 = m2 == -INFINITY ? 0.f : __builtin_amdgcn_exp2f(m2 - mn);
+              sum = sum * c1 + s2 * c2;
+#pragma unroll
+              for (int i = 0; i < VEC; ++i) {
+                const float o2 = __shfl_xor(o[i], off);
+                o[i] = o[i] * c1 + o2 * c2;
               }
+              mx = mn;
             }
-            float sc[UNR];
-            float mnew = mx;
+            if (lrow == 0) {
+              const float inv = 1.0f / sum;
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-              float d = 0.f;
-#pragma unroll
-              for (int i = 0; i < VEC; ++i) d += qv[i] * kc[u].v[i];
-              if (LPH >= 2) d += __shfl_xor(d, 1);
-              if (LPH >= 4) d += __shfl_xor(d, 2);
-              sc[u] = ok[u] ? d : -INFINITY;
-              mnew = fmaxf(mnew, sc[u]);
+              for (int i = 0; i < VEC; ++i) sm.h[m][lcol + i] += o[i] * inv;
             }
-            const bool any = mnew != -INFINITY;
-            const float corr = any ? __builtin_amdgcn_exp2f(mx - mnew) : 1.f;
-            sum *= corr;
-#pragma unroll
-            for (int i = 0; i < VEC; ++i) o[i] *= corr;
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-              const float p = ok[u] ? __builtin_amdgcn_exp2f(sc[u] - mnew) : 0.f;
-              sum += p;
-#pragma unroll
-              for (int i = 0; i < VEC; ++i) o[i] += p * (ok[u] ? vc[u].v[i] : 0.f);
-            }
-            mx = mnew;
           }
-          // merge the RPL row groups of the wave
 #pragma unroll
-          for (int off = LPR; off < 64; off <<= 1) {
-            const float m2 = __shfl_xor(mx, off);
-            const float s2 = __shfl_xor(sum, off);
-            const float mn = fmaxf(mx, m2);
-            const float c1 = mx == -INFINITY ? 0.f : __builtin_amdgcn_exp2f(mx - mn);
-            const float c2 = m2 == -INFINITY ? 0.f : __builtin_amdgcn_exp2f(m2 - mn);
-            sum = sum * c1 + s2 * c2;
-#pragma unroll
-            for (int i = 0; i < VEC; ++i) {
-              const float o2 = __shfl_xor(o[i], off);
-              o[i] = o[i] * c1 + o2 * c2;
-            }
-            mx = mn;
-          }
-          if (lrow == 0) {
-            const float inv = 1.0f / sum;
-#pragma unroll
-            for (int i = 0; i < VEC; ++i) sm.h[m][lcol + i] += o[i] * inv;
-          }
+          for (int u = 0; u < UNR; ++u) { kr[u] = kn[u]; vr[u] = vn[u]; }
         }
       }
       __syncthreads();

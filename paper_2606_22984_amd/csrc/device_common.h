@@ -46,16 +46,16 @@ template <typename T> struct Chunk;
 template <> struct Chunk<float> {
   static constexpr int N = 4;
   float v[4];
-  __device__ __forceinline__ void load(const float* p) {
-    float4 t = *reinterpret_cast<const float4*>(p);
-    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+  __device__ __forceinline__ void unpack(const uint4& t) {
+    v[0] = __uint_as_float(t.x); v[1] = __uint_as_float(t.y); v[2] = __uint_as_float(t.z); v[3] = __uint_as_float(t.w);
   }
+  __device__ __forceinline__ void load(const float* p) { unpack(*reinterpret_cast<const uint4*>(p)); }
 };
 template <> struct Chunk<__bf16> {
   static constexpr int N = 8;
   float v[8];
-  __device__ __forceinline__ void load(const __bf16* p) {
-    uint4 t = *reinterpret_cast<const uint4*>(p);
+  __device__ __forceinline__ void load(const __bf16* p) { unpack(*reinterpret_cast<const uint4*>(p)); }
+  __device__ __forceinline__ void unpack(const uint4& t) {
     uint32_t w[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -67,8 +67,8 @@ template <> struct Chunk<__bf16> {
 template <> struct Chunk<_Float16> {
   static constexpr int N = 8;
   float v[8];
-  __device__ __forceinline__ void load(const _Float16* p) {
-    uint4 t = *reinterpret_cast<const uint4*>(p);
+  __device__ __forceinline__ void load(const _Float16* p) { unpack(*reinterpret_cast<const uint4*>(p)); }
+  __device__ __forceinline__ void unpack(const uint4& t) {
     f16x8 h;
     __builtin_memcpy(&h, &t, 16);
 #pragma unroll

@@ -57,30 +57,69 @@ __global__ __launch_bounds__(256) void ln_kernel(const float* __restrict__ X, in
 
 // ---------------------------------------------------------------- row GEMM
 // C[r][n] = sum_k A[r][k] W[n][k] over a packed W [NOUT x K]; 64 rows per
-// workgroup, one wave per 16 rows, every 16-column tile of the output.
+// workgroup, one wave per 16 rows.  A is read from HBM once: for K <= 128 the
+// wave's A fragments stay in registers across all output tiles; for larger K
+// (NOUT <= 128) the loop runs K-outer with every output tile's accumulator live.
 template <int MODE, int K, int NOUT, int EPI>
 __global__ __launch_bounds__(256) void gemm_rows_kernel(const typename Mode<MODE>::ActT* __restrict__ A,
                                                         int64_t rows, const uint4* __restrict__ pack,
                                                         EpiArgs e) {
   typedef typename Mode<MODE>::ActT AT;
   constexpr int KC = Mode<MODE>::KC;
+  constexpr int LK = KC / 4;                 // A elements per lane per chunk
   constexpr int NC = K / KC;
+  constexpr int NT = NOUT / 16;
   constexpr size_t LO = (size_t)NOUT * K / 8;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t rbase = (int64_t)blockIdx.x * 64 + wave * 16;
   if (rbase >= rows) return;
   const int64_t ra = std::min<int64_t>(rbase + (lane & 15), rows - 1);   // clamp the A row; stores are guarded
-  const AT* arow = A + ra * K + (lane >> 4) * (KC / 4);
-  for (int nt = 0; nt < NOUT / 16; ++nt) {
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    const uint4* bp = pack + (size_t)nt * NC * 64 + lane;
-#pragma unroll 4
-    for (int c = 0; c < NC; ++c) acc = Frag<MODE>::step(arow + c * KC, bp + c * 64, bp + c * 64 + LO, acc);
-    const int n = nt * 16 + (lane & 15);
+  const AT* arow = A + ra * K + (lane >> 4) * LK;
+  if constexpr (K <= 128) {
+    alignas(16) AT af[NC][LK];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t r = rbase + 4 * (lane >> 4) + i;
-      if (r < rows) Epi<MODE, EPI>::apply(e, r, n, NOUT, acc[i]);
+    for (int c = 0; c < NC; ++c) {
+#pragma unroll
+      for (int i = 0; i < LK; i += 16 / (int)sizeof(AT))
+        *reinterpret_cast<uint4*>(&af[c][i]) = *reinterpret_cast<const uint4*>(arow + c * KC + i);
+    }
+    for (int nt = 0; nt < NT; ++nt) {
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+      const uint4* bp = pack + (size_t)nt * NC * 64 + lane;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc = Frag<MODE>::step(af[c], bp + c * 64, bp + c * 64 + LO, acc);
+      const int n = nt * 16 + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = rbase + 4 * (lane >> 4) + i;
+        if (r < rows) Epi<MODE, EPI>::apply(e, r, n, NOUT, acc[i]);
+      }
+    }
+  } else {
+    static_assert(NT <= 8, "K-outer row GEMM keeps at most 8 output tiles live");
+    floatx4 acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const uint4* bp = pack + lane;
+    for (int c = 0; c < NC; ++c) {
+      alignas(16) AT af[LK];
+#pragma unroll
+      for (int i = 0; i < LK; i += 16 / (int)sizeof(AT))
+        *reinterpret_cast<uint4*>(&af[i]) = *reinterpret_cast<const uint4*>(arow + c * KC + i);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const uint4* b = bp + ((size_t)nt * NC + c) * 64;
+        acc[nt] = Frag<MODE>::step(af, b, b + LO, acc[nt]);
+      }
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int n = nt * 16 + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = rbase + 4 * (lane >> 4) + i;
+        if (r < rows) Epi<MODE, EPI>::apply(e, r, n, NOUT, acc[nt][i]);
+      }
     }
   }
 }

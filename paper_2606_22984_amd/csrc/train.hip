@@ -43,7 +43,7 @@ int ensure_fwd_workspace(fvan_model* m) {
   const size_t R = (size_t)f.rows, ldT = (size_t)f.ldT;
   const size_t at = c.precision == FVAN_BF16 ? 2 : 4;
   const size_t kt = kv_elem_bytes(c.precision);
-  f.part_floats = (size_t)256 * 4 * D * (D + 16);
+  f.part_floats = (size_t)512 * 4 * D * (D + 16);
   f.colpart_floats = std::max<size_t>((size_t)f.chunk * (2 * D + 2), ((R + 63) / 64) * 2 * D);
   struct A { void** p; size_t bytes; const char* what; } allocs[] = {
       {(void**)&f.X, (size_t)(L + 1) * R * D * 4, "X"},   {(void**)&f.XM, (size_t)L * R * D * 4, "XM"},
