@@ -72,7 +72,10 @@ __device__ __forceinline__ float4 load4(const T* p) {
 }
 __device__ __forceinline__ float4 load4(const float* p) { return *reinterpret_cast<const float4*>(p); }
 
-__device__ __forceinline__ bool visible(int t, int j, int W, int P) { return j <= t && (t - j <= W || j < P); }
+// Branch-free mask test (bitwise, so no divergent control flow in the tile loops).
+__device__ __forceinline__ bool visible(int t, int j, int W, int P) {
+  return (j <= t) & ((t - j <= W) | (j < P));
+}
 
 constexpr float kScaleLog2 = 0.25f * 1.4426950408889634f;   // 1/sqrt(16) * log2(e)
 
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV,
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int kv = kb + 4 * g + i;
-          const bool ok = kv < nv && qok && visible(tq, kr.pos(v0 + kv), W, P);
+          const bool ok = (kv < nv) & qok & visible(tq, kr.pos(v0 + kv), W, P);
           s[4 * u + i] = ok ? acc[i] : -INFINITY;
           bmax = fmaxf(bmax, s[4 * u + i]);
         }
@@ -158,7 +161,8 @@ __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV,
       float ps = 0.f;
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        s[i] = s[i] == -INFINITY ? 0.f : __builtin_amdgcn_exp2f(s[i] - mn);
+        const float e = __builtin_amdgcn_exp2f(s[i] - mn);   // -inf - finite -> 0; guarded below for mn = -inf
+        s[i] = mn == -INFINITY ? 0.f : e;
         ps += s[i];
       }
       ps += __shfl_xor(ps, 16);
@@ -246,8 +250,9 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_mfma(const KT* __restrict__ Q
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int kv = kb + 4 * g + i;
-        const bool ok = kv < nv && qok && visible(tq, kr.pos(v0 + kv), W, P);
-        const float p = ok ? __builtin_amdgcn_exp2f(sa[i] - lse) : 0.f;
+        const bool ok = (kv < nv) & qok & visible(tq, kr.pos(v0 + kv), W, P);
+        const float e = __builtin_amdgcn_exp2f(sa[i] - lse);
+        const float p = ok ? e : 0.f;
         ds[i] = p * (pa[i] - delta);
       }
       // dQ[query][dim] += dS[query][key] K[key][dim]; lane's dS = A layout of dS
@@ -327,13 +332,16 @@ __global__ __launch_bounds__(256) void attn_bwd_dkv_mfma(const KT* __restrict__ 
       sa = mfma16<MODE>(k4, *reinterpret_cast<const float4*>(&Qs[qb + c][4 * g]), sa);   // S^T[key 4g+i][query c]
       pa = mfma16<MODE>(v4, *reinterpret_cast<const float4*>(&Gs[qb + c][4 * g]), pa);   // dP^T[key 4g+i][query c]
       const int iq = i0 + qb + c;
+      const float lse_q = Ls[qb + c], del_q = Ds[qb + c];
+      const bool qin = qb + c < nq;
       float p[4], ds[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int jj = j0 + 16 * wave + 4 * g + i;
-        const bool ok = qb + c < nq && jj < N && visible(iq, jj, W, P);
-        p[i] = ok ? __builtin_amdgcn_exp2f(sa[i] - Ls[qb + c]) : 0.f;
-        ds[i] = p[i] * (pa[i] - Ds[qb + c]);
+        const bool ok = qin & (jj < N) & visible(iq, jj, W, P);
+        const float e = __builtin_amdgcn_exp2f(sa[i] - lse_q);
+        p[i] = ok ? e : 0.f;
+        ds[i] = p[i] * (pa[i] - del_q);
       }
       // transpose P^T and dS^T from (key 4g+i, query c) to (key c, queries 4g..4g+3)
 #pragma unroll
