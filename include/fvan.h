@@ -60,7 +60,8 @@ typedef enum {
   FVAN_EINVAL = -1,        /* bad argument: null pointer, size out of range, mismatch */
   FVAN_ENOMEM = -2,        /* workspace allocation failed at create time */
   FVAN_EDEVICE = -3,       /* a HIP runtime call failed (message names it) */
-  FVAN_ENONFINITE = -4,    /* a NaN/Inf reached a reduction (reported by the next synchronising call) */
+  FVAN_ENONFINITE = -4,    /* reserved, not returned by this build: a NaN/Inf energy or log q
+                              propagates into NaN statistics and weights instead */
   FVAN_EUNSUPPORTED = -5   /* valid request this build does not implement */
 } fvan_status;
 

@@ -166,10 +166,11 @@ __global__ __launch_bounds__(256) void transpose_cast_kernel(const float* __rest
 }
 
 // ---------------------------------------------------------------- weight-gradient GEMM
-// part[s][m][n] = sum_{k in slice s, k < K} A[m][k] B[n][k]; A [M x lda] and
-// B [NB x ldb] feature-major, K = rows of the chunk.  One workgroup (8 waves)
-// owns the whole M x NB output for its K slice, so each operand element is read
-// from HBM once; K chunks are staged in LDS and every wave keeps a block of
+// part[s][m][n] = sum_{k in slice s, k < K} A[m][k] B[n][k]; A [m_total x lda]
+// and B [NB x ldb] feature-major, K = rows of the chunk.  One workgroup (8 waves)
+// owns an M x NB block (rows blockIdx.y * M ..) of the output for its K slice, so
+// each operand element is read from HBM once per block; K chunks are staged in LDS (the next chunk is fetched into
+// registers while the current one is multiplied) and every wave keeps a block of
 // RT x CT accumulator tiles (rows split over WRG wave groups, columns over WCG).
 template <int MT>
 struct WaveGrid {
@@ -181,7 +182,7 @@ struct WaveGrid {
 template <int MODE, int M, int NB>
 __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::ActT* __restrict__ A, int64_t lda,
                                                     const typename Mode<MODE>::ActT* __restrict__ B, int64_t ldb,
-                                                    int64_t K, int64_t kper, float* __restrict__ part) {
+                                                    int64_t K, int64_t kper, int m_total, float* __restrict__ part) {
   typedef typename Mode<MODE>::ActT AT;
   constexpr int KC = Mode<MODE>::KC;
   constexpr int LK = KC / 4;
@@ -196,6 +197,7 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave / WCG, wc = wave % WCG;
   const int s = blockIdx.x;
+  A += (int64_t)blockIdx.y * M * lda;              // this workgroup's block of M output rows
   const int64_t kb = (int64_t)s * kper;
   const int64_t ke = std::min<int64_t>(K, kb + kper);
   floatx4 acc[RT][CT];
@@ -203,23 +205,44 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
   for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int j = 0; j < CT; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t k = kb; k < ke; k += KC) {
+  // K chunks are fetched into registers one chunk ahead of the MFMA loop
+  constexpr int NPIECE = (M + NB) * (KC / VPL);    // 16-byte pieces per chunk
+  constexpr int NLD = (NPIECE + 511) / 512;
+  uint4 pre[NLD];
+  auto fetch = [&](int64_t k) {
     const bool full = k + KC <= ke;
-    // stage A[:, k:k+KC] and B[:, k:k+KC]
-    for (int x = threadIdx.x; x < (M + NB) * (KC / VPL); x += 512) {
-      const int row = x / (KC / VPL), piece = x % (KC / VPL);
-      const bool isA = row < M;
-      const AT* src = isA ? A + (int64_t)row * lda : B + (int64_t)(row - M) * ldb;
-      AT* dst = isA ? &As[row][piece * VPL] : &Bs[row - M][piece * VPL];
-      const int64_t kk = k + piece * VPL;
-      if (full) {
-        *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src + kk);
-      } else {
 #pragma unroll
-        for (int i = 0; i < VPL; ++i) dst[i] = kk + i < ke ? src[kk + i] : from_f<AT>(0.f);
+    for (int u = 0; u < NLD; ++u) {
+      const int x = threadIdx.x + 512 * u;
+      pre[u] = make_uint4(0u, 0u, 0u, 0u);
+      if (x < NPIECE) {
+        const int row = x / (KC / VPL), piece = x % (KC / VPL);
+        const AT* src = row < M ? A + (int64_t)row * lda : B + (int64_t)(row - M) * ldb;
+        const int64_t kk = k + piece * VPL;
+        if (full) {
+          pre[u] = *reinterpret_cast<const uint4*>(src + kk);
+        } else {
+          alignas(16) AT tmp[VPL];
+#pragma unroll
+          for (int i = 0; i < VPL; ++i) tmp[i] = kk + i < ke ? src[kk + i] : from_f<AT>(0.f);
+          pre[u] = *reinterpret_cast<const uint4*>(tmp);
+        }
+      }
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int64_t k = kb; k < ke; k += KC) {
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+      const int x = threadIdx.x + 512 * u;
+      if (x < NPIECE) {
+        const int row = x / (KC / VPL), piece = x % (KC / VPL);
+        AT* dst = row < M ? &As[row][piece * VPL] : &Bs[row - M][piece * VPL];
+        *reinterpret_cast<uint4*>(dst) = pre[u];
       }
     }
     __syncthreads();
+    if (k + KC < ke) fetch(k + KC);
     alignas(16) AT af[RT][LK];
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
@@ -241,7 +264,7 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
     }
     __syncthreads();
   }
-  float* out = part + (size_t)s * M * NB;
+  float* out = part + ((size_t)s * m_total + (size_t)blockIdx.y * M) * NB;
 #pragma unroll
   for (int i = 0; i < RT; ++i) {
 #pragma unroll
@@ -280,8 +303,11 @@ static hipError_t wgrad(fvan_model* m, const void* A, const void* B, int64_t K, 
   int64_t kper = (K + S - 1) / S;
   kper = (kper + KC - 1) / KC * KC;
   S = (int)((K + kper - 1) / kper);
-  hipLaunchKernelGGL((wgrad_kernel<MODE, M, NB>), dim3(S), dim3(512), 0, s, (const AT*)A, f.ldT, (const AT*)B, f.ldT,
-                     K, kper, f.part);
+  // outputs of 512 rows are split over two workgroups per K slice (keeps the
+  // accumulators and the prefetch registers of a wave within 256 VGPRs)
+  constexpr int MS = M >= 512 ? M / 2 : M;
+  hipLaunchKernelGGL((wgrad_kernel<MODE, MS, NB>), dim3(S, M / MS), dim3(512), 0, s, (const AT*)A, f.ldT,
+                     (const AT*)B, f.ldT, K, kper, M, f.part);
   const int total = M * (Nw + 1);
   hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(std::min(1024, (total + 255) / 256)), dim3(256), 0, s,
                      (const float*)f.part, S, M, NB, Nw, gW, gb);
@@ -443,7 +469,7 @@ static hipError_t backward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp
     hipLaunchKernelGGL((attn_bwd_dq_mfma<KT, AT, MODE>), dim3((N + 63) / 64, H, nsamp), dim3(256), 0, s, QKV, X,
                        XM, (const float*)f.dXM, LSE, f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window,
                        m->kg.P);
-    hipLaunchKernelGGL((attn_bwd_dkv_mfma<KT, AT, MODE>), dim3((N + 63) / 64, H, nsamp), dim3(256), 0, s, QKV,
+    hipLaunchKernelGGL((attn_bwd_dkv_mfma<KT, AT, MODE>), dim3(H, (N + 63) / 64, nsamp), dim3(256), 0, s, QKV,
                        (const float*)f.dXM, LSE, (const float*)f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H,
                        c.window, m->kg.P);
     // ---- QKV backward

@@ -124,12 +124,130 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(const typename Mode<MODE
   }
 }
 
+// Row GEMM with an LDS-staged epilogue for the wide FFN outputs (K <= 128,
+// GELU / GELU' epilogues).  Each group of four 16-column tiles is computed into
+// a 64 x 64 tile in LDS; the workgroup then writes the row-major outputs as
+// 256-byte row segments and the feature-major copy as 256-byte column segments
+// (16-byte stores), instead of one scattered element per lane.
+//   EPI_GELU : h = acc + bias; hpre_out[r][n] = h, out[r][n] = GELU(h), outT[n][r] = GELU(h)
+//   EPI_DGELU: d = acc * GELU'(hpre_in[r][n]); out[r][n] = d, outT[n][r] = d
+// (each output only if its pointer is set).
+template <typename T>
+__device__ __forceinline__ void store4(T* p, float a, float b, float c, float d) {
+  if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
+  } else {
+    typedef __attribute__((__vector_size__(4 * sizeof(T)))) T v4;
+    v4 v = {from_f<T>(a), from_f<T>(b), from_f<T>(c), from_f<T>(d)};
+    *reinterpret_cast<v4*>(p) = v;
+  }
+}
+
+template <int MODE, int K, int NOUT, int EPI>
+__global__ __launch_bounds__(256) void gemm_rows_staged_kernel(const typename Mode<MODE>::ActT* __restrict__ A,
+                                                               int64_t rows, const uint4* __restrict__ pack,
+                                                               EpiArgs e) {
+  typedef typename Mode<MODE>::ActT AT;
+  static_assert(K <= 128 && NOUT % 64 == 0, "staged row GEMM: K <= 128, NOUT a multiple of 64");
+  static_assert(EPI == EPI_GELU || EPI == EPI_DGELU, "staged row GEMM: GELU or GELU' epilogue");
+  constexpr int KC = Mode<MODE>::KC;
+  constexpr int LK = KC / 4;
+  constexpr int NC = K / KC;
+  constexpr int NG = NOUT / 64;
+  constexpr size_t LO = (size_t)NOUT * K / 8;
+  __shared__ __align__(16) float Ev[64][68];     // out / outT values
+  __shared__ __align__(16) float Eh[64][68];     // pre-activation: GELU output hpre_out, GELU' input hpre_in
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int64_t ra = std::min<int64_t>(r0 + wave * 16 + c, rows - 1);   // clamp the A row; stores are guarded
+  const AT* arow = A + ra * K + g * LK;
+  alignas(16) AT af[NC][LK];
+#pragma unroll
+  for (int cc = 0; cc < NC; ++cc) {
+#pragma unroll
+    for (int i = 0; i < LK; i += 16 / (int)sizeof(AT))
+      *reinterpret_cast<uint4*>(&af[cc][i]) = *reinterpret_cast<const uint4*>(arow + cc * KC + i);
+  }
+  const bool full = r0 + 64 <= rows;
+  AT* out = reinterpret_cast<AT*>(e.out);
+  AT* outT = reinterpret_cast<AT*>(e.outT);
+  for (int ng = 0; ng < NG; ++ng) {
+    if constexpr (EPI == EPI_DGELU) {
+      // stage the pre-activation tile (256-byte row segments)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int idx = tid + 256 * k, row = idx >> 4, c4 = (idx & 15) * 4;
+        const int64_t r = std::min<int64_t>(r0 + row, rows - 1);
+        *reinterpret_cast<float4*>(&Eh[row][c4]) =
+            *reinterpret_cast<const float4*>(e.hpre_in + r * NOUT + ng * 64 + c4);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int nt = ng * 4 + u;
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+      const uint4* bp = pack + (size_t)nt * NC * 64 + lane;
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) acc = Frag<MODE>::step(af[cc], bp + cc * 64, bp + cc * 64 + LO, acc);
+      const int col = 16 * u + c;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = wave * 16 + 4 * g + i;
+        if constexpr (EPI == EPI_GELU) {
+          const float hv = acc[i] + e.bias[ng * 64 + col];
+          Eh[row][col] = hv;
+          Ev[row][col] = gelu(hv);
+        } else {
+          Ev[row][col] = acc[i] * gelu_grad(Eh[row][col]);
+        }
+      }
+    }
+    __syncthreads();
+    const int n0 = ng * 64;
+    // row-major outputs: thread -> (row, 4 columns); 16 threads cover a 64-column row segment
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int idx = tid + 256 * k, row = idx >> 4, c4 = (idx & 15) * 4;
+      const int64_t r = r0 + row;
+      if (r < rows) {
+        if (out) store4(out + r * NOUT + n0 + c4, Ev[row][c4], Ev[row][c4 + 1], Ev[row][c4 + 2], Ev[row][c4 + 3]);
+        if constexpr (EPI == EPI_GELU) {
+          if (e.hpre_out)
+            *reinterpret_cast<float4*>(e.hpre_out + r * NOUT + n0 + c4) =
+                *reinterpret_cast<const float4*>(&Eh[row][c4]);
+        }
+      }
+    }
+    // feature-major copy: thread -> (column, 4 rows); 16 threads cover the tile's 64 rows
+    if (outT) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int idx = tid + 256 * k, col = idx >> 4, q4 = (idx & 15) * 4;
+        AT* dst = outT + (int64_t)(n0 + col) * e.ldT + r0 + q4;
+        if (full) {
+          store4(dst, Ev[q4][col], Ev[q4 + 1][col], Ev[q4 + 2][col], Ev[q4 + 3][col]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (r0 + q4 + i < rows) dst[i] = from_f<AT>(Ev[q4 + i][col]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <int MODE, int K, int NOUT, int EPI>
 inline hipError_t gemm_rows(const typename Mode<MODE>::ActT* A, int64_t rows, const void* pack, const EpiArgs& e,
                             hipStream_t s) {
   const int grid = (int)((rows + 63) / 64);
-  hipLaunchKernelGGL((gemm_rows_kernel<MODE, K, NOUT, EPI>), dim3(grid), dim3(256), 0, s, A, rows,
-                     reinterpret_cast<const uint4*>(pack), e);
+  if constexpr ((EPI == EPI_GELU || EPI == EPI_DGELU) && K <= 128 && NOUT % 64 == 0)
+    hipLaunchKernelGGL((gemm_rows_staged_kernel<MODE, K, NOUT, EPI>), dim3(grid), dim3(256), 0, s, A, rows,
+                       reinterpret_cast<const uint4*>(pack), e);
+  else
+    hipLaunchKernelGGL((gemm_rows_kernel<MODE, K, NOUT, EPI>), dim3(grid), dim3(256), 0, s, A, rows,
+                       reinterpret_cast<const uint4*>(pack), e);
   return hipGetLastError();
 }
 
