@@ -23,6 +23,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Bytes moved per decode launch at this workload (FETCH_SIZE + WRITE_SIZE from two
+# rocprofv3 --pmc runs, each scaled by the same counter's reading for a 1 GiB copy);
+# the record with the commands is profiles/decode_ea3d_L10_hbm_counters.md.
+# Set to None whenever decode_kernel changes until the counters are taken again.
+DECODE_TRAFFIC_BYTES = 16.23e12
 # first learning rate of the paper's linear warm-up (SI Sec. III B); larger first
 # Adam steps collapse this random-init model within a few steps
 LR = 1e-5
@@ -147,7 +152,7 @@ def main():
     bytes_launch = kv_bytes_per_sample(N, L, D, W, P, kv_elem) * B
     achieved = bytes_launch / (head["decode_ms"] * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": DECODE_TRAFFIC_BYTES,
             "kernel": "decode_kernel<128,2>", "algorithmic_bytes_per_launch": bytes_launch}
 
     cpu = None
