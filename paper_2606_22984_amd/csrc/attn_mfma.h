@@ -3,17 +3,23 @@
 //
 // Notation per (sample, head): S = Q K^T / sqrt(16) in log2 units (the scale
 // and log2(e) are folded into Q or K), P = 2^(S - LSE), O = P V.
-// Lane layouts of a 16x16 tile (l = lane): the A operand holds A[l%16][4g..4g+3]
-// and the B operand B[4g..4g+3][l%16] with g = l/16; the accumulator holds
-// C[4g+i][l%16].  Computing S^T = K Q^T therefore leaves lane l with keys 4g+i
-// of query l%16, which is the B layout P^T needs in O^T = V^T P^T and the A
-// layout dS needs in dQ = dS K; the dK/dV kernel forms S = Q K^T instead, which
-// leaves P^T and dS^T in the A layout of dV and dK.
+// Lane layouts of a 16x16 tile (l = lane, g = l/16, c = l%16): the A operand
+// holds A[c][4g..4g+3], the B operand B[4g..4g+3][c] and the accumulator
+// C[4g+i][c].  Computing S^T = K Q^T leaves lane l with keys 4g+i of query c,
+// which is the B layout P^T needs in O^T = V^T P^T and the A layout dS needs in
+// dQ = dS K; the dK/dV kernel forms S = Q K^T instead, which leaves P^T and dS^T
+// in the A layout of dV and dK.
+//
+// Operands are converted once, when a block of rows is staged in LDS, into the
+// MFMA operand type of the precision mode (AOp below), in both the A layout
+// ([row][g]: four consecutive dims of a row) and the B layout ([dim][row group]:
+// four consecutive rows of a dim), so the tile loops only load and multiply.
 //
 // Precision of the tile products (mode = fvan_precision): FP32 MFMA
 // (16x16x4, four per tile) for FVAN_FP32, BF16 MFMA (16x16x16) for FVAN_BF16,
-// and for FVAN_BF16_SPLIT three BF16 MFMAs on hi/lo operand splits
-// (lo*hi + hi*lo + hi*hi; the dropped lo*lo term is below 2^-16 relative).
+// and for FVAN_BF16_SPLIT the three products hi*hi + lo*hi + hi*lo of hi/lo
+// BF16 operand splits (the dropped lo*lo term is below 2^-16 relative), issued
+// as two 16x16x32 MFMAs.
 #pragma once
 
 #include <algorithm>
@@ -29,41 +35,56 @@ __device__ __forceinline__ bf16x4 bf4(float a, float b, float c, float d) {
   return v;
 }
 
-template <int MODE>
-__device__ __forceinline__ floatx4 mfma16(const float4& a, const float4& b, floatx4 acc) {
-  if constexpr (MODE == 1) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bf4(a.x, a.y, a.z, a.w), bf4(b.x, b.y, b.z, b.w), acc, 0, 0, 0);
-  } else if constexpr (MODE == 2) {
-    const bf16x4 ah = bf4(a.x, a.y, a.z, a.w), bh = bf4(b.x, b.y, b.z, b.w);
-    const bf16x4 al = bf4(a.x - (float)ah[0], a.y - (float)ah[1], a.z - (float)ah[2], a.w - (float)ah[3]);
-    const bf16x4 bl = bf4(b.x - (float)bh[0], b.y - (float)bh[1], b.z - (float)bh[2], b.w - (float)bh[3]);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
-  } else {
+// MFMA operand of one lane (four k values) per precision mode.
+template <int MODE> struct AOp;
+template <> struct AOp<0> {
+  typedef float4 T;
+  static __device__ __forceinline__ T make(float a, float b, float c, float d) { return make_float4(a, b, c, d); }
+  static __device__ __forceinline__ floatx4 mma(const T& a, const T& b, floatx4 acc) {
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
   }
-}
-
-// 16 consecutive elements (one head's slice of a row) as floats.
-template <typename T>
-__device__ __forceinline__ void load16(const T* p, float* out) {
-  Chunk<T> a, b;
-  a.unpack(*reinterpret_cast<const uint4*>(p));
-  b.unpack(*reinterpret_cast<const uint4*>(p + 8));
-#pragma unroll
-  for (int i = 0; i < 8; ++i) { out[i] = a.v[i]; out[8 + i] = b.v[i]; }
-}
-template <>
-__device__ __forceinline__ void load16<float>(const float* p, float* out) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const float4 t = reinterpret_cast<const float4*>(p)[i];
-    out[4 * i] = t.x; out[4 * i + 1] = t.y; out[4 * i + 2] = t.z; out[4 * i + 3] = t.w;
+};
+template <> struct AOp<1> {
+  typedef bf16x4 T;
+  static __device__ __forceinline__ T make(float a, float b, float c, float d) { return bf4(a, b, c, d); }
+  static __device__ __forceinline__ floatx4 mma(const T& a, const T& b, floatx4 acc) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
   }
+};
+struct SplitBf16x4 {
+  bf16x4 h, l;
+};
+template <> struct AOp<2> {
+  typedef SplitBf16x4 T;
+  static __device__ __forceinline__ T make(float a, float b, float c, float d) {
+    T t;
+    t.h = bf4(a, b, c, d);
+    t.l = bf4(a - (float)t.h[0], b - (float)t.h[1], c - (float)t.h[2], d - (float)t.h[3]);
+    return t;
+  }
+  // The contraction index of a 16x16x32 MFMA runs over (part, dim): lane g's
+  // eight k slots hold dims 4g..4g+3 twice.  First [a_hi | a_lo] x [b_hi ; b_hi]
+  // = a_hi b_hi + a_lo b_hi, then [a_hi | a_hi] x [b_lo ; 0] = a_hi b_lo.  Both
+  // products use the same opcode: a 16x16x32 result fed straight into a
+  // dependent 16x16x16 MFMA was measured to come out wrong with this toolchain
+  // (missing wait states between the two opcodes), so that pairing is avoided.
+  static __device__ __forceinline__ floatx4 mma(const T& a, const T& b, floatx4 acc) {
+    const bf16x4 z = {(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
+    const bf16x8 a8 = __builtin_shufflevector(a.h, a.l, 0, 1, 2, 3, 4, 5, 6, 7);
+    const bf16x8 b8 = __builtin_shufflevector(b.h, b.h, 0, 1, 2, 3, 4, 5, 6, 7);
+    const bf16x8 a9 = __builtin_shufflevector(a.h, a.h, 0, 1, 2, 3, 4, 5, 6, 7);
+    const bf16x8 b9 = __builtin_shufflevector(b.l, z, 0, 1, 2, 3, 4, 5, 6, 7);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a8, b8, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a9, b9, acc, 0, 0, 0);
+  }
+};
+
+template <int MODE>
+__device__ __forceinline__ typename AOp<MODE>::T aop(const float4& v) {
+  return AOp<MODE>::make(v.x, v.y, v.z, v.w);
 }
 
 template <typename T>
@@ -78,7 +99,6 @@ __device__ __forceinline__ bool visible(int t, int j, int W, int P) {
 }
 
 constexpr float kScaleLog2 = 0.25f * 1.4426950408889634f;   // 1/sqrt(16) * log2(e)
-
 constexpr int kKeyChunk = 128;                               // keys staged in LDS at a time
 
 // The keys a query tile [t0, t1) can see: [0, pend) then [bstart, t1), as one
@@ -94,9 +114,9 @@ struct KeyRange {
 };
 
 // Stages kKeyChunk keys (one head's K and V slices) of a query tile's visible
-// range into LDS as floats, [key][dim] with rows padded to 20.  Every thread
-// loads 16-byte chunks; the next chunk is fetched into registers while the
-// current one is processed.
+// range: every thread loads 16-byte chunks of K and V into registers (the next
+// chunk is fetched while the current one is processed), commit() writes them to
+// float tiles [key][dim] with rows padded to 20.
 template <typename KT>
 struct KeyStager {
   static constexpr int QE = 16 / (int)sizeof(KT);            // elements per 16-byte chunk
@@ -118,7 +138,7 @@ struct KeyStager {
       }
     }
   }
-  __device__ __forceinline__ void commit(float (*Ks)[20], float (*Vs)[20]) const {
+  __device__ __forceinline__ void commit(float (*Kf)[20], float (*Vf)[20]) const {
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
       const int idx = threadIdx.x + 256 * u, key = idx / QC, ch = (idx % QC) * QE;
@@ -127,12 +147,33 @@ struct KeyStager {
       vc.unpack(vraw[u]);
 #pragma unroll
       for (int e = 0; e < QE; e += 4) {
-        *reinterpret_cast<float4*>(&Ks[key][ch + e]) = make_float4(kc.v[e], kc.v[e + 1], kc.v[e + 2], kc.v[e + 3]);
-        *reinterpret_cast<float4*>(&Vs[key][ch + e]) = make_float4(vc.v[e], vc.v[e + 1], vc.v[e + 2], vc.v[e + 3]);
+        *reinterpret_cast<float4*>(&Kf[key][ch + e]) = make_float4(kc.v[e], kc.v[e + 1], kc.v[e + 2], kc.v[e + 3]);
+        *reinterpret_cast<float4*>(&Vf[key][ch + e]) = make_float4(vc.v[e], vc.v[e + 1], vc.v[e + 2], vc.v[e + 3]);
       }
     }
   }
 };
+
+// Operand tiles of R staged rows (R = 64 or 128) of one head: A layout [row][g]
+// (dims 4g..4g+3 of the row) and B layout [dim][row group] (rows 4j..4j+3 of
+// the dim; one padding column against bank conflicts).  Built by all 256
+// threads from a float tile [row][dim].
+template <int MODE, int R>
+__device__ __forceinline__ void build_a(const float (*F)[20], typename AOp<MODE>::T (*A)[4]) {
+#pragma unroll
+  for (int idx = threadIdx.x; idx < R * 4; idx += 256) {
+    const int row = idx >> 2, g = idx & 3;
+    A[row][g] = aop<MODE>(*reinterpret_cast<const float4*>(&F[row][4 * g]));
+  }
+}
+template <int MODE, int R>
+__device__ __forceinline__ void build_b(const float (*F)[20], typename AOp<MODE>::T (*B)[R / 4 + 1]) {
+#pragma unroll
+  for (int idx = threadIdx.x; idx < R * 4; idx += 256) {
+    const int dim = idx / (R / 4), j = idx % (R / 4);
+    B[dim][j] = AOp<MODE>::make(F[4 * j][dim], F[4 * j + 1][dim], F[4 * j + 2][dim], F[4 * j + 3][dim]);
+  }
+}
 
 // ---------------------------------------------------------------- forward
 // One workgroup = (64 queries, head, sample); wave w owns queries t0+16w..+15.
@@ -141,8 +182,12 @@ template <typename KT, int MODE>
 __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV, const float* __restrict__ X,
                                                      float* __restrict__ XM, float* __restrict__ LSE, int N, int D,
                                                      int H, int W, int P) {
-  __shared__ __align__(16) float Ks[kKeyChunk][20];   // [key][dim] (padded)
-  __shared__ __align__(16) float Vs[kKeyChunk][20];
+  typedef AOp<MODE> Op;
+  typedef typename Op::T OT;
+  __shared__ __align__(16) float Kf[kKeyChunk][20];
+  __shared__ __align__(16) float Vf[kKeyChunk][20];
+  __shared__ __align__(16) OT Ka[kKeyChunk][4];               // K, A layout
+  __shared__ __align__(16) OT Vb[16][kKeyChunk / 4 + 1];      // V^T as the A operand: [dim][key group]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
   const int t0 = blockIdx.x * 64, h = blockIdx.y, b = blockIdx.z;
   const int t1 = min(t0 + 64, N);
@@ -154,6 +199,7 @@ __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV,
     q4 = load4(QKV + (rowbase + tq) * 3 * D + h * 16 + 4 * g);
     q4.x *= kScaleLog2; q4.y *= kScaleLog2; q4.z *= kScaleLog2; q4.w *= kScaleLog2;
   }
+  const OT qb = aop<MODE>(q4);                       // B operand Q^T[dim 4g..][query c]
   const KeyRange kr(t0, t1, W, P);
   KeyStager<KT> st;
   st.fetch(QKV, rowbase, D, h, kr, 0);
@@ -162,9 +208,12 @@ __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV,
   for (int v0 = 0; v0 < kr.nk; v0 += kKeyChunk) {
     const int nv = min(kKeyChunk, kr.nk - v0);
     __syncthreads();
-    st.commit(Ks, Vs);
+    st.commit(Kf, Vf);
     __syncthreads();
     if (v0 + kKeyChunk < kr.nk) st.fetch(QKV, rowbase, D, h, kr, v0 + kKeyChunk);
+    build_a<MODE, kKeyChunk>(Kf, Ka);
+    build_b<MODE, kKeyChunk>(Vf, Vb);
+    __syncthreads();
     for (int kt0 = 0; kt0 < nv; kt0 += 64) {         // 4 key tiles of 16 per softmax update
       float s[16];
       float bmax = -INFINITY;
@@ -172,7 +221,7 @@ __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV,
       for (int u = 0; u < 4; ++u) {
         const int kb = kt0 + 16 * u;
         floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-        if (kb < nv) acc = mfma16<MODE>(load4(&Ks[kb + c][4 * g]), q4, acc);
+        if (kb < nv) acc = Op::mma(Ka[kb + c][g], qb, acc);   // S^T[key 4g+i][query c]
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int kv = kb + 4 * g + i;
@@ -201,11 +250,8 @@ __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV,
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int kb = kt0 + 16 * u;
-        if (kb < nv) {
-          const int r0 = kb + 4 * g;                  // A = V^T[dim c][keys r0..r0+3]
-          const float4 vt = make_float4(Vs[r0][c], Vs[r0 + 1][c], Vs[r0 + 2][c], Vs[r0 + 3][c]);
-          o = mfma16<MODE>(vt, make_float4(s[4 * u], s[4 * u + 1], s[4 * u + 2], s[4 * u + 3]), o);
-        }
+        if (kb < nv)   // A = V^T[dim c][keys kb+4g..+3], B = P^T[keys][query c]
+          o = Op::mma(Vb[c][kb / 4 + g], Op::make(s[4 * u], s[4 * u + 1], s[4 * u + 2], s[4 * u + 3]), o);
       }
     }
   }
@@ -229,8 +275,13 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_mfma(const KT* __restrict__ Q
                                                         const float* __restrict__ LSE, float* __restrict__ DELTA,
                                                         AT* __restrict__ dQKV, AT* __restrict__ T, int64_t ldT, int N,
                                                         int D, int H, int W, int P) {
-  __shared__ __align__(16) float Ks[kKeyChunk][20];
-  __shared__ __align__(16) float Vs[kKeyChunk][20];
+  typedef AOp<MODE> Op;
+  typedef typename Op::T OT;
+  __shared__ __align__(16) float Kf[kKeyChunk][20];
+  __shared__ __align__(16) float Vf[kKeyChunk][20];
+  __shared__ __align__(16) OT Ka[kKeyChunk][4];
+  __shared__ __align__(16) OT Va[kKeyChunk][4];
+  __shared__ __align__(16) OT Kb[16][kKeyChunk / 4 + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
   const int t0 = blockIdx.x * 64, h = blockIdx.y, b = blockIdx.z;
   const int t1 = min(t0 + 64, N);
@@ -255,17 +306,22 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_mfma(const KT* __restrict__ Q
   delta += __shfl_xor(delta, 16);
   delta += __shfl_xor(delta, 32);
   if (qok && g == 0) DELTA[r * H + h] = delta;
+  const OT qb = aop<MODE>(q4), gb = aop<MODE>(g4);   // B operands Q^T, dO^T [dim 4g..][query c]
   floatx4 dq = {0.f, 0.f, 0.f, 0.f};               // dQ[query 16w+4g+i][dim c]
   for (int v0 = 0; v0 < kr.nk; v0 += kKeyChunk) {
     const int nv = min(kKeyChunk, kr.nk - v0);
     __syncthreads();
-    st.commit(Ks, Vs);
+    st.commit(Kf, Vf);
     __syncthreads();
     if (v0 + kKeyChunk < kr.nk) st.fetch(QKV, rowbase, D, h, kr, v0 + kKeyChunk);
+    build_a<MODE, kKeyChunk>(Kf, Ka);
+    build_a<MODE, kKeyChunk>(Vf, Va);
+    build_b<MODE, kKeyChunk>(Kf, Kb);
+    __syncthreads();
     for (int kb = 0; kb < nv; kb += 16) {
-      floatx4 sa = {0.f, 0.f, 0.f, 0.f}, pa = {0.f, 0.f, 0.f, 0.f};
-      sa = mfma16<MODE>(load4(&Ks[kb + c][4 * g]), q4, sa);     // S^T[key 4g+i][query c]
-      pa = mfma16<MODE>(load4(&Vs[kb + c][4 * g]), g4, pa);     // dP^T[key 4g+i][query c]
+      const floatx4 z = {0.f, 0.f, 0.f, 0.f};
+      const floatx4 sa = Op::mma(Ka[kb + c][g], qb, z);     // S^T[key 4g+i][query c]
+      const floatx4 pa = Op::mma(Va[kb + c][g], gb, z);     // dP^T[key 4g+i][query c]
       float ds[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -276,9 +332,7 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_mfma(const KT* __restrict__ Q
         ds[i] = p * (pa[i] - delta);
       }
       // dQ[query][dim] += dS[query][key] K[key][dim]; lane's dS = A layout of dS
-      const int r0 = kb + 4 * g;
-      const float4 kt = make_float4(Ks[r0][c], Ks[r0 + 1][c], Ks[r0 + 2][c], Ks[r0 + 3][c]);
-      dq = mfma16<MODE>(make_float4(ds[0], ds[1], ds[2], ds[3]), kt, dq);
+      dq = Op::mma(Op::make(ds[0], ds[1], ds[2], ds[3]), Kb[c][kb / 4 + g], dq);
     }
   }
   // dq[i] = dQ[query 16w + 4g + i][dim c]
@@ -300,21 +354,24 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_mfma(const KT* __restrict__ Q
 // one head's tiles and the long prefix tiles are spread evenly (with the tile
 // index fastest, every prefix tile would land on the same two XCDs).  Wave w
 // owns keys j0+16w..+15 and loops over the 64-query blocks that can see the tile
-// ([j0, j1 + W), or [j0, N) when the tile holds prefix keys).  Scores are formed as S = Q K^T (A = staged query
-// rows, B = the wave's fixed keys), so lane l holds S[4g+i][key l%16]: exactly the
-// A layout of P^T and dS^T in dV += P^T dO and dK += dS^T Q, with no transpose.
-// The next query block is fetched into registers while the current one is
-// processed; every thread issues at most three 16-byte (or 4-byte) loads per block.
+// ([j0, j1 + W), or [j0, N) when the tile holds prefix keys).  The next query
+// block is fetched into registers while the current one is processed.
 template <typename KT, typename AT, int MODE>
 __global__ __launch_bounds__(256) void attn_bwd_dkv_mfma(const KT* __restrict__ QKV, const float* __restrict__ dO,
                                                          const float* __restrict__ LSE, const float* __restrict__ DELTA,
                                                          AT* __restrict__ dQKV, AT* __restrict__ T, int64_t ldT, int N,
                                                          int D, int H, int W, int P) {
+  typedef AOp<MODE> Op;
+  typedef typename Op::T OT;
   constexpr int QB = 64;
   constexpr int QE = 16 / (int)sizeof(KT);          // Q elements per 16-byte chunk
   constexpr int QC = 16 / QE;                       // 16-byte chunks per query row slice
-  __shared__ __align__(16) float Qs[QB][20];
-  __shared__ __align__(16) float Gs[QB][20];
+  __shared__ __align__(16) float Qf[QB][20];
+  __shared__ __align__(16) float Gf[QB][20];
+  __shared__ __align__(16) OT Qa[QB][4];            // Q, A layout (S = Q K^T)
+  __shared__ __align__(16) OT Ga[QB][4];            // dO, A layout (dP = dO V^T)
+  __shared__ __align__(16) OT Qb[16][QB / 4 + 1];   // Q, B layout (dK += dS^T Q)
+  __shared__ __align__(16) OT Gb[16][QB / 4 + 1];   // dO, B layout (dV += P^T dO)
   __shared__ __align__(16) float Ls[QB];
   __shared__ __align__(16) float Ds[QB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
@@ -330,6 +387,7 @@ __global__ __launch_bounds__(256) void attn_bwd_dkv_mfma(const KT* __restrict__ 
     k4.x *= kScaleLog2; k4.y *= kScaleLog2; k4.z *= kScaleLog2; k4.w *= kScaleLog2;
     v4 = load4(kp + D);
   }
+  const OT kb = aop<MODE>(k4), vb = aop<MODE>(v4);  // B operands K^T, V^T [dim 4g..][key c]
   const int qend = j0 < P ? N : min(N, j1 + W);
   // staging roles: dO row tid/4, quarter tid%4; Q row tid/QC, chunk tid%QC (tid < 64*QC);
   // LSE (tid < 64) or DELTA (64 <= tid < 128) of row tid%64
@@ -354,38 +412,40 @@ __global__ __launch_bounds__(256) void attn_bwd_dkv_mfma(const KT* __restrict__ 
   for (int i0 = j0; i0 < qend; i0 += QB) {
     const int nq = min(QB, qend - i0);
     __syncthreads();                                 // the previous block's reads are done
-    *reinterpret_cast<float4*>(&Gs[gr][gc]) = graw;
+    *reinterpret_cast<float4*>(&Gf[gr][gc]) = graw;
     if (qthr) {
       Chunk<KT> ch;
       ch.unpack(qraw);
 #pragma unroll
-      for (int e = 0; e < QE; ++e) Qs[qr][qc + e] = ch.v[e];
+      for (int e = 0; e < QE; ++e) Qf[qr][qc + e] = ch.v[e];
     }
     if (tid < 64) Ls[sr] = sraw;
     else if (tid < 128) Ds[sr] = sraw;
     __syncthreads();
     if (i0 + QB < qend) fetch(i0 + QB);
-    for (int qb = 0; qb < nq; qb += 16) {
+    build_a<MODE, QB>(Qf, Qa);
+    build_a<MODE, QB>(Gf, Ga);
+    build_b<MODE, QB>(Qf, Qb);
+    build_b<MODE, QB>(Gf, Gb);
+    __syncthreads();
+    for (int q0 = 0; q0 < nq; q0 += 16) {
       const floatx4 z = {0.f, 0.f, 0.f, 0.f};
-      const floatx4 sa = mfma16<MODE>(*reinterpret_cast<const float4*>(&Qs[qb + c][4 * g]), k4, z);  // S[q 4g+i][key c]
-      const floatx4 pa = mfma16<MODE>(*reinterpret_cast<const float4*>(&Gs[qb + c][4 * g]), v4, z);  // dP[q 4g+i][key c]
-      const float4 l4 = *reinterpret_cast<const float4*>(&Ls[qb + 4 * g]);
-      const float4 d4 = *reinterpret_cast<const float4*>(&Ds[qb + 4 * g]);
+      const floatx4 sa = Op::mma(Qa[q0 + c][g], kb, z);   // S[q 4g+i][key c]
+      const floatx4 pa = Op::mma(Ga[q0 + c][g], vb, z);   // dP[q 4g+i][key c]
+      const float4 l4 = *reinterpret_cast<const float4*>(&Ls[q0 + 4 * g]);
+      const float4 d4 = *reinterpret_cast<const float4*>(&Ds[q0 + 4 * g]);
       const float lq[4] = {l4.x, l4.y, l4.z, l4.w}, dq[4] = {d4.x, d4.y, d4.z, d4.w};
       float p[4], ds[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int q = qb + 4 * g + i;
+        const int q = q0 + 4 * g + i;
         const bool ok = (q < nq) & kok & visible(i0 + q, jk, W, P);
         const float e = __builtin_amdgcn_exp2f(sa[i] - lq[i]);
         p[i] = ok ? e : 0.f;
         ds[i] = p[i] * (pa[i] - dq[i]);
       }
-      const int r0 = qb + 4 * g;
-      const float4 go = make_float4(Gs[r0][c], Gs[r0 + 1][c], Gs[r0 + 2][c], Gs[r0 + 3][c]);
-      const float4 qo = make_float4(Qs[r0][c], Qs[r0 + 1][c], Qs[r0 + 2][c], Qs[r0 + 3][c]);
-      dv = mfma16<MODE>(make_float4(p[0], p[1], p[2], p[3]), go, dv);     // dV[key][dim] += P^T[key][q] dO[q][dim]
-      dk = mfma16<MODE>(make_float4(ds[0], ds[1], ds[2], ds[3]), qo, dk); // dK[key][dim] += dS^T[key][q] Q[q][dim]
+      dv = Op::mma(Op::make(p[0], p[1], p[2], p[3]), Gb[c][q0 / 4 + g], dv);      // dV += P^T dO
+      dk = Op::mma(Op::make(ds[0], ds[1], ds[2], ds[3]), Qb[c][q0 / 4 + g], dk);  // dK += dS^T Q
     }
   }
 #pragma unroll

@@ -391,24 +391,34 @@ __global__ void pos_grad_kernel(const float* __restrict__ dX, int nsamp, int N, 
   }
 }
 
-// dT[tok][k] += sum over rows fed token tok: one workgroup per (tok, k).
-__global__ __launch_bounds__(256) void tok_grad_kernel(const float* __restrict__ dX, const int8_t* __restrict__ spins,
-                                                       int64_t rows, int N, int D, int dt, float* __restrict__ gtok) {
-  __shared__ float red[256];
-  const int tok = blockIdx.x / dt, k = blockIdx.x % dt;
-  float s = 0.f;
-  for (int64_t r = threadIdx.x; r < rows; r += 256) {
-    const int t = (int)(r % N);
-    const int tr = t == 0 ? 0 : (spins[r - 1] + 1) >> 1;
-    if (tr == tok) s += dX[r * D + k];
+// dT[tok][k] += sum over the rows fed token tok (vocab 2), in two fixed-order
+// steps: workgroup (slice, k) sums its slice of rows into part[slice][tok * dt + k],
+// then colsum_final_kernel adds the kColSlices partials.
+__global__ __launch_bounds__(256) void tok_grad_slices_kernel(const float* __restrict__ dX,
+                                                              const int8_t* __restrict__ spins, int64_t rows, int N,
+                                                              int D, int dt, float* __restrict__ part) {
+  __shared__ float red[2][4];
+  const int k = blockIdx.y;
+  const int64_t per = (rows + kColSlices - 1) / kColSlices;
+  const int64_t r0 = (int64_t)blockIdx.x * per, r1 = std::min<int64_t>(rows, r0 + per);
+  float s0 = 0.f, s1 = 0.f;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+    const bool one = (r % N != 0) && spins[r - 1] > 0;   // token of row r is s_{t-1} (0 at t = 0)
+    const float v = dX[r * D + k];
+    s0 += one ? 0.f : v;
+    s1 += one ? v : 0.f;
   }
-  red[threadIdx.x] = s;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o);
+    s1 += __shfl_xor(s1, o);
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { red[0][wave] = s0; red[1][wave] = s1; }
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) gtok[tok * dt + k] += red[0];
+  if (threadIdx.x < 2)
+    part[(size_t)blockIdx.x * 2 * dt + threadIdx.x * dt + k] =
+        red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
 }
 
 // ---------------------------------------------------------------- driver
@@ -487,8 +497,10 @@ static hipError_t backward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp
   const int64_t npos = (int64_t)N * (D - c.d_token);
   hipLaunchKernelGGL(pos_grad_kernel, dim3((int)std::min<int64_t>((npos + 255) / 256, 4096)), dim3(256), 0, s,
                      (const float*)f.dX, nsamp, N, D, c.d_token, G + m->po.pos);
-  hipLaunchKernelGGL(tok_grad_kernel, dim3(c.vocab * c.d_token), dim3(256), 0, s, (const float*)f.dX, spins, rows, N,
-                     D, c.d_token, G + m->po.tok);
+  hipLaunchKernelGGL(tok_grad_slices_kernel, dim3(kColSlices, c.d_token), dim3(256), 0, s, (const float*)f.dX, spins,
+                     rows, N, D, c.d_token, f.part);
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((2 * c.d_token + 255) / 256), dim3(256), 0, s, (const float*)f.part,
+                     2 * c.d_token, G + m->po.tok);
   return hipGetLastError();
 }
 

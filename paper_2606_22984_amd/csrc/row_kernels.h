@@ -3,6 +3,8 @@
 // packed weights with fused epilogues.
 #pragma once
 
+#include <type_traits>
+
 #include <algorithm>
 
 #include "device_common.h"
@@ -124,13 +126,14 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(const typename Mode<MODE
   }
 }
 
-// Row GEMM with an LDS-staged epilogue for the wide FFN outputs (K <= 128,
-// GELU / GELU' epilogues).  Each group of four 16-column tiles is computed into
+// Row GEMM with an LDS-staged epilogue for the wide outputs (K <= 128: the QKV
+// projection and FFN1 with their GELU / GELU' epilogues).  Each group of four 16-column tiles is computed into
 // a 64 x 64 tile in LDS; the workgroup then writes the row-major outputs as
 // 256-byte row segments and the feature-major copy as 256-byte column segments
 // (16-byte stores), instead of one scattered element per lane.
 //   EPI_GELU : h = acc + bias; hpre_out[r][n] = h, out[r][n] = GELU(h), outT[n][r] = GELU(h)
 //   EPI_DGELU: d = acc * GELU'(hpre_in[r][n]); out[r][n] = d, outT[n][r] = d
+//   EPI_STORE_KV: out[r][n] = acc + bias[n] in the K/V element type
 // (each output only if its pointer is set).
 template <typename T>
 __device__ __forceinline__ void store4(T* p, float a, float b, float c, float d) {
@@ -149,7 +152,9 @@ __global__ __launch_bounds__(256) void gemm_rows_staged_kernel(const typename Mo
                                                                EpiArgs e) {
   typedef typename Mode<MODE>::ActT AT;
   static_assert(K <= 128 && NOUT % 64 == 0, "staged row GEMM: K <= 128, NOUT a multiple of 64");
-  static_assert(EPI == EPI_GELU || EPI == EPI_DGELU, "staged row GEMM: GELU or GELU' epilogue");
+  static_assert(EPI == EPI_GELU || EPI == EPI_DGELU || EPI == EPI_STORE_KV,
+                "staged row GEMM: GELU, GELU' or K/V-type store epilogue");
+  typedef typename std::conditional<EPI == EPI_STORE_KV, typename Mode<MODE>::KvT, AT>::type OT;
   constexpr int KC = Mode<MODE>::KC;
   constexpr int LK = KC / 4;
   constexpr int NC = K / KC;
@@ -169,7 +174,7 @@ __global__ __launch_bounds__(256) void gemm_rows_staged_kernel(const typename Mo
       *reinterpret_cast<uint4*>(&af[cc][i]) = *reinterpret_cast<const uint4*>(arow + cc * KC + i);
   }
   const bool full = r0 + 64 <= rows;
-  AT* out = reinterpret_cast<AT*>(e.out);
+  OT* out = reinterpret_cast<OT*>(e.out);
   AT* outT = reinterpret_cast<AT*>(e.outT);
   for (int ng = 0; ng < NG; ++ng) {
     if constexpr (EPI == EPI_DGELU) {
@@ -198,6 +203,8 @@ __global__ __launch_bounds__(256) void gemm_rows_staged_kernel(const typename Mo
           const float hv = acc[i] + e.bias[ng * 64 + col];
           Eh[row][col] = hv;
           Ev[row][col] = gelu(hv);
+        } else if constexpr (EPI == EPI_STORE_KV) {
+          Ev[row][col] = acc[i] + e.bias[ng * 64 + col];
         } else {
           Ev[row][col] = acc[i] * gelu_grad(Eh[row][col]);
         }
@@ -220,7 +227,7 @@ __global__ __launch_bounds__(256) void gemm_rows_staged_kernel(const typename Mo
       }
     }
     // feature-major copy: thread -> (column, 4 rows); 16 threads cover the tile's 64 rows
-    if (outT) {
+    if (EPI != EPI_STORE_KV && outT) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int idx = tid + 256 * k, col = idx >> 4, q4 = (idx & 15) * 4;
@@ -242,7 +249,7 @@ template <int MODE, int K, int NOUT, int EPI>
 inline hipError_t gemm_rows(const typename Mode<MODE>::ActT* A, int64_t rows, const void* pack, const EpiArgs& e,
                             hipStream_t s) {
   const int grid = (int)((rows + 63) / 64);
-  if constexpr ((EPI == EPI_GELU || EPI == EPI_DGELU) && K <= 128 && NOUT % 64 == 0)
+  if constexpr ((EPI == EPI_GELU || EPI == EPI_DGELU || EPI == EPI_STORE_KV) && K <= 128 && NOUT % 64 == 0)
     hipLaunchKernelGGL((gemm_rows_staged_kernel<MODE, K, NOUT, EPI>), dim3(grid), dim3(256), 0, s, A, rows,
                        reinterpret_cast<const uint4*>(pack), e);
   else
