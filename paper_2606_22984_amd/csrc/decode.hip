@@ -1,11 +1,13 @@
 // KV-cached ancestral sampling (Alg. 2 of the paper) for gfx950.
 //
-// One workgroup (4 waves) owns a tile of kM = 16 samples and runs every step
+// One workgroup (8 waves) owns a tile of kM = 32 samples and runs every step
 // t = 0..N-1 and every layer without leaving the kernel: samples are
 // independent, so no grid-wide synchronisation is ever needed.  Per layer step:
 //   LN1 (16 lanes per sample, shuffle reductions)
-//   QKV = LN1(h) W^T + b on MFMA (16 samples x 3d), k_t and v_t go straight
-//        from the MFMA accumulators to the sample's KV cache slot
+//   QKV = LN1(h) W^T + b on MFMA (32 samples x 3d: every weight fragment a wave
+//        loads feeds both 16-sample row tiles, which halves the weight traffic
+//        per sample), k_t and v_t go straight from the MFMA accumulators to the
+//        sample's KV cache slot
 //   attention: one wave per sample, K/V rows streamed with 16-byte coalesced
 //        loads, per-head dot products and an online softmax reduced with lane
 //        shuffles; the heads' concatenation is added to h (no W_O)
@@ -18,8 +20,9 @@
 
 namespace fvan {
 
-constexpr int kM = 16;
-constexpr int kThreads = 256;
+constexpr int kM = 32;                 // samples per workgroup (two 16-row MFMA tiles)
+constexpr int kThreads = 512;
+constexpr int kWaves = kThreads / 64;
 
 int decode_tile_samples() { return kM; }
 
@@ -76,19 +79,23 @@ __device__ __forceinline__ void ln_rows(DecodeSmem<D, MODE>& sm, const float* __
   }
 }
 
-// acc(16 x 16 tile nt) = A[16 x K] (LDS, row stride lda elements) . pack tile nt.
+// acc0, acc1 (16 x 16 tile nt of rows 0..15 and 16..31) = A[32 x K] (LDS, row
+// stride lda elements) . pack tile nt; each weight fragment is loaded once.
 // lo_u4: distance (in 16-byte units) from a split pack's hi part to its lo part.
 template <int MODE, int K>
-__device__ __forceinline__ floatx4 mfma_rowtile(const typename Mode<MODE>::ActT* A, int lda,
-                                                const uint4* __restrict__ pack, size_t lo_u4, int nt, int lane) {
+__device__ __forceinline__ void mfma_rowtiles(const typename Mode<MODE>::ActT* A, int lda,
+                                              const uint4* __restrict__ pack, size_t lo_u4, int nt, int lane,
+                                              floatx4& acc0, floatx4& acc1) {
   constexpr int KC = Mode<MODE>::KC;
   constexpr int NC = K / KC;
-  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  acc0 = floatx4{0.f, 0.f, 0.f, 0.f};
+  acc1 = acc0;
   const typename Mode<MODE>::ActT* arow = A + (lane & 15) * lda + (lane >> 4) * (KC / 4);
+  const typename Mode<MODE>::ActT* arow1 = arow + 16 * lda;
   const uint4* bp = pack + (size_t)nt * NC * 64 + lane;
-#pragma unroll 2
-  for (int c = 0; c < NC; ++c) acc = Frag<MODE>::step(arow + c * KC, bp + c * 64, bp + c * 64 + lo_u4, acc);
-  return acc;
+#pragma unroll 1
+  for (int c = 0; c < NC; ++c)
+    Frag<MODE>::step2(arow + c * KC, arow1 + c * KC, bp + c * 64, bp + c * 64 + lo_u4, acc0, acc1);
 }
 
 template <int D, int MODE>
@@ -137,14 +144,15 @@ __device__ void decode_tile(DecodeSmem<D, MODE>& sm, const DecodeUnit& U, int lo
       // ---- QKV projection; k_t, v_t appended to the cache ----
       {
         const uint4* pk = reinterpret_cast<const uint4*>(wl + U.p_qkv);
-        for (int nt = wave; nt < 3 * D / 16; nt += 4) {
-          floatx4 acc = mfma_rowtile<MODE, D>(&sm.a[0][0], Sm::LDA, pk, (size_t)3 * D * D / 8, nt, lane);
+        for (int nt = wave; nt < 3 * D / 16; nt += kWaves) {
+          floatx4 acc[2];
+          mfma_rowtiles<MODE, D>(&sm.a[0][0], Sm::LDA, pk, (size_t)3 * D * D / 8, nt, lane, acc[0], acc[1]);
           const int n = nt * 16 + (lane & 15);
           const float bias = lp[U.o_qkv_b + n];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int row = 4 * (lane >> 4) + i;
-            const float val = acc[i] + bias;
+          for (int ri = 0; ri < 8; ++ri) {
+            const int row = 16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3);
+            const float val = acc[ri >> 2][ri & 3] + bias;
             if (n < D) {
               sm.u.q[row][n] = val;
             } else if (row < nb) {
@@ -167,11 +175,11 @@ __device__ void decode_tile(DecodeSmem<D, MODE>& sm, const DecodeUnit& U, int lo
         const int lrow = lane / LPR;
         const int lcol = (lane % LPR) * VEC;
         const int per = (nvis + RPL * UNR - 1) / (RPL * UNR);   // batches per sample
-        const int nsw = nb > wave ? (nb - wave + 3) / 4 : 0;    // samples of this wave
+        const int nsw = nb > wave ? (nb - wave + kWaves - 1) / kWaves : 0;   // samples of this wave
         const int total = per * nsw;
         uint4 kr[UNR], vr[UNR];
         auto issue = [&](int bi, uint4* kk, uint4* vv) {
-          const int m = wave + 4 * (bi / per);
+          const int m = wave + kWaves * (bi / per);
           const int s0 = (bi % per) * RPL * UNR;
           const T* Kb = kvbase + ((size_t)(b0 + m) * nl + l) * 2 * plane;
 #pragma unroll
@@ -189,7 +197,7 @@ __device__ void decode_tile(DecodeSmem<D, MODE>& sm, const DecodeUnit& U, int lo
         for (int bi = 0; bi < total; ++bi) {
           uint4 kn[UNR], vn[UNR];
           if (bi + 1 < total) issue(bi + 1, kn, vn);
-          const int m = wave + 4 * (bi / per);
+          const int m = wave + kWaves * (bi / per);
           const int part = bi % per;
           if (part == 0) {
 #pragma unroll
@@ -261,24 +269,27 @@ __device__ void decode_tile(DecodeSmem<D, MODE>& sm, const DecodeUnit& U, int lo
       __syncthreads();
       {
         const uint4* p1 = reinterpret_cast<const uint4*>(wl + U.p_ffn1);
-        for (int nt = wave; nt < 4 * D / 16; nt += 4) {
-          floatx4 acc = mfma_rowtile<MODE, D>(&sm.a[0][0], Sm::LDA, p1, (size_t)4 * D * D / 8, nt, lane);
+        for (int nt = wave; nt < 4 * D / 16; nt += kWaves) {
+          floatx4 acc[2];
+          mfma_rowtiles<MODE, D>(&sm.a[0][0], Sm::LDA, p1, (size_t)4 * D * D / 8, nt, lane, acc[0], acc[1]);
           const int n = nt * 16 + (lane & 15);
           const float bias = lp[U.o_ffn1_b + n];
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            sm.u.hid[4 * (lane >> 4) + i][n] = from_f<typename Mode<MODE>::ActT>(gelu(acc[i] + bias));
+          for (int ri = 0; ri < 8; ++ri)
+            sm.u.hid[16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3)][n] =
+                from_f<typename Mode<MODE>::ActT>(gelu(acc[ri >> 2][ri & 3] + bias));
         }
       }
       __syncthreads();
       {
         const uint4* p2 = reinterpret_cast<const uint4*>(wl + U.p_ffn2);
-        for (int nt = wave; nt < D / 16; nt += 4) {
-          floatx4 acc = mfma_rowtile<MODE, 4 * D>(&sm.u.hid[0][0], Sm::LDH, p2, (size_t)4 * D * D / 8, nt, lane);
+        for (int nt = wave; nt < D / 16; nt += kWaves) {
+          floatx4 acc[2];
+          mfma_rowtiles<MODE, 4 * D>(&sm.u.hid[0][0], Sm::LDH, p2, (size_t)4 * D * D / 8, nt, lane, acc[0], acc[1]);
           const int n = nt * 16 + (lane & 15);
           const float bias = lp[U.o_ffn2_b + n];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) sm.h[4 * (lane >> 4) + i][n] += acc[i] + bias;
+          for (int ri = 0; ri < 8; ++ri) sm.h[16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3)][n] += acc[ri >> 2][ri & 3] + bias;
         }
       }
       __syncthreads();

@@ -114,10 +114,32 @@ template <> struct Frag<0> {
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, __uint_as_float(bv.w), acc, 0, 0, 0);
     return acc;
   }
+  // two 16-row A tiles against one B fragment (loaded once)
+  static __device__ __forceinline__ void step2(const float* a0, const float* a1, const uint4* b, const uint4*,
+                                               floatx4& acc0, floatx4& acc1) {
+    const uint4 bv = *b;
+    const float4 x = *reinterpret_cast<const float4*>(a0), y = *reinterpret_cast<const float4*>(a1);
+    const float b0 = __uint_as_float(bv.x), b1 = __uint_as_float(bv.y), b2 = __uint_as_float(bv.z),
+                b3 = __uint_as_float(bv.w);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, b0, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(y.x, b0, acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, b1, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(y.y, b1, acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, b2, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(y.z, b2, acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, b3, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(y.w, b3, acc1, 0, 0, 0);
+  }
 };
 template <> struct Frag<1> {
   static __device__ __forceinline__ floatx4 step(const __bf16* a, const uint4* b, const uint4*, floatx4 acc) {
     return mfma_bf16(*reinterpret_cast<const uint4*>(a), *b, acc);
+  }
+  static __device__ __forceinline__ void step2(const __bf16* a0, const __bf16* a1, const uint4* b, const uint4*,
+                                               floatx4& acc0, floatx4& acc1) {
+    const uint4 bv = *b;
+    acc0 = mfma_bf16(*reinterpret_cast<const uint4*>(a0), bv, acc0);
+    acc1 = mfma_bf16(*reinterpret_cast<const uint4*>(a1), bv, acc1);
   }
 };
 template <> struct Frag<2> {
@@ -132,6 +154,26 @@ template <> struct Frag<2> {
     acc = mfma_bf16(al, bh, acc);
     acc = mfma_bf16(ah, bl, acc);
     return mfma_bf16(ah, bh, acc);
+  }
+  static __device__ __forceinline__ void split_a(const float* a, uint4& ah, uint4& al) {
+    float x[8];
+    const float4 a0 = *reinterpret_cast<const float4*>(a);
+    const float4 a1 = *reinterpret_cast<const float4*>(a + 4);
+    x[0] = a0.x; x[1] = a0.y; x[2] = a0.z; x[3] = a0.w; x[4] = a1.x; x[5] = a1.y; x[6] = a1.z; x[7] = a1.w;
+    split8(x, ah, al);
+  }
+  static __device__ __forceinline__ void step2(const float* a0, const float* a1, const uint4* b, const uint4* blo,
+                                               floatx4& acc0, floatx4& acc1) {
+    uint4 xh, xl, yh, yl;
+    split_a(a0, xh, xl);
+    split_a(a1, yh, yl);
+    const uint4 bh = *b, bl = *blo;
+    acc0 = mfma_bf16(xl, bh, acc0);
+    acc1 = mfma_bf16(yl, bh, acc1);
+    acc0 = mfma_bf16(xh, bl, acc0);
+    acc1 = mfma_bf16(yh, bl, acc1);
+    acc0 = mfma_bf16(xh, bh, acc0);
+    acc1 = mfma_bf16(yh, bh, acc1);
   }
 };
 
