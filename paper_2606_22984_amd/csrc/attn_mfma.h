@@ -113,6 +113,22 @@ struct KeyRange {
   __device__ __forceinline__ int pos(int v) const { return v < pend ? v : bstart + (v - pend); }
 };
 
+// The virtual key indices (KeyRange order) that query t of the tile sees, as two
+// intervals [0, a1) and [b0, b0 + bw): the prefix keys j <= t, then the band keys
+// t - W <= j <= t (band keys are >= P by construction).  Equivalent to visible()
+// on every key of the range, at two compares per key instead of a select and five.
+struct QueryVis {
+  int a1, b0, bw;
+  __device__ QueryVis(const KeyRange& kr, int t, int W, bool ok) {
+    a1 = ok ? min(kr.pend, t + 1) : 0;
+    b0 = kr.pend + max(0, t - W - kr.bstart);
+    bw = ok ? max(0, kr.pend + t - kr.bstart + 1 - b0) : 0;
+  }
+  __device__ __forceinline__ bool operator()(int v) const {
+    return (v < a1) | ((unsigned)(v - b0) < (unsigned)bw);
+  }
+};
+
 // Stages kKeyChunk keys (one head's K and V slices) of a query tile's visible
 // range: every thread loads 16-byte chunks of K and V into registers (the next
 // chunk is fetched while the current one is processed), commit() writes them to
@@ -201,6 +217,7 @@ __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV,
   }
   const OT qb = aop<MODE>(q4);                       // B operand Q^T[dim 4g..][query c]
   const KeyRange kr(t0, t1, W, P);
+  const QueryVis vis(kr, tq, W, qok);
   KeyStager<KT> st;
   st.fetch(QKV, rowbase, D, h, kr, 0);
   float mx = -INFINITY, l = 0.f;
@@ -224,8 +241,7 @@ __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV,
         if (kb < nv) acc = Op::mma(Ka[kb + c][g], qb, acc);   // S^T[key 4g+i][query c]
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int kv = kb + 4 * g + i;
-          const bool ok = (kv < nv) & qok & visible(tq, kr.pos(v0 + kv), W, P);
+          const bool ok = vis(v0 + kb + 4 * g + i);   // keys past nv lie beyond kr.nk: never visible
           s[4 * u + i] = ok ? acc[i] : -INFINITY;
           bmax = fmaxf(bmax, s[4 * u + i]);
         }
@@ -291,6 +307,7 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_mfma(const KT* __restrict__ Q
   st.fetch(QKV, rowbase, D, h, kr, 0);
   const int tq = t0 + 16 * wave + c;
   const bool qok = tq < N;
+  const QueryVis vis(kr, tq, W, qok);
   const int64_t r = rowbase + tq;
   float4 q4 = make_float4(0.f, 0.f, 0.f, 0.f), g4 = q4;
   float lse = 0.f, delta = 0.f;
@@ -325,8 +342,7 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_mfma(const KT* __restrict__ Q
       float ds[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int kv = kb + 4 * g + i;
-        const bool ok = (kv < nv) & qok & visible(tq, kr.pos(v0 + kv), W, P);
+        const bool ok = vis(v0 + kb + 4 * g + i);
         const float e = __builtin_amdgcn_exp2f(sa[i] - lse);
         const float p = ok ? e : 0.f;
         ds[i] = p * (pa[i] - delta);
@@ -389,6 +405,8 @@ __global__ __launch_bounds__(256) void attn_bwd_dkv_mfma(const KT* __restrict__ 
   }
   const OT kb = aop<MODE>(k4), vb = aop<MODE>(v4);  // B operands K^T, V^T [dim 4g..][key c]
   const int qend = j0 < P ? N : min(N, j1 + W);
+  // queries that see this lane's key: jk <= iq < qhi (any later query for a prefix key)
+  const int qw = kok ? max(0, min(jk < P ? N : jk + W + 1, qend) - jk) : 0;
   // staging roles: dO row tid/4, quarter tid%4; Q row tid/QC, chunk tid%QC (tid < 64*QC);
   // LSE (tid < 64) or DELTA (64 <= tid < 128) of row tid%64
   const int gr = tid >> 2, gc = (tid & 3) * 4;
@@ -438,8 +456,7 @@ __global__ __launch_bounds__(256) void attn_bwd_dkv_mfma(const KT* __restrict__ 
       float p[4], ds[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int q = q0 + 4 * g + i;
-        const bool ok = (q < nq) & kok & visible(i0 + q, jk, W, P);
+        const bool ok = (unsigned)(i0 + q0 + 4 * g + i - jk) < (unsigned)qw;   // also excludes iq >= qend
         const float e = __builtin_amdgcn_exp2f(sa[i] - lq[i]);
         p[i] = ok ? e : 0.f;
         ds[i] = p[i] * (pa[i] - dq[i]);
