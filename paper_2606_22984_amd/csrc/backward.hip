@@ -13,9 +13,11 @@
 // gradient falls out as one more output column; partial sums are reduced in a
 // fixed order and added to the caller's gradient vector.
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 #include "fvan_model.h"
+
 #include "passes.h"
 #include "row_kernels.h"
 #include "attn_mfma.h"
@@ -184,16 +186,21 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
                                                     const typename Mode<MODE>::ActT* __restrict__ B, int64_t ldb,
                                                     int64_t K, int64_t kper, int m_total, float* __restrict__ part) {
   typedef typename Mode<MODE>::ActT AT;
+  // split mode stages each operand already split into BF16 hi and lo planes, so a
+  // K chunk is converted once instead of once per wave that multiplies it
+  constexpr bool SPLIT = Mode<MODE>::SPLIT;
+  typedef typename std::conditional<SPLIT, __bf16, AT>::type ST;
+  constexpr int NPL = SPLIT ? 2 : 1;                // LDS planes (hi, lo)
   constexpr int KC = Mode<MODE>::KC;
   constexpr int LK = KC / 4;
-  constexpr int PADK = KC + 16 / (int)sizeof(AT);
+  constexpr int PADK = KC + 16 / (int)sizeof(ST);
   constexpr int MT = M / 16, NT = NB / 16;
   typedef WaveGrid<MT> G;
   constexpr int RT = G::RT, WCG = G::WCG;
   constexpr int CT = (NT + WCG - 1) / WCG;
   constexpr int VPL = 16 / (int)sizeof(AT);        // elements per 16-byte load
-  __shared__ __attribute__((aligned(16))) AT As[M][PADK];
-  __shared__ __attribute__((aligned(16))) AT Bs[NB][PADK];
+  __shared__ __attribute__((aligned(16))) ST As[NPL][M][PADK];
+  __shared__ __attribute__((aligned(16))) ST Bs[NPL][NB][PADK];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave / WCG, wc = wave % WCG;
   const int s = blockIdx.x;
@@ -237,16 +244,55 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
       const int x = threadIdx.x + 512 * u;
       if (x < NPIECE) {
         const int row = x / (KC / VPL), piece = x % (KC / VPL);
-        AT* dst = row < M ? &As[row][piece * VPL] : &Bs[row - M][piece * VPL];
-        *reinterpret_cast<uint4*>(dst) = pre[u];
+        ST* hi_dst = row < M ? &As[0][row][piece * VPL] : &Bs[0][row - M][piece * VPL];
+        if constexpr (SPLIT) {
+          ST* lo_dst = row < M ? &As[1][row][piece * VPL] : &Bs[1][row - M][piece * VPL];
+          const float f[4] = {__uint_as_float(pre[u].x), __uint_as_float(pre[u].y), __uint_as_float(pre[u].z),
+                              __uint_as_float(pre[u].w)};
+          bf16x4 hi, lo;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            hi[e] = (__bf16)f[e];
+            lo[e] = (__bf16)(f[e] - (float)hi[e]);
+          }
+          *reinterpret_cast<bf16x4*>(hi_dst) = hi;
+          *reinterpret_cast<bf16x4*>(lo_dst) = lo;
+        } else {
+          *reinterpret_cast<uint4*>(hi_dst) = pre[u];
+        }
       }
     }
     __syncthreads();
     if (k + KC < ke) fetch(k + KC);
+    if constexpr (SPLIT) {
+      // lane fragments: 8 consecutive k of one row, hi and lo planes
+      uint4 ah[RT], al[RT];
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        const int row = (wr * RT + i) * 16 + (lane & 15), k8 = (lane >> 4) * LK;
+        ah[i] = *reinterpret_cast<const uint4*>(&As[0][row][k8]);
+        al[i] = *reinterpret_cast<const uint4*>(&As[1][row][k8]);
+      }
+#pragma unroll
+      for (int j = 0; j < CT; ++j) {
+        const int ct = wc * CT + j;
+        if (ct < NT) {
+          const int row = ct * 16 + (lane & 15), k8 = (lane >> 4) * LK;
+          const uint4 bh = *reinterpret_cast<const uint4*>(&Bs[0][row][k8]);
+          const uint4 bl = *reinterpret_cast<const uint4*>(&Bs[1][row][k8]);
+#pragma unroll
+          for (int i = 0; i < RT; ++i) {
+            acc[i][j] = mfma_bf16(al[i], bh, acc[i][j]);
+            acc[i][j] = mfma_bf16(ah[i], bl, acc[i][j]);
+            acc[i][j] = mfma_bf16(ah[i], bh, acc[i][j]);
+          }
+        }
+      }
+    } else {
     alignas(16) AT af[RT][LK];
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
-      const AT* ap = &As[(wr * RT + i) * 16 + (lane & 15)][(lane >> 4) * LK];
+      const AT* ap = &As[0][(wr * RT + i) * 16 + (lane & 15)][(lane >> 4) * LK];
 #pragma unroll
       for (int e = 0; e < LK; e += VPL) *reinterpret_cast<uint4*>(&af[i][e]) = *reinterpret_cast<const uint4*>(ap + e);
     }
@@ -255,12 +301,13 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
       const int ct = wc * CT + j;
       if (ct < NT) {
         alignas(16) AT bf[LK];
-        const AT* bp = &Bs[ct * 16 + (lane & 15)][(lane >> 4) * LK];
+        const AT* bp = &Bs[0][ct * 16 + (lane & 15)][(lane >> 4) * LK];
 #pragma unroll
         for (int e = 0; e < LK; e += VPL) *reinterpret_cast<uint4*>(&bf[e]) = *reinterpret_cast<const uint4*>(bp + e);
 #pragma unroll
         for (int i = 0; i < RT; ++i) acc[i][j] = FragAB<MODE>::step(af[i], bf, acc[i][j]);
       }
+    }
     }
     __syncthreads();
   }
@@ -303,9 +350,10 @@ static hipError_t wgrad(fvan_model* m, const void* A, const void* B, int64_t K, 
   int64_t kper = (K + S - 1) / S;
   kper = (kper + KC - 1) / KC * KC;
   S = (int)((K + kper - 1) / kper);
-  // outputs of 512 rows are split over two workgroups per K slice (keeps the
-  // accumulators and the prefetch registers of a wave within 256 VGPRs)
-  constexpr int MS = M >= 512 ? M / 2 : M;
+  // outputs of 512 rows or 512 + 16 columns are split over two workgroups per K
+  // slice by rows (keeps the accumulators and the prefetch registers of a wave
+  // within 256 VGPRs)
+  constexpr int MS = (M >= 512 || NB >= 512) ? M / 2 : M;
   hipLaunchKernelGGL((wgrad_kernel<MODE, MS, NB>), dim3(S, M / MS), dim3(512), 0, s, (const AT*)A, f.ldT,
                      (const AT*)B, f.ldT, K, kper, M, f.part);
   const int total = M * (Nw + 1);
