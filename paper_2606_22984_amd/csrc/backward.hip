@@ -184,7 +184,8 @@ struct WaveGrid {
 template <int MODE, int M, int NB>
 __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::ActT* __restrict__ A, int64_t lda,
                                                     const typename Mode<MODE>::ActT* __restrict__ B, int64_t ldb,
-                                                    int64_t K, int64_t kper, int m_total, float* __restrict__ part) {
+                                                    int64_t K, int64_t kper, int m_total, int n_total,
+                                                    float* __restrict__ part) {
   typedef typename Mode<MODE>::ActT AT;
   // split mode stages each operand already split into BF16 hi and lo planes, so a
   // K chunk is converted once instead of once per wave that multiplies it
@@ -205,6 +206,7 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
   const int wr = wave / WCG, wc = wave % WCG;
   const int s = blockIdx.x;
   A += (int64_t)blockIdx.y * M * lda;              // this workgroup's block of M output rows
+  B += (int64_t)blockIdx.z * NB * ldb;             // and of NB output columns
   const int64_t kb = (int64_t)s * kper;
   const int64_t ke = std::min<int64_t>(K, kb + kper);
   floatx4 acc[RT][CT];
@@ -311,7 +313,7 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
     }
     __syncthreads();
   }
-  float* out = part + ((size_t)s * m_total + (size_t)blockIdx.y * M) * NB;
+  float* out = part + ((size_t)s * m_total + (size_t)blockIdx.y * M) * n_total + (size_t)blockIdx.z * NB;
 #pragma unroll
   for (int i = 0; i < RT; ++i) {
 #pragma unroll
@@ -320,7 +322,7 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
       if (ct < NT) {
         const int n = ct * 16 + (lane & 15);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) out[(size_t)((wr * RT + i) * 16 + 4 * (lane >> 4) + q) * NB + n] = acc[i][j][q];
+        for (int q = 0; q < 4; ++q) out[(size_t)((wr * RT + i) * 16 + 4 * (lane >> 4) + q) * n_total + n] = acc[i][j][q];
       }
     }
   }
@@ -350,12 +352,14 @@ static hipError_t wgrad(fvan_model* m, const void* A, const void* B, int64_t K, 
   int64_t kper = (K + S - 1) / S;
   kper = (kper + KC - 1) / KC * KC;
   S = (int)((K + kper - 1) / kper);
-  // outputs of 512 rows or 512 + 16 columns are split over two workgroups per K
-  // slice by rows (keeps the accumulators and the prefetch registers of a wave
-  // within 256 VGPRs)
-  constexpr int MS = (M >= 512 || NB >= 512) ? M / 2 : M;
-  hipLaunchKernelGGL((wgrad_kernel<MODE, MS, NB>), dim3(S, M / MS), dim3(512), 0, s, (const AT*)A, f.ldT,
-                     (const AT*)B, f.ldT, K, kper, M, f.part);
+  // large outputs are split over several workgroups per K slice (keeps the
+  // accumulators and the prefetch registers of a wave within 256 VGPRs): 512 rows
+  // by rows, 512 + 16 columns into three column blocks, so that the split re-reads
+  // the smaller operand
+  constexpr int MS = M >= 512 ? M / 2 : M;
+  constexpr int NBS = NB >= 512 && NB % 48 == 0 ? NB / 3 : NB;
+  hipLaunchKernelGGL((wgrad_kernel<MODE, MS, NBS>), dim3(S, M / MS, NB / NBS), dim3(512), 0, s, (const AT*)A,
+                     f.ldT, (const AT*)B, f.ldT, K, kper, M, NB, f.part);
   const int total = M * (Nw + 1);
   hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(std::min(1024, (total + 255) / 256)), dim3(256), 0, s,
                      (const float*)f.part, S, M, NB, Nw, gW, gb);
