@@ -177,6 +177,40 @@ template <> struct Frag<2> {
   }
 };
 
+// An A fragment held in MFMA-ready form, for reuse against many B fragments:
+// load() reads the lane's LK elements (splitting them once in split mode) and
+// mma() multiplies by one B fragment (hi at b, lo at blo in split mode), with
+// the same products as Frag<MODE>::step.
+template <int MODE> struct FragA;
+template <> struct FragA<0> {
+  float4 v;
+  __device__ __forceinline__ void load(const float* a) { v = *reinterpret_cast<const float4*>(a); }
+  __device__ __forceinline__ floatx4 mma(const uint4* b, const uint4*, floatx4 acc) const {
+    const uint4 bv = *b;
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, __uint_as_float(bv.x), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v.y, __uint_as_float(bv.y), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v.z, __uint_as_float(bv.z), acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(v.w, __uint_as_float(bv.w), acc, 0, 0, 0);
+  }
+};
+template <> struct FragA<1> {
+  uint4 v;
+  __device__ __forceinline__ void load(const __bf16* a) { v = *reinterpret_cast<const uint4*>(a); }
+  __device__ __forceinline__ floatx4 mma(const uint4* b, const uint4*, floatx4 acc) const {
+    return mfma_bf16(v, *b, acc);
+  }
+};
+template <> struct FragA<2> {
+  uint4 h, l;
+  __device__ __forceinline__ void load(const float* a) { Frag<2>::split_a(a, h, l); }
+  __device__ __forceinline__ floatx4 mma(const uint4* b, const uint4* blo, floatx4 acc) const {
+    const uint4 bh = *b, bl = *blo;
+    acc = mfma_bf16(l, bh, acc);
+    acc = mfma_bf16(h, bl, acc);
+    return mfma_bf16(h, bh, acc);
+  }
+};
+
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float x) {
   // d/dx [x Phi(x)] = Phi(x) + x phi(x)

@@ -101,16 +101,11 @@ hipError_t forward_layer(fvan_model* m, int l, int64_t rows, int nsamp, hipStrea
                      (const KT*)QKV, X, XM, LSE, c.n_spins, D, H, c.window, m->kg.P);
   hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(lgrid), dim3(256), 0, s, (const float*)XM, rows,
                      lp + m->po.ln2_g, lp + m->po.ln2_b, (AT*)f.A, (AT*)nullptr, (int64_t)0);
-  EpiArgs e1{};
-  e1.bias = lp + m->po.ffn1_b;
-  e1.out = f.HID;
-  err = gemm_rows<MODE, D, 4 * D, EPI_GELU>((const AT*)f.A, rows, wl + m->pk.ffn1, e1, s);
-  if (err != hipSuccess) return err;
-  EpiArgs e2{};
-  e2.bias = lp + m->po.ffn2_b;
-  e2.resid = XM;
-  e2.out = Xn;
-  return gemm_rows<MODE, 4 * D, D, EPI_RESID>((const AT*)f.HID, rows, wl + m->pk.ffn2, e2, s);
+  hipLaunchKernelGGL((ffn_fused_kernel<MODE, D>), dim3((int)((rows + kFfnRows - 1) / kFfnRows)), dim3(256), 0, s,
+                     (const AT*)f.A, rows,
+                     reinterpret_cast<const uint4*>(wl + m->pk.ffn1), reinterpret_cast<const uint4*>(wl + m->pk.ffn2),
+                     lp + m->po.ffn1_b, lp + m->po.ffn2_b, (const float*)XM, Xn);
+  return hipGetLastError();
 }
 
 template <int MODE, int D>

@@ -78,18 +78,20 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(const typename Mode<MODE
   const int64_t ra = std::min<int64_t>(rbase + (lane & 15), rows - 1);   // clamp the A row; stores are guarded
   const AT* arow = A + ra * K + (lane >> 4) * LK;
   if constexpr (K <= 128) {
-    alignas(16) AT af[NC][LK];
+    FragA<MODE> fa[NC];                      // the wave's A fragments, converted once
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
+      alignas(16) AT af[LK];
 #pragma unroll
       for (int i = 0; i < LK; i += 16 / (int)sizeof(AT))
-        *reinterpret_cast<uint4*>(&af[c][i]) = *reinterpret_cast<const uint4*>(arow + c * KC + i);
+        *reinterpret_cast<uint4*>(&af[i]) = *reinterpret_cast<const uint4*>(arow + c * KC + i);
+      fa[c].load(af);
     }
     for (int nt = 0; nt < NT; ++nt) {
       floatx4 acc = {0.f, 0.f, 0.f, 0.f};
       const uint4* bp = pack + (size_t)nt * NC * 64 + lane;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) acc = Frag<MODE>::step(af[c], bp + c * 64, bp + c * 64 + LO, acc);
+      for (int c = 0; c < NC; ++c) acc = fa[c].mma(bp + c * 64, bp + c * 64 + LO, acc);
       const int n = nt * 16 + (lane & 15);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -108,10 +110,12 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(const typename Mode<MODE
 #pragma unroll
       for (int i = 0; i < LK; i += 16 / (int)sizeof(AT))
         *reinterpret_cast<uint4*>(&af[i]) = *reinterpret_cast<const uint4*>(arow + c * KC + i);
+      FragA<MODE> fa;
+      fa.load(af);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         const uint4* b = bp + ((size_t)nt * NC + c) * 64;
-        acc[nt] = Frag<MODE>::step(af, b, b + LO, acc[nt]);
+        acc[nt] = fa.mma(b, b + LO, acc[nt]);
       }
     }
 #pragma unroll
@@ -166,12 +170,14 @@ __global__ __launch_bounds__(256) void gemm_rows_staged_kernel(const typename Mo
   const int64_t r0 = (int64_t)blockIdx.x * 64;
   const int64_t ra = std::min<int64_t>(r0 + wave * 16 + c, rows - 1);   // clamp the A row; stores are guarded
   const AT* arow = A + ra * K + g * LK;
-  alignas(16) AT af[NC][LK];
+  FragA<MODE> fa[NC];                        // the wave's A fragments, converted once
 #pragma unroll
   for (int cc = 0; cc < NC; ++cc) {
+    alignas(16) AT af[LK];
 #pragma unroll
     for (int i = 0; i < LK; i += 16 / (int)sizeof(AT))
-      *reinterpret_cast<uint4*>(&af[cc][i]) = *reinterpret_cast<const uint4*>(arow + cc * KC + i);
+      *reinterpret_cast<uint4*>(&af[i]) = *reinterpret_cast<const uint4*>(arow + cc * KC + i);
+    fa[cc].load(af);
   }
   const bool full = r0 + 64 <= rows;
   OT* out = reinterpret_cast<OT*>(e.out);
@@ -194,7 +200,7 @@ __global__ __launch_bounds__(256) void gemm_rows_staged_kernel(const typename Mo
       floatx4 acc = {0.f, 0.f, 0.f, 0.f};
       const uint4* bp = pack + (size_t)nt * NC * 64 + lane;
 #pragma unroll
-      for (int cc = 0; cc < NC; ++cc) acc = Frag<MODE>::step(af[cc], bp + cc * 64, bp + cc * 64 + LO, acc);
+      for (int cc = 0; cc < NC; ++cc) acc = fa[cc].mma(bp + cc * 64, bp + cc * 64 + LO, acc);
       const int col = 16 * u + c;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -242,6 +248,108 @@ __global__ __launch_bounds__(256) void gemm_rows_staged_kernel(const typename Mo
       }
     }
     __syncthreads();
+  }
+}
+
+// Fused feed-forward block of the teacher-forced forward pass:
+//   out[r] = resid[r] + W2 GELU(W1 a[r] + b1) + b2,   W1 [4D x D], W2 [D x 4D].
+// 128 rows per workgroup, one wave per 32 rows (two 16-row MFMA tiles, so every
+// weight fragment a wave loads feeds both).  A wave's hidden activations go
+// through a wave-private LDS tile, 64 hidden units at a time, straight into the
+// W2 product, so the 4D-wide hidden layer never reaches HBM.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+constexpr int kFfnRows = 128;                // rows per fused-FFN workgroup
+
+template <int MODE, int D>
+__global__ __launch_bounds__(256) void ffn_fused_kernel(const typename Mode<MODE>::ActT* __restrict__ A,
+                                                        int64_t rows, const uint4* __restrict__ p1,
+                                                        const uint4* __restrict__ p2, const float* __restrict__ b1,
+                                                        const float* __restrict__ b2, const float* __restrict__ resid,
+                                                        float* __restrict__ out) {
+  typedef typename Mode<MODE>::ActT AT;
+  constexpr int KC = Mode<MODE>::KC;
+  constexpr int LK = KC / 4;                 // A elements per lane per chunk
+  constexpr int NC1 = D / KC;                // K chunks of the W1 product
+  constexpr int HC = 64;                     // hidden units per chunk
+  constexpr int NH = 4 * D / HC;             // hidden chunks
+  constexpr int NT1 = HC / 16;               // W1 output tiles per hidden chunk
+  constexpr int NT2 = D / 16;                // W2 output tiles
+  constexpr int NC2 = 4 * D / KC;            // K chunks of the W2 product
+  constexpr int NC2H = HC / KC;              // ... per hidden chunk
+  constexpr size_t LO = (size_t)4 * D * D / 8;   // hi-to-lo distance of a split pack (both matrices 4D^2)
+  constexpr int LDH = HC + 16 / (int)sizeof(AT);
+  __shared__ __align__(16) AT Hs[4][32][LDH];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+  const int64_t rbase = (int64_t)blockIdx.x * kFfnRows + wave * 32;
+  if (rbase >= rows) return;                 // no block-wide barrier below
+  FragA<MODE> fa[2][NC1];                    // both row tiles' A fragments, converted once
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    const int64_t ra = std::min<int64_t>(rbase + 16 * rt + c, rows - 1);
+    const AT* arow = A + ra * D + g * LK;
+#pragma unroll
+    for (int cc = 0; cc < NC1; ++cc) {
+      alignas(16) AT af[LK];
+#pragma unroll
+      for (int i = 0; i < LK; i += 16 / (int)sizeof(AT))
+        *reinterpret_cast<uint4*>(&af[i]) = *reinterpret_cast<const uint4*>(arow + cc * KC + i);
+      fa[rt][cc].load(af);
+    }
+  }
+  floatx4 acc2[2][NT2];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int t = 0; t < NT2; ++t) acc2[rt][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  AT (*H)[LDH] = Hs[wave];
+  for (int hc = 0; hc < NH; ++hc) {
+#pragma unroll
+    for (int t = 0; t < NT1; ++t) {
+      const int nt = hc * NT1 + t;
+      floatx4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0;
+      const uint4* bp = p1 + (size_t)nt * NC1 * 64 + lane;
+#pragma unroll
+      for (int cc = 0; cc < NC1; ++cc) {
+        a0 = fa[0][cc].mma(bp + cc * 64, bp + cc * 64 + LO, a0);
+        a1 = fa[1][cc].mma(bp + cc * 64, bp + cc * 64 + LO, a1);
+      }
+      const float bias = b1[nt * 16 + c];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        H[4 * g + i][t * 16 + c] = from_f<AT>(gelu(a0[i] + bias));
+        H[16 + 4 * g + i][t * 16 + c] = from_f<AT>(gelu(a1[i] + bias));
+      }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int cc = 0; cc < NC2H; ++cc) {
+      FragA<MODE> h0, h1;
+      h0.load(&H[c][cc * KC + g * LK]);
+      h1.load(&H[16 + c][cc * KC + g * LK]);
+#pragma unroll
+      for (int t = 0; t < NT2; ++t) {
+        const uint4* bp = p2 + ((size_t)t * NC2 + hc * NC2H + cc) * 64 + lane;
+        acc2[0][t] = h0.mma(bp, bp + LO, acc2[0][t]);
+        acc2[1][t] = h1.mma(bp, bp + LO, acc2[1][t]);
+      }
+    }
+    wave_lds_sync();                         // the next chunk overwrites H
+  }
+#pragma unroll
+  for (int t = 0; t < NT2; ++t) {
+    const int n = t * 16 + c;
+    const float bias = b2[n];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = rbase + 16 * rt + 4 * g + i;
+        if (r < rows) out[r * D + n] = resid[r * D + n] + acc2[rt][t][i] + bias;
+      }
   }
 }
 
