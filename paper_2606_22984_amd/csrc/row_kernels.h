@@ -58,10 +58,13 @@ __global__ __launch_bounds__(256) void ln_kernel(const float* __restrict__ X, in
 }
 
 // ---------------------------------------------------------------- row GEMM
-// C[r][n] = sum_k A[r][k] W[n][k] over a packed W [NOUT x K]; 64 rows per
-// workgroup, one wave per 16 rows.  A is read from HBM once: for K <= 128 the
+// C[r][n] = sum_k A[r][k] W[n][k] over a packed W [NOUT x K]; 128 rows per
+// workgroup, one wave per 32 rows (two 16-row MFMA tiles: every weight fragment
+// a wave loads from L2 feeds both).  A is read from HBM once: for K <= 128 the
 // wave's A fragments stay in registers across all output tiles; for larger K
 // (NOUT <= 128) the loop runs K-outer with every output tile's accumulator live.
+constexpr int kGemmRows = 128;
+
 template <int MODE, int K, int NOUT, int EPI>
 __global__ __launch_bounds__(256) void gemm_rows_kernel(const typename Mode<MODE>::ActT* __restrict__ A,
                                                         int64_t rows, const uint4* __restrict__ pack,
@@ -72,69 +75,70 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(const typename Mode<MODE
   constexpr int NC = K / KC;
   constexpr int NT = NOUT / 16;
   constexpr size_t LO = (size_t)NOUT * K / 8;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t rbase = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+  const int64_t rbase = (int64_t)blockIdx.x * kGemmRows + wave * 32;
   if (rbase >= rows) return;
-  const int64_t ra = std::min<int64_t>(rbase + (lane & 15), rows - 1);   // clamp the A row; stores are guarded
-  const AT* arow = A + ra * K + (lane >> 4) * LK;
-  if constexpr (K <= 128) {
-    FragA<MODE> fa[NC];                      // the wave's A fragments, converted once
+  // clamp the A rows; stores are guarded
+  const AT* arow[2] = {A + std::min<int64_t>(rbase + c, rows - 1) * K + g * LK,
+                       A + std::min<int64_t>(rbase + 16 + c, rows - 1) * K + g * LK};
+  auto load_frag = [&](FragA<MODE>& fa, int rt, int cc) {
+    alignas(16) AT af[LK];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      alignas(16) AT af[LK];
+    for (int i = 0; i < LK; i += 16 / (int)sizeof(AT))
+      *reinterpret_cast<uint4*>(&af[i]) = *reinterpret_cast<const uint4*>(arow[rt] + cc * KC + i);
+    fa.load(af);
+  };
+  auto epilogue = [&](int nt, const floatx4& a0, const floatx4& a1) {
+    const int n = nt * 16 + c;
 #pragma unroll
-      for (int i = 0; i < LK; i += 16 / (int)sizeof(AT))
-        *reinterpret_cast<uint4*>(&af[i]) = *reinterpret_cast<const uint4*>(arow + c * KC + i);
-      fa[c].load(af);
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = rbase + 4 * g + i;
+      if (r < rows) Epi<MODE, EPI>::apply(e, r, n, NOUT, a0[i]);
+      if (r + 16 < rows) Epi<MODE, EPI>::apply(e, r + 16, n, NOUT, a1[i]);
     }
+  };
+  if constexpr (K <= 128) {
+    FragA<MODE> fa[2][NC];                   // the wave's A fragments, converted once
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) { load_frag(fa[0][cc], 0, cc); load_frag(fa[1][cc], 1, cc); }
     for (int nt = 0; nt < NT; ++nt) {
-      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+      floatx4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0;
       const uint4* bp = pack + (size_t)nt * NC * 64 + lane;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) acc = fa[c].mma(bp + c * 64, bp + c * 64 + LO, acc);
-      const int n = nt * 16 + (lane & 15);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t r = rbase + 4 * (lane >> 4) + i;
-        if (r < rows) Epi<MODE, EPI>::apply(e, r, n, NOUT, acc[i]);
+      for (int cc = 0; cc < NC; ++cc) {
+        a0 = fa[0][cc].mma(bp + cc * 64, bp + cc * 64 + LO, a0);
+        a1 = fa[1][cc].mma(bp + cc * 64, bp + cc * 64 + LO, a1);
       }
+      epilogue(nt, a0, a1);
     }
   } else {
     static_assert(NT <= 8, "K-outer row GEMM keeps at most 8 output tiles live");
-    floatx4 acc[NT];
+    floatx4 acc[2][NT];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int nt = 0; nt < NT; ++nt) { acc[0][nt] = floatx4{0.f, 0.f, 0.f, 0.f}; acc[1][nt] = acc[0][nt]; }
     const uint4* bp = pack + lane;
-    for (int c = 0; c < NC; ++c) {
-      alignas(16) AT af[LK];
-#pragma unroll
-      for (int i = 0; i < LK; i += 16 / (int)sizeof(AT))
-        *reinterpret_cast<uint4*>(&af[i]) = *reinterpret_cast<const uint4*>(arow + c * KC + i);
-      FragA<MODE> fa;
-      fa.load(af);
+    for (int cc = 0; cc < NC; ++cc) {
+      FragA<MODE> f0, f1;
+      load_frag(f0, 0, cc);
+      load_frag(f1, 1, cc);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        const uint4* b = bp + ((size_t)nt * NC + c) * 64;
-        acc[nt] = fa.mma(b, b + LO, acc[nt]);
+        const uint4* b = bp + ((size_t)nt * NC + cc) * 64;
+        acc[0][nt] = f0.mma(b, b + LO, acc[0][nt]);
+        acc[1][nt] = f1.mma(b, b + LO, acc[1][nt]);
       }
     }
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int n = nt * 16 + (lane & 15);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t r = rbase + 4 * (lane >> 4) + i;
-        if (r < rows) Epi<MODE, EPI>::apply(e, r, n, NOUT, acc[nt][i]);
-      }
-    }
+    for (int nt = 0; nt < NT; ++nt) epilogue(nt, acc[0][nt], acc[1][nt]);
   }
 }
 
 // Row GEMM with an LDS-staged epilogue for the wide outputs (K <= 128: the QKV
-// projection and FFN1 with their GELU / GELU' epilogues).  Each group of four 16-column tiles is computed into
-// a 64 x 64 tile in LDS; the workgroup then writes the row-major outputs as
-// 256-byte row segments and the feature-major copy as 256-byte column segments
-// (16-byte stores), instead of one scattered element per lane.
+// projection and FFN1 with their GELU / GELU' epilogues).  Each group of four
+// 16-column tiles is computed into an R x 64 tile in LDS (R = 64 or 128 rows);
+// the workgroup then writes the row-major outputs as 256-byte row segments and
+// the feature-major copy as R*4-byte column segments (16-byte stores), instead
+// of one scattered element per lane.
 //   EPI_GELU : h = acc + bias; hpre_out[r][n] = h, out[r][n] = GELU(h), outT[n][r] = GELU(h)
 //   EPI_DGELU: d = acc * GELU'(hpre_in[r][n]); out[r][n] = d, outT[n][r] = d
 //   EPI_STORE_KV: out[r][n] = acc + bias[n] in the K/V element type
@@ -150,6 +154,11 @@ __device__ __forceinline__ void store4(T* p, float a, float b, float c, float d)
   }
 }
 
+// 16-row tiles per wave of the staged kernel: two for the QKV projection (each
+// weight fragment feeds both; measured faster), one for the HBM-bound 512-wide
+// GELU / GELU' epilogues, where the larger tile halves the occupancy.
+template <int EPI> struct StagedRowTiles { static constexpr int value = EPI == EPI_STORE_KV ? 2 : 1; };
+
 template <int MODE, int K, int NOUT, int EPI>
 __global__ __launch_bounds__(256) void gemm_rows_staged_kernel(const typename Mode<MODE>::ActT* __restrict__ A,
                                                                int64_t rows, const uint4* __restrict__ pack,
@@ -163,30 +172,35 @@ __global__ __launch_bounds__(256) void gemm_rows_staged_kernel(const typename Mo
   constexpr int LK = KC / 4;
   constexpr int NC = K / KC;
   constexpr int NG = NOUT / 64;
+  constexpr int RT = StagedRowTiles<EPI>::value; // 16-row tiles per wave
+  constexpr int R = 64 * RT;                     // rows per workgroup
   constexpr size_t LO = (size_t)NOUT * K / 8;
-  __shared__ __align__(16) float Ev[64][68];     // out / outT values
-  __shared__ __align__(16) float Eh[64][68];     // pre-activation: GELU output hpre_out, GELU' input hpre_in
+  __shared__ __align__(16) float Ev[R][68];                               // out / outT values
+  __shared__ __align__(16) float Eh[EPI == EPI_STORE_KV ? 1 : R][68];     // GELU: hpre_out; GELU': hpre_in
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
-  const int64_t r0 = (int64_t)blockIdx.x * 64;
-  const int64_t ra = std::min<int64_t>(r0 + wave * 16 + c, rows - 1);   // clamp the A row; stores are guarded
-  const AT* arow = A + ra * K + g * LK;
-  FragA<MODE> fa[NC];                        // the wave's A fragments, converted once
+  const int64_t r0 = (int64_t)blockIdx.x * R;
+  FragA<MODE> fa[RT][NC];                    // the wave's A fragments (rows 16 RT w ..), converted once
 #pragma unroll
-  for (int cc = 0; cc < NC; ++cc) {
-    alignas(16) AT af[LK];
+  for (int rt = 0; rt < RT; ++rt) {
+    const int64_t ra = std::min<int64_t>(r0 + wave * 16 * RT + 16 * rt + c, rows - 1);   // stores are guarded
+    const AT* arow = A + ra * K + g * LK;
 #pragma unroll
-    for (int i = 0; i < LK; i += 16 / (int)sizeof(AT))
-      *reinterpret_cast<uint4*>(&af[i]) = *reinterpret_cast<const uint4*>(arow + cc * KC + i);
-    fa[cc].load(af);
+    for (int cc = 0; cc < NC; ++cc) {
+      alignas(16) AT af[LK];
+#pragma unroll
+      for (int i = 0; i < LK; i += 16 / (int)sizeof(AT))
+        *reinterpret_cast<uint4*>(&af[i]) = *reinterpret_cast<const uint4*>(arow + cc * KC + i);
+      fa[rt][cc].load(af);
+    }
   }
-  const bool full = r0 + 64 <= rows;
+  const bool full = r0 + R <= rows;
   OT* out = reinterpret_cast<OT*>(e.out);
   AT* outT = reinterpret_cast<AT*>(e.outT);
   for (int ng = 0; ng < NG; ++ng) {
     if constexpr (EPI == EPI_DGELU) {
       // stage the pre-activation tile (256-byte row segments)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < R / 16; ++k) {
         const int idx = tid + 256 * k, row = idx >> 4, c4 = (idx & 15) * 4;
         const int64_t r = std::min<int64_t>(r0 + row, rows - 1);
         *reinterpret_cast<float4*>(&Eh[row][c4]) =
@@ -197,30 +211,36 @@ __global__ __launch_bounds__(256) void gemm_rows_staged_kernel(const typename Mo
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int nt = ng * 4 + u;
-      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+      floatx4 acc[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
       const uint4* bp = pack + (size_t)nt * NC * 64 + lane;
 #pragma unroll
-      for (int cc = 0; cc < NC; ++cc) acc = fa[cc].mma(bp + cc * 64, bp + cc * 64 + LO, acc);
+      for (int cc = 0; cc < NC; ++cc)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[rt] = fa[rt][cc].mma(bp + cc * 64, bp + cc * 64 + LO, acc[rt]);
       const int col = 16 * u + c;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = wave * 16 + 4 * g + i;
-        if constexpr (EPI == EPI_GELU) {
-          const float hv = acc[i] + e.bias[ng * 64 + col];
-          Eh[row][col] = hv;
-          Ev[row][col] = gelu(hv);
-        } else if constexpr (EPI == EPI_STORE_KV) {
-          Ev[row][col] = acc[i] + e.bias[ng * 64 + col];
-        } else {
-          Ev[row][col] = acc[i] * gelu_grad(Eh[row][col]);
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = wave * 16 * RT + 16 * rt + 4 * g + i;
+          if constexpr (EPI == EPI_GELU) {
+            const float hv = acc[rt][i] + e.bias[ng * 64 + col];
+            Eh[row][col] = hv;
+            Ev[row][col] = gelu(hv);
+          } else if constexpr (EPI == EPI_STORE_KV) {
+            Ev[row][col] = acc[rt][i] + e.bias[ng * 64 + col];
+          } else {
+            Ev[row][col] = acc[rt][i] * gelu_grad(Eh[row][col]);
+          }
         }
-      }
     }
     __syncthreads();
     const int n0 = ng * 64;
     // row-major outputs: thread -> (row, 4 columns); 16 threads cover a 64-column row segment
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < R / 16; ++k) {
       const int idx = tid + 256 * k, row = idx >> 4, c4 = (idx & 15) * 4;
       const int64_t r = r0 + row;
       if (r < rows) {
@@ -232,18 +252,20 @@ __global__ __launch_bounds__(256) void gemm_rows_staged_kernel(const typename Mo
         }
       }
     }
-    // feature-major copy: thread -> (column, 4 rows); 16 threads cover the tile's 64 rows
-    if (EPI != EPI_STORE_KV && outT) {
+    // feature-major copy: thread -> (column, 4 rows); R/4 threads cover a column's R rows
+    if constexpr (EPI != EPI_STORE_KV) {
+      if (outT) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int idx = tid + 256 * k, col = idx >> 4, q4 = (idx & 15) * 4;
-        AT* dst = outT + (int64_t)(n0 + col) * e.ldT + r0 + q4;
-        if (full) {
-          store4(dst, Ev[q4][col], Ev[q4 + 1][col], Ev[q4 + 2][col], Ev[q4 + 3][col]);
-        } else {
+        for (int k = 0; k < R / 16; ++k) {
+          const int idx = tid + 256 * k, col = idx / (R / 4), q4 = (idx % (R / 4)) * 4;
+          AT* dst = outT + (int64_t)(n0 + col) * e.ldT + r0 + q4;
+          if (full) {
+            store4(dst, Ev[q4][col], Ev[q4 + 1][col], Ev[q4 + 2][col], Ev[q4 + 3][col]);
+          } else {
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (r0 + q4 + i < rows) dst[i] = from_f<AT>(Ev[q4 + i][col]);
+            for (int i = 0; i < 4; ++i)
+              if (r0 + q4 + i < rows) dst[i] = from_f<AT>(Ev[q4 + i][col]);
+          }
         }
       }
     }
@@ -356,13 +378,14 @@ __global__ __launch_bounds__(256) void ffn_fused_kernel(const typename Mode<MODE
 template <int MODE, int K, int NOUT, int EPI>
 inline hipError_t gemm_rows(const typename Mode<MODE>::ActT* A, int64_t rows, const void* pack, const EpiArgs& e,
                             hipStream_t s) {
-  const int grid = (int)((rows + 63) / 64);
-  if constexpr ((EPI == EPI_GELU || EPI == EPI_DGELU || EPI == EPI_STORE_KV) && K <= 128 && NOUT % 64 == 0)
-    hipLaunchKernelGGL((gemm_rows_staged_kernel<MODE, K, NOUT, EPI>), dim3(grid), dim3(256), 0, s, A, rows,
-                       reinterpret_cast<const uint4*>(pack), e);
-  else
-    hipLaunchKernelGGL((gemm_rows_kernel<MODE, K, NOUT, EPI>), dim3(grid), dim3(256), 0, s, A, rows,
-                       reinterpret_cast<const uint4*>(pack), e);
+  if constexpr ((EPI == EPI_GELU || EPI == EPI_DGELU || EPI == EPI_STORE_KV) && K <= 128 && NOUT % 64 == 0) {
+    constexpr int R = 64 * StagedRowTiles<EPI>::value;
+    hipLaunchKernelGGL((gemm_rows_staged_kernel<MODE, K, NOUT, EPI>), dim3((int)((rows + R - 1) / R)), dim3(256), 0,
+                       s, A, rows, reinterpret_cast<const uint4*>(pack), e);
+  } else {
+    hipLaunchKernelGGL((gemm_rows_kernel<MODE, K, NOUT, EPI>), dim3((int)((rows + kGemmRows - 1) / kGemmRows)),
+                       dim3(256), 0, s, A, rows, reinterpret_cast<const uint4*>(pack), e);
+  }
   return hipGetLastError();
 }
 
