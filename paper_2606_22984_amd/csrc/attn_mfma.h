@@ -100,6 +100,11 @@ __device__ __forceinline__ bool visible(int t, int j, int W, int P) {
 
 constexpr float kScaleLog2 = 0.25f * 1.4426950408889634f;   // 1/sqrt(16) * log2(e)
 constexpr int kKeyChunk = 128;                               // keys staged in LDS at a time
+// Workgroup shapes, measured per kernel at the 3D workload: the forward and the
+// dK/dV kernels run 4 waves x 16 rows, the dQ kernel 8 waves x 16 rows (its key
+// staging is then shared by 128 queries).
+constexpr int kFwdThreads = 256, kDqThreads = 512, kDkvThreads = 256;
+__host__ __device__ constexpr int attn_rows(int threads) { return threads / 4; }   // 16 rows per wave
 
 // The keys a query tile [t0, t1) can see: [0, pend) then [bstart, t1), as one
 // virtual index v -> position.
@@ -133,21 +138,22 @@ struct QueryVis {
 // range: every thread loads 16-byte chunks of K and V into registers (the next
 // chunk is fetched while the current one is processed), commit() writes them to
 // float tiles [key][dim] with rows padded to 20.
-template <typename KT>
+template <typename KT, int NTHREADS>
 struct KeyStager {
   static constexpr int QE = 16 / (int)sizeof(KT);            // elements per 16-byte chunk
   static constexpr int QC = 16 / QE;                         // chunks per key slice
-  static constexpr int NLD = kKeyChunk * QC / 256;           // chunks per thread (1 or 2)
+  static constexpr int NPC = kKeyChunk * QC;                 // 16-byte chunks per staged block
+  static constexpr int NLD = (NPC + NTHREADS - 1) / NTHREADS;   // per thread
   uint4 kraw[NLD], vraw[NLD];
   __device__ __forceinline__ void fetch(const KT* __restrict__ QKV, int64_t rowbase, int D, int h,
                                         const KeyRange& kr, int v0) {
     const int nv = min(kKeyChunk, kr.nk - v0);
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
-      const int idx = threadIdx.x + 256 * u, key = idx / QC, ch = (idx % QC) * QE;
+      const int idx = threadIdx.x + NTHREADS * u, key = idx / QC, ch = (idx % QC) * QE;
       kraw[u] = make_uint4(0u, 0u, 0u, 0u);
       vraw[u] = kraw[u];
-      if (key < nv) {
+      if ((idx < NPC) & (key < nv)) {
         const KT* kp = QKV + (rowbase + kr.pos(v0 + key)) * 3 * D + D + h * 16 + ch;
         kraw[u] = *reinterpret_cast<const uint4*>(kp);
         vraw[u] = *reinterpret_cast<const uint4*>(kp + D);
@@ -157,7 +163,8 @@ struct KeyStager {
   __device__ __forceinline__ void commit(float (*Kf)[20], float (*Vf)[20]) const {
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
-      const int idx = threadIdx.x + 256 * u, key = idx / QC, ch = (idx % QC) * QE;
+      const int idx = threadIdx.x + NTHREADS * u, key = idx / QC, ch = (idx % QC) * QE;
+      if (idx >= NPC) break;
       Chunk<KT> kc, vc;
       kc.unpack(kraw[u]);
       vc.unpack(vraw[u]);
@@ -172,20 +179,20 @@ struct KeyStager {
 
 // Operand tiles of R staged rows (R = 64 or 128) of one head: A layout [row][g]
 // (dims 4g..4g+3 of the row) and B layout [dim][row group] (rows 4j..4j+3 of
-// the dim; one padding column against bank conflicts).  Built by all 256
-// threads from a float tile [row][dim].
-template <int MODE, int R>
+// the dim; one padding column against bank conflicts).  Built by all the
+// workgroup's threads from a float tile [row][dim].
+template <int MODE, int R, int NTHREADS>
 __device__ __forceinline__ void build_a(const float (*F)[20], typename AOp<MODE>::T (*A)[4]) {
 #pragma unroll
-  for (int idx = threadIdx.x; idx < R * 4; idx += 256) {
+  for (int idx = threadIdx.x; idx < R * 4; idx += NTHREADS) {
     const int row = idx >> 2, g = idx & 3;
     A[row][g] = aop<MODE>(*reinterpret_cast<const float4*>(&F[row][4 * g]));
   }
 }
-template <int MODE, int R>
+template <int MODE, int R, int NTHREADS>
 __device__ __forceinline__ void build_b(const float (*F)[20], typename AOp<MODE>::T (*B)[R / 4 + 1]) {
 #pragma unroll
-  for (int idx = threadIdx.x; idx < R * 4; idx += 256) {
+  for (int idx = threadIdx.x; idx < R * 4; idx += NTHREADS) {
     const int dim = idx / (R / 4), j = idx % (R / 4);
     B[dim][j] = AOp<MODE>::make(F[4 * j][dim], F[4 * j + 1][dim], F[4 * j + 2][dim], F[4 * j + 3][dim]);
   }
@@ -195,7 +202,7 @@ __device__ __forceinline__ void build_b(const float (*F)[20], typename AOp<MODE>
 // One workgroup = (64 queries, head, sample); wave w owns queries t0+16w..+15.
 // Writes XM = X + O, and LSE (log2 units).
 template <typename KT, int MODE>
-__global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV, const float* __restrict__ X,
+__global__ __launch_bounds__(kFwdThreads) void attn_fwd_mfma(const KT* __restrict__ QKV, const float* __restrict__ X,
                                                      float* __restrict__ XM, float* __restrict__ LSE, int N, int D,
                                                      int H, int W, int P) {
   typedef AOp<MODE> Op;
@@ -205,8 +212,8 @@ __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV,
   __shared__ __align__(16) OT Ka[kKeyChunk][4];               // K, A layout
   __shared__ __align__(16) OT Vb[16][kKeyChunk / 4 + 1];      // V^T as the A operand: [dim][key group]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
-  const int t0 = blockIdx.x * 64, h = blockIdx.y, b = blockIdx.z;
-  const int t1 = min(t0 + 64, N);
+  const int t0 = blockIdx.x * attn_rows(kFwdThreads), h = blockIdx.y, b = blockIdx.z;
+  const int t1 = min(t0 + attn_rows(kFwdThreads), N);
   const int64_t rowbase = (int64_t)b * N;
   const int tq = t0 + 16 * wave + c;                 // this lane's query
   const bool qok = tq < N;
@@ -218,7 +225,7 @@ __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV,
   const OT qb = aop<MODE>(q4);                       // B operand Q^T[dim 4g..][query c]
   const KeyRange kr(t0, t1, W, P);
   const QueryVis vis(kr, tq, W, qok);
-  KeyStager<KT> st;
+  KeyStager<KT, kFwdThreads> st;
   st.fetch(QKV, rowbase, D, h, kr, 0);
   float mx = -INFINITY, l = 0.f;
   floatx4 o = {0.f, 0.f, 0.f, 0.f};                 // O^T[dim 4g+i][query c]
@@ -228,8 +235,8 @@ __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV,
     st.commit(Kf, Vf);
     __syncthreads();
     if (v0 + kKeyChunk < kr.nk) st.fetch(QKV, rowbase, D, h, kr, v0 + kKeyChunk);
-    build_a<MODE, kKeyChunk>(Kf, Ka);
-    build_b<MODE, kKeyChunk>(Vf, Vb);
+    build_a<MODE, kKeyChunk, kFwdThreads>(Kf, Ka);
+    build_b<MODE, kKeyChunk, kFwdThreads>(Vf, Vb);
     __syncthreads();
     for (int kt0 = 0; kt0 < nv; kt0 += 64) {         // 4 key tiles of 16 per softmax update
       float s[16];
@@ -283,10 +290,10 @@ __global__ __launch_bounds__(256) void attn_fwd_mfma(const KT* __restrict__ QKV,
 }
 
 // ---------------------------------------------------------------- backward: dQ
-// One workgroup = (64 queries, head, sample).  O is recovered as XM - X.
+// One workgroup = (128 queries, head, sample).  O is recovered as XM - X.
 // Writes DELTA = dO . O, dQ (scaled) into dQKV and the feature-major copy T.
 template <typename KT, typename AT, int MODE>
-__global__ __launch_bounds__(256) void attn_bwd_dq_mfma(const KT* __restrict__ QKV, const float* __restrict__ X,
+__global__ __launch_bounds__(kDqThreads) void attn_bwd_dq_mfma(const KT* __restrict__ QKV, const float* __restrict__ X,
                                                         const float* __restrict__ XM, const float* __restrict__ dO,
                                                         const float* __restrict__ LSE, float* __restrict__ DELTA,
                                                         AT* __restrict__ dQKV, AT* __restrict__ T, int64_t ldT, int N,
@@ -299,11 +306,11 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_mfma(const KT* __restrict__ Q
   __shared__ __align__(16) OT Va[kKeyChunk][4];
   __shared__ __align__(16) OT Kb[16][kKeyChunk / 4 + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
-  const int t0 = blockIdx.x * 64, h = blockIdx.y, b = blockIdx.z;
-  const int t1 = min(t0 + 64, N);
+  const int t0 = blockIdx.x * attn_rows(kDqThreads), h = blockIdx.y, b = blockIdx.z;
+  const int t1 = min(t0 + attn_rows(kDqThreads), N);
   const int64_t rowbase = (int64_t)b * N;
   const KeyRange kr(t0, t1, W, P);
-  KeyStager<KT> st;
+  KeyStager<KT, kDqThreads> st;
   st.fetch(QKV, rowbase, D, h, kr, 0);
   const int tq = t0 + 16 * wave + c;
   const bool qok = tq < N;
@@ -331,9 +338,9 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_mfma(const KT* __restrict__ Q
     st.commit(Kf, Vf);
     __syncthreads();
     if (v0 + kKeyChunk < kr.nk) st.fetch(QKV, rowbase, D, h, kr, v0 + kKeyChunk);
-    build_a<MODE, kKeyChunk>(Kf, Ka);
-    build_a<MODE, kKeyChunk>(Vf, Va);
-    build_b<MODE, kKeyChunk>(Kf, Kb);
+    build_a<MODE, kKeyChunk, kDqThreads>(Kf, Ka);
+    build_a<MODE, kKeyChunk, kDqThreads>(Vf, Va);
+    build_b<MODE, kKeyChunk, kDqThreads>(Kf, Kb);
     __syncthreads();
     for (int kb = 0; kb < nv; kb += 16) {
       const floatx4 z = {0.f, 0.f, 0.f, 0.f};
@@ -373,13 +380,13 @@ __global__ __launch_bounds__(256) void attn_bwd_dq_mfma(const KT* __restrict__ Q
 // ([j0, j1 + W), or [j0, N) when the tile holds prefix keys).  The next query
 // block is fetched into registers while the current one is processed.
 template <typename KT, typename AT, int MODE>
-__global__ __launch_bounds__(256) void attn_bwd_dkv_mfma(const KT* __restrict__ QKV, const float* __restrict__ dO,
+__global__ __launch_bounds__(kDkvThreads) void attn_bwd_dkv_mfma(const KT* __restrict__ QKV, const float* __restrict__ dO,
                                                          const float* __restrict__ LSE, const float* __restrict__ DELTA,
                                                          AT* __restrict__ dQKV, AT* __restrict__ T, int64_t ldT, int N,
                                                          int D, int H, int W, int P) {
   typedef AOp<MODE> Op;
   typedef typename Op::T OT;
-  constexpr int QB = 64;
+  constexpr int QB = attn_rows(kDkvThreads);
   constexpr int QE = 16 / (int)sizeof(KT);          // Q elements per 16-byte chunk
   constexpr int QC = 16 / QE;                       // 16-byte chunks per query row slice
   __shared__ __align__(16) float Qf[QB][20];
@@ -391,8 +398,8 @@ __global__ __launch_bounds__(256) void attn_bwd_dkv_mfma(const KT* __restrict__ 
   __shared__ __align__(16) float Ls[QB];
   __shared__ __align__(16) float Ds[QB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
-  const int h = blockIdx.x, j0 = blockIdx.y * 64, b = blockIdx.z;
-  const int j1 = min(j0 + 64, N);
+  const int h = blockIdx.x, j0 = blockIdx.y * QB, b = blockIdx.z;
+  const int j1 = min(j0 + QB, N);
   const int64_t rowbase = (int64_t)b * N;
   const int jk = j0 + 16 * wave + c;               // this lane's key (B-operand column)
   const bool kok = jk < N;
@@ -407,12 +414,13 @@ __global__ __launch_bounds__(256) void attn_bwd_dkv_mfma(const KT* __restrict__ 
   const int qend = j0 < P ? N : min(N, j1 + W);
   // queries that see this lane's key: jk <= iq < qhi (any later query for a prefix key)
   const int qw = kok ? max(0, min(jk < P ? N : jk + W + 1, qend) - jk) : 0;
-  // staging roles: dO row tid/4, quarter tid%4; Q row tid/QC, chunk tid%QC (tid < 64*QC);
-  // LSE (tid < 64) or DELTA (64 <= tid < 128) of row tid%64
+  // staging roles (QB rows): dO row tid/4, quarter tid%4; Q row tid/QC, chunk
+  // tid%QC (tid < QB*QC); LSE (tid < QB) or DELTA (QB <= tid < 2 QB) of row tid%QB
+  static_assert(QB * 4 == kDkvThreads, "dK/dV staging: one dO quarter-row per thread");
   const int gr = tid >> 2, gc = (tid & 3) * 4;
   const int qr = tid / QC, qc = (tid % QC) * QE;
-  const bool qthr = tid < 64 * QC;
-  const int sr = tid & 63;
+  const bool qthr = tid < QB * QC;
+  const int sr = tid % QB;
   float4 graw = make_float4(0.f, 0.f, 0.f, 0.f);
   uint4 qraw = make_uint4(0u, 0u, 0u, 0u);
   float sraw = 0.f;
@@ -423,7 +431,7 @@ __global__ __launch_bounds__(256) void attn_bwd_dkv_mfma(const KT* __restrict__ 
     qraw = make_uint4(0u, 0u, 0u, 0u);
     if (qthr & (qr < nq)) qraw = *reinterpret_cast<const uint4*>(QKV + (rowbase + i0 + qr) * 3 * D + h * 16 + qc);
     sraw = 0.f;
-    if ((tid < 128) & (sr < nq)) sraw = (tid < 64 ? LSE : DELTA)[(rowbase + i0 + sr) * H + h];
+    if ((tid < 2 * QB) & (sr < nq)) sraw = (tid < QB ? LSE : DELTA)[(rowbase + i0 + sr) * H + h];
   };
   fetch(j0);
   floatx4 dk = {0.f, 0.f, 0.f, 0.f}, dv = {0.f, 0.f, 0.f, 0.f};   // [key 16w+4g+i][dim c]
@@ -437,14 +445,14 @@ __global__ __launch_bounds__(256) void attn_bwd_dkv_mfma(const KT* __restrict__ 
 #pragma unroll
       for (int e = 0; e < QE; ++e) Qf[qr][qc + e] = ch.v[e];
     }
-    if (tid < 64) Ls[sr] = sraw;
-    else if (tid < 128) Ds[sr] = sraw;
+    if (tid < QB) Ls[sr] = sraw;
+    else if (tid < 2 * QB) Ds[sr] = sraw;
     __syncthreads();
     if (i0 + QB < qend) fetch(i0 + QB);
-    build_a<MODE, QB>(Qf, Qa);
-    build_a<MODE, QB>(Gf, Ga);
-    build_b<MODE, QB>(Qf, Qb);
-    build_b<MODE, QB>(Gf, Gb);
+    build_a<MODE, QB, kDkvThreads>(Qf, Qa);
+    build_a<MODE, QB, kDkvThreads>(Gf, Ga);
+    build_b<MODE, QB, kDkvThreads>(Qf, Qb);
+    build_b<MODE, QB, kDkvThreads>(Gf, Gb);
     __syncthreads();
     for (int q0 = 0; q0 < nq; q0 += 16) {
       const floatx4 z = {0.f, 0.f, 0.f, 0.f};

@@ -97,7 +97,8 @@ hipError_t forward_layer(fvan_model* m, int l, int64_t rows, int nsamp, hipStrea
   hipError_t err = gemm_rows<MODE, D, 3 * D, EPI_STORE_KV>((const AT*)f.A, rows, wl + m->pk.qkv, e, s);
   if (err != hipSuccess) return err;
   const int H = c.n_heads;
-  hipLaunchKernelGGL((attn_fwd_mfma<KT, MODE>), dim3((c.n_spins + 63) / 64, H, nsamp), dim3(256), 0, s,
+  hipLaunchKernelGGL((attn_fwd_mfma<KT, MODE>), dim3((c.n_spins + attn_rows(kFwdThreads) - 1) / attn_rows(kFwdThreads), H, nsamp),
+                     dim3(kFwdThreads), 0, s,
                      (const KT*)QKV, X, XM, LSE, c.n_spins, D, H, c.window, m->kg.P);
   hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(lgrid), dim3(256), 0, s, (const float*)XM, rows,
                      lp + m->po.ln2_g, lp + m->po.ln2_b, (AT*)f.A, (AT*)nullptr, (int64_t)0);
