@@ -193,7 +193,9 @@ template <int MODE, int R, int NTHREADS>
 __device__ __forceinline__ void build_b(const float (*F)[20], typename AOp<MODE>::T (*B)[R / 4 + 1]) {
 #pragma unroll
   for (int idx = threadIdx.x; idx < R * 4; idx += NTHREADS) {
-    const int dim = idx / (R / 4), j = idx % (R / 4);
+    // consecutive lanes take consecutive dims: the column reads F[4j + r][dim] of a
+    // wave then hit 64 distinct banks (rows are 80 bytes apart)
+    const int dim = idx & 15, j = idx >> 4;
     B[dim][j] = AOp<MODE>::make(F[4 * j][dim], F[4 * j + 1][dim], F[4 * j + 2][dim], F[4 * j + 3][dim]);
   }
 }
@@ -253,8 +255,7 @@ __global__ __launch_bounds__(kFwdThreads) void attn_fwd_mfma(const KT* __restric
           bmax = fmaxf(bmax, s[4 * u + i]);
         }
       }
-      bmax = fmaxf(bmax, __shfl_xor(bmax, 16));
-      bmax = fmaxf(bmax, __shfl_xor(bmax, 32));
+      bmax = max_xor32(max_xor16(bmax));
       const float mn = fmaxf(mx, bmax);
       const float corr = mn == -INFINITY ? 1.f : __builtin_amdgcn_exp2f(mx - mn);
       float ps = 0.f;
@@ -264,8 +265,7 @@ __global__ __launch_bounds__(kFwdThreads) void attn_fwd_mfma(const KT* __restric
         s[i] = mn == -INFINITY ? 0.f : e;
         ps += s[i];
       }
-      ps += __shfl_xor(ps, 16);
-      ps += __shfl_xor(ps, 32);
+      ps = sum_xor32(sum_xor16(ps));
       l = l * corr + ps;
       mx = mn;
 #pragma unroll
@@ -327,8 +327,7 @@ __global__ __launch_bounds__(kDqThreads) void attn_bwd_dq_mfma(const KT* __restr
     delta = g4.x * (xm.x - xx.x) + g4.y * (xm.y - xx.y) + g4.z * (xm.z - xx.z) + g4.w * (xm.w - xx.w);
     lse = LSE[r * H + h];
   }
-  delta += __shfl_xor(delta, 16);
-  delta += __shfl_xor(delta, 32);
+  delta = sum_xor32(sum_xor16(delta));
   if (qok && g == 0) DELTA[r * H + h] = delta;
   const OT qb = aop<MODE>(q4), gb = aop<MODE>(g4);   // B operands Q^T, dO^T [dim 4g..][query c]
   floatx4 dq = {0.f, 0.f, 0.f, 0.f};               // dQ[query 16w+4g+i][dim c]
