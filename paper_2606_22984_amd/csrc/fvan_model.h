@@ -42,14 +42,13 @@ struct fvan_model {
     int64_t ldT = 0;               // row stride of the feature-major buffers (rows rounded up to 64)
     void* A = nullptr;             // [rows][D] LN output (GEMM operand)
     void* QKV = nullptr;           // [n_layers][rows][3D] (K/V element type)
-    void* HID = nullptr;           // [rows][4D] GELU output
     float* HPRE = nullptr;         // [rows][4D] FFN pre-activation (backward)
     float* logp = nullptr;         // [rows] log p_t(s_t)
     // backward
     float* dX = nullptr;           // [rows][D]
     float* dXM = nullptr;          // [rows][D]
-    void* dQKV = nullptr;          // [rows][3D]
     void* dH = nullptr;            // [rows][4D] gradient of the FFN pre-activation
+    void* dQKV = nullptr;          // [rows][3D]
     void* T_a = nullptr;           // [4D][ldT] feature-major left operands of the weight gradients
     void* T_b = nullptr;           // [(4D+16)][ldT] feature-major GELU outputs (+ ones row)
     float* part = nullptr;         // split-K partial sums

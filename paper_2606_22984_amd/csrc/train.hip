@@ -50,10 +50,10 @@ int ensure_fwd_workspace(fvan_model* m) {
       {(void**)&f.LSE, (size_t)L * R * H * 4, "LSE"},
       {(void**)&f.DELTA, R * H * 4, "DELTA"},             {(void**)&f.TMP, R * D * 4, "TMP"},
       {&f.DY, R * D * at, "DY"},                          {&f.A, R * D * at, "A"},
-      {&f.QKV, (size_t)L * R * 3 * D * kt, "QKV"},       {&f.HID, R * 4 * D * at, "HID"},
-      {(void**)&f.HPRE, R * 4 * D * 4, "HPRE"},           {(void**)&f.dX, R * D * 4, "dX"},
-      {(void**)&f.dXM, R * D * 4, "dXM"},                 {&f.dQKV, R * 3 * D * at, "dQKV"},
-      {&f.dH, R * 4 * D * at, "dH"},                      {&f.T_a, 4 * D * ldT * at, "T_a"},
+      {&f.QKV, (size_t)L * R * 3 * D * kt, "QKV"},       {(void**)&f.HPRE, R * 4 * D * 4, "HPRE"},
+      {(void**)&f.dX, R * D * 4, "dX"},                   {(void**)&f.dXM, R * D * 4, "dXM"},
+      {&f.dQKV, R * 3 * D * at, "dQKV"},                  {&f.dH, R * 4 * D * at, "dH"},
+      {&f.T_a, 4 * D * ldT * at, "T_a"},
       {&f.T_b, (4 * D + 16) * ldT * at, "T_b"},           {&f.T_c, (D + 16) * ldT * at, "T_c"},
       {(void**)&f.part, f.part_floats * 4, "partials"},   {(void**)&f.colpart, f.colpart_floats * 4, "column partials"},
       {(void**)&f.colpart2, (size_t)64 * (2 * D + 2) * 4, "column slices"},
