@@ -147,7 +147,7 @@ static void colsum_add(const float* part, int n, int width, float* part2, float*
 }
 
 // ---------------------------------------------------------------- transpose + cast
-// dY (float, [rows x D]) -> Yrm (ActT, row-major) and YT (ActT, [D x ldT]).
+// dY (float, [rows x D]) -> Yrm (ActT, row-major; skipped when NULL) and YT (ActT, [D x ldT]).
 template <int D, typename AT>
 __global__ __launch_bounds__(256) void transpose_cast_kernel(const float* __restrict__ Y, int64_t rows,
                                                              AT* __restrict__ Yrm, AT* __restrict__ YT, int64_t ldT) {
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void transpose_cast_kernel(const float* __rest
     const int64_t r = r0 + rr;
     const float v = r < rows ? Y[r * D + k] : 0.f;
     tile[rr][k] = v;
-    if (r < rows) Yrm[r * D + k] = from_f<AT>(v);
+    if (Yrm && r < rows) Yrm[r * D + k] = from_f<AT>(v);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 64 * D; i += 256) {
@@ -510,15 +510,18 @@ static hipError_t backward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp
     e1.outT = f.T_b;
     e1.ldT = f.ldT;
     if ((err = gemm_rows<MODE, D, 4 * D, EPI_GELU>((const AT*)f.A, rows, wl + m->pk.ffn1, e1, s))) return err;
+    // with FP32 activations (FP32 and split modes) the row-major dY operand is dX itself
+    constexpr bool kF32Act = sizeof(AT) == 4;
+    const AT* dY = kF32Act ? (const AT*)f.dX : (const AT*)f.DY;
     hipLaunchKernelGGL((transpose_cast_kernel<D, AT>), dim3(rgrid), dim3(256), 0, s, (const float*)f.dX, rows,
-                       (AT*)f.DY, (AT*)f.T_a, f.ldT);
+                       kF32Act ? (AT*)nullptr : (AT*)f.DY, (AT*)f.T_a, f.ldT);
     if ((err = wgrad<MODE, D, 4 * D>(m, f.T_a, f.T_b, rows, gl + m->po.ffn2_w, gl + m->po.ffn2_b, s))) return err;
     EpiArgs e2{};
     e2.hpre_in = f.HPRE;
     e2.out = f.dH;
     e2.outT = f.T_a;
     e2.ldT = f.ldT;
-    if ((err = gemm_rows<MODE, D, 4 * D, EPI_DGELU>((const AT*)f.DY, rows, wl + m->pk.ffn2T, e2, s))) return err;
+    if ((err = gemm_rows<MODE, D, 4 * D, EPI_DGELU>(dY, rows, wl + m->pk.ffn2T, e2, s))) return err;
     if ((err = wgrad<MODE, 4 * D, D>(m, f.T_a, f.T_c, rows, gl + m->po.ffn1_w, gl + m->po.ffn1_b, s))) return err;
     EpiArgs e3{};
     e3.out = f.TMP;

@@ -77,7 +77,6 @@ __global__ __launch_bounds__(256) void head_fwd_kernel(const float* __restrict__
 // ---------------------------------------------------------------- drivers
 template <int MODE, int D>
 hipError_t forward_layer(fvan_model* m, int l, int64_t rows, int nsamp, hipStream_t s) {
-  typedef typename Mode<MODE>::ActT AT;
   typedef typename Mode<MODE>::KvT KT;
   const fvan_model_config& c = m->cfg;
   auto& f = m->fw;
@@ -88,22 +87,21 @@ hipError_t forward_layer(fvan_model* m, int l, int64_t rows, int nsamp, hipStrea
   float* XM = f.XM + (size_t)l * f.rows * D;
   KT* QKV = reinterpret_cast<KT*>(f.QKV) + (size_t)l * f.rows * 3 * D;
   float* LSE = f.LSE + (size_t)l * f.rows * c.n_heads;
-  const int lgrid = (int)((rows + 63) / 64);
-  hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(lgrid), dim3(256), 0, s, X, rows, lp + m->po.ln1_g,
-                     lp + m->po.ln1_b, (AT*)f.A, (AT*)nullptr, (int64_t)0);
+  // LN1 is computed inside the QKV projection and LN2 inside the fused FFN
   EpiArgs e{};
   e.bias = lp + m->po.qkv_b;
   e.out = QKV;
-  hipError_t err = gemm_rows<MODE, D, 3 * D, EPI_STORE_KV>((const AT*)f.A, rows, wl + m->pk.qkv, e, s);
+  e.ln_x = X;
+  e.ln_g = lp + m->po.ln1_g;
+  e.ln_b = lp + m->po.ln1_b;
+  hipError_t err = gemm_rows<MODE, D, 3 * D, EPI_STORE_KV>(nullptr, rows, wl + m->pk.qkv, e, s);
   if (err != hipSuccess) return err;
   const int H = c.n_heads;
   hipLaunchKernelGGL((attn_fwd_mfma<KT, MODE>), dim3((c.n_spins + attn_rows(kFwdThreads) - 1) / attn_rows(kFwdThreads), H, nsamp),
                      dim3(kFwdThreads), 0, s,
                      (const KT*)QKV, X, XM, LSE, c.n_spins, D, H, c.window, m->kg.P);
-  hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(lgrid), dim3(256), 0, s, (const float*)XM, rows,
-                     lp + m->po.ln2_g, lp + m->po.ln2_b, (AT*)f.A, (AT*)nullptr, (int64_t)0);
   hipLaunchKernelGGL((ffn_fused_kernel<MODE, D>), dim3((int)((rows + kFfnRows - 1) / kFfnRows)), dim3(256), 0, s,
-                     (const AT*)f.A, rows,
+                     (const float*)XM, lp + m->po.ln2_g, lp + m->po.ln2_b, rows,
                      reinterpret_cast<const uint4*>(wl + m->pk.ffn1), reinterpret_cast<const uint4*>(wl + m->pk.ffn2),
                      lp + m->po.ffn1_b, lp + m->po.ffn2_b, (const float*)XM, Xn);
   return hipGetLastError();

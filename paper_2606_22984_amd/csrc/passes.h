@@ -23,6 +23,11 @@ struct EpiArgs {
   void* out = nullptr;
   void* outT = nullptr;
   int64_t ldT = 0;
+  // staged GEMM: when ln_x is set the A rows are LayerNorm(ln_x rows; ln_g, ln_b),
+  // computed in the kernel, and the A argument is not read
+  const float* ln_x = nullptr;
+  const float* ln_g = nullptr;
+  const float* ln_b = nullptr;
 };
 
 template <int MODE, int EPI> struct Epi;

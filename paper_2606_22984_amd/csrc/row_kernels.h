@@ -57,6 +57,45 @@ __global__ __launch_bounds__(256) void ln_kernel(const float* __restrict__ X, in
   }
 }
 
+// A fragments of one 16-row tile computed as LayerNorm(X row) (affine g, b;
+// population variance, eps kLnEps): lane (g, c) holds row c's elements
+// cc*KC + g*LK .. +LK for every chunk cc, so the four lanes of a row together
+// hold it whole and the row statistics are two pair reductions.
+template <int MODE, int K>
+__device__ __forceinline__ void load_ln_frags(const float* __restrict__ X, int64_t row,
+                                              const float* __restrict__ gam, const float* __restrict__ bet, int g,
+                                              FragA<MODE>* fa) {
+  typedef typename Mode<MODE>::ActT AT;
+  constexpr int KC = Mode<MODE>::KC, LK = KC / 4, NC = K / KC;
+  float x[NC][LK];
+  float s = 0.f;
+#pragma unroll
+  for (int cc = 0; cc < NC; ++cc)
+#pragma unroll
+    for (int i = 0; i < LK; i += 4) {
+      const float4 v = *reinterpret_cast<const float4*>(X + row * K + cc * KC + g * LK + i);
+      x[cc][i] = v.x; x[cc][i + 1] = v.y; x[cc][i + 2] = v.z; x[cc][i + 3] = v.w;
+      s += (v.x + v.y) + (v.z + v.w);
+    }
+  const float mean = sum_xor32(sum_xor16(s)) * (1.0f / K);
+  float q = 0.f;
+#pragma unroll
+  for (int cc = 0; cc < NC; ++cc)
+#pragma unroll
+    for (int i = 0; i < LK; ++i) { x[cc][i] -= mean; q += x[cc][i] * x[cc][i]; }
+  const float rstd = rsqrtf(sum_xor32(sum_xor16(q)) * (1.0f / K) + kLnEps);
+#pragma unroll
+  for (int cc = 0; cc < NC; ++cc) {
+    alignas(16) AT af[LK];
+#pragma unroll
+    for (int i = 0; i < LK; ++i) {
+      const int k = cc * KC + g * LK + i;
+      af[i] = from_f<AT>(x[cc][i] * rstd * gam[k] + bet[k]);
+    }
+    fa[cc].load(af);
+  }
+}
+
 // ---------------------------------------------------------------- row GEMM
 // C[r][n] = sum_k A[r][k] W[n][k] over a packed W [NOUT x K]; 128 rows per
 // workgroup, one wave per 32 rows (two 16-row MFMA tiles: every weight fragment
@@ -78,7 +117,7 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(const typename Mode<MODE
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
   const int64_t rbase = (int64_t)blockIdx.x * kGemmRows + wave * 32;
   if (rbase >= rows) return;
-  // clamp the A rows; stores are guarded
+  // clamp the A rows; stores are guarded (A is not read when the rows come from ln_x)
   const AT* arow[2] = {A + std::min<int64_t>(rbase + c, rows - 1) * K + g * LK,
                        A + std::min<int64_t>(rbase + 16 + c, rows - 1) * K + g * LK};
   auto load_frag = [&](FragA<MODE>& fa, int rt, int cc) {
@@ -99,8 +138,14 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(const typename Mode<MODE
   };
   if constexpr (K <= 128) {
     FragA<MODE> fa[2][NC];                   // the wave's A fragments, converted once
+    if (e.ln_x) {                            // A = LayerNorm(ln_x rows), computed here
 #pragma unroll
-    for (int cc = 0; cc < NC; ++cc) { load_frag(fa[0][cc], 0, cc); load_frag(fa[1][cc], 1, cc); }
+      for (int rt = 0; rt < 2; ++rt)
+        load_ln_frags<MODE, K>(e.ln_x, std::min<int64_t>(rbase + 16 * rt + c, rows - 1), e.ln_g, e.ln_b, g, fa[rt]);
+    } else {
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) { load_frag(fa[0][cc], 0, cc); load_frag(fa[1][cc], 1, cc); }
+    }
     for (int nt = 0; nt < NT; ++nt) {
       floatx4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0;
       const uint4* bp = pack + (size_t)nt * NC * 64 + lane;
@@ -183,14 +228,18 @@ __global__ __launch_bounds__(256) void gemm_rows_staged_kernel(const typename Mo
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
     const int64_t ra = std::min<int64_t>(r0 + wave * 16 * RT + 16 * rt + c, rows - 1);   // stores are guarded
-    const AT* arow = A + ra * K + g * LK;
+    if (e.ln_x) {
+      load_ln_frags<MODE, K>(e.ln_x, ra, e.ln_g, e.ln_b, g, fa[rt]);
+    } else {
+      const AT* arow = A + ra * K + g * LK;
 #pragma unroll
-    for (int cc = 0; cc < NC; ++cc) {
-      alignas(16) AT af[LK];
+      for (int cc = 0; cc < NC; ++cc) {
+        alignas(16) AT af[LK];
 #pragma unroll
-      for (int i = 0; i < LK; i += 16 / (int)sizeof(AT))
-        *reinterpret_cast<uint4*>(&af[i]) = *reinterpret_cast<const uint4*>(arow + cc * KC + i);
-      fa[rt][cc].load(af);
+        for (int i = 0; i < LK; i += 16 / (int)sizeof(AT))
+          *reinterpret_cast<uint4*>(&af[i]) = *reinterpret_cast<const uint4*>(arow + cc * KC + i);
+        fa[rt][cc].load(af);
+      }
     }
   }
   const bool full = r0 + R <= rows;
@@ -286,12 +335,13 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 constexpr int kFfnRows = 128;                // rows per fused-FFN workgroup
 
+// The input rows are LayerNorm(X rows; ln_g, ln_b), computed in the kernel.
 template <int MODE, int D>
-__global__ __launch_bounds__(256) void ffn_fused_kernel(const typename Mode<MODE>::ActT* __restrict__ A,
-                                                        int64_t rows, const uint4* __restrict__ p1,
-                                                        const uint4* __restrict__ p2, const float* __restrict__ b1,
-                                                        const float* __restrict__ b2, const float* __restrict__ resid,
-                                                        float* __restrict__ out) {
+__global__ __launch_bounds__(256) void ffn_fused_kernel(const float* __restrict__ X, const float* __restrict__ ln_g,
+                                                        const float* __restrict__ ln_b, int64_t rows,
+                                                        const uint4* __restrict__ p1, const uint4* __restrict__ p2,
+                                                        const float* __restrict__ b1, const float* __restrict__ b2,
+                                                        const float* __restrict__ resid, float* __restrict__ out) {
   typedef typename Mode<MODE>::ActT AT;
   constexpr int KC = Mode<MODE>::KC;
   constexpr int LK = KC / 4;                 // A elements per lane per chunk
@@ -310,18 +360,8 @@ __global__ __launch_bounds__(256) void ffn_fused_kernel(const typename Mode<MODE
   if (rbase >= rows) return;                 // no block-wide barrier below
   FragA<MODE> fa[2][NC1];                    // both row tiles' A fragments, converted once
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt) {
-    const int64_t ra = std::min<int64_t>(rbase + 16 * rt + c, rows - 1);
-    const AT* arow = A + ra * D + g * LK;
-#pragma unroll
-    for (int cc = 0; cc < NC1; ++cc) {
-      alignas(16) AT af[LK];
-#pragma unroll
-      for (int i = 0; i < LK; i += 16 / (int)sizeof(AT))
-        *reinterpret_cast<uint4*>(&af[i]) = *reinterpret_cast<const uint4*>(arow + cc * KC + i);
-      fa[rt][cc].load(af);
-    }
-  }
+  for (int rt = 0; rt < 2; ++rt)
+    load_ln_frags<MODE, D>(X, std::min<int64_t>(rbase + 16 * rt + c, rows - 1), ln_g, ln_b, g, fa[rt]);
   floatx4 acc2[2][NT2];
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
@@ -378,6 +418,8 @@ __global__ __launch_bounds__(256) void ffn_fused_kernel(const typename Mode<MODE
 template <int MODE, int K, int NOUT, int EPI>
 inline hipError_t gemm_rows(const typename Mode<MODE>::ActT* A, int64_t rows, const void* pack, const EpiArgs& e,
                             hipStream_t s) {
+  // the rows come either from A or, for K <= 128, from LayerNorm(e.ln_x)
+  if (e.ln_x ? (K > 128) : (A == nullptr)) return hipErrorInvalidValue;
   if constexpr ((EPI == EPI_GELU || EPI == EPI_DGELU || EPI == EPI_STORE_KV) && K <= 128 && NOUT % 64 == 0) {
     constexpr int R = 64 * StagedRowTiles<EPI>::value;
     hipLaunchKernelGGL((gemm_rows_staged_kernel<MODE, K, NOUT, EPI>), dim3((int)((rows + R - 1) / R)), dim3(256), 0,
