@@ -315,6 +315,12 @@ __global__ __launch_bounds__(kDqThreads) void attn_bwd_dq_mfma(const KT* __restr
   const int tq = t0 + 16 * wave + c;
   const bool qok = tq < N;
   const QueryVis vis(kr, tq, W, qok);
+  // the virtual keys seen by any query of the wave (queries tw0..tw1, in order):
+  // [0, wa1) and [wb0, wb1); a 16-key step outside both is skipped by the whole wave
+  const int tw0 = t0 + 16 * wave, tw1 = min(tw0 + 15, N - 1);
+  const int wa1 = tw0 < N ? min(kr.pend, tw1 + 1) : 0;
+  const int wb0 = kr.pend + max(0, tw0 - W - kr.bstart);
+  const int wb1 = tw0 < N ? kr.pend + tw1 - kr.bstart + 1 : 0;
   const int64_t r = rowbase + tq;
   float4 q4 = make_float4(0.f, 0.f, 0.f, 0.f), g4 = q4;
   float lse = 0.f, delta = 0.f;
@@ -342,6 +348,8 @@ __global__ __launch_bounds__(kDqThreads) void attn_bwd_dq_mfma(const KT* __restr
     build_b<MODE, kKeyChunk, kDqThreads>(Kf, Kb);
     __syncthreads();
     for (int kb = 0; kb < nv; kb += 16) {
+      const int vb = v0 + kb;
+      if ((vb >= wa1) & ((vb + 16 <= wb0) | (vb >= wb1))) continue;   // no query of the wave sees these keys
       const floatx4 z = {0.f, 0.f, 0.f, 0.f};
       const floatx4 sa = Op::mma(Ka[kb + c][g], qb, z);     // S^T[key 4g+i][query c]
       const floatx4 pa = Op::mma(Va[kb + c][g], gb, z);     // dP^T[key 4g+i][query c]
@@ -413,6 +421,10 @@ __global__ __launch_bounds__(kDkvThreads) void attn_bwd_dkv_mfma(const KT* __res
   const int qend = j0 < P ? N : min(N, j1 + W);
   // queries that see this lane's key: jk <= iq < qhi (any later query for a prefix key)
   const int qw = kok ? max(0, min(jk < P ? N : jk + W + 1, qend) - jk) : 0;
+  // and the queries that see any key of the wave (keys jw0..jw0+15, in order): a
+  // 16-query step outside [jw0, qhi_w) is skipped by the whole wave
+  const int jw0 = j0 + 16 * wave;
+  const int qhi_w = jw0 >= N ? jw0 : (jw0 < P ? qend : min(qend, min(N - 1, jw0 + 15) + W + 1));
   // staging roles (QB rows): dO row tid/4, quarter tid%4; Q row tid/QC, chunk
   // tid%QC (tid < QB*QC); LSE (tid < QB) or DELTA (QB <= tid < 2 QB) of row tid%QB
   static_assert(QB * 4 == kDkvThreads, "dK/dV staging: one dO quarter-row per thread");
@@ -454,6 +466,7 @@ __global__ __launch_bounds__(kDkvThreads) void attn_bwd_dkv_mfma(const KT* __res
     build_b<MODE, QB, kDkvThreads>(Gf, Gb);
     __syncthreads();
     for (int q0 = 0; q0 < nq; q0 += 16) {
+      if ((i0 + q0 + 16 <= jw0) | (i0 + q0 >= qhi_w)) continue;   // no key of the wave sees these queries
       const floatx4 z = {0.f, 0.f, 0.f, 0.f};
       const floatx4 sa = Op::mma(Qa[q0 + c][g], kb, z);   // S[q 4g+i][key c]
       const floatx4 pa = Op::mma(Ga[q0 + c][g], vb, z);   // dP[q 4g+i][key c]
