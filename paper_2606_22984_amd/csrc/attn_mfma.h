@@ -227,6 +227,12 @@ __global__ __launch_bounds__(kFwdThreads) void attn_fwd_mfma(const KT* __restric
   const OT qb = aop<MODE>(q4);                       // B operand Q^T[dim 4g..][query c]
   const KeyRange kr(t0, t1, W, P);
   const QueryVis vis(kr, tq, W, qok);
+  // virtual keys seen by any query of the wave: [0, wa1) and [wb0, wb1) (as in the dQ kernel)
+  const int tw0 = t0 + 16 * wave, tw1 = min(tw0 + 15, N - 1);
+  const int wa1 = tw0 < N ? min(kr.pend, tw1 + 1) : 0;
+  const int wb0 = kr.pend + max(0, tw0 - W - kr.bstart);
+  const int wb1 = tw0 < N ? kr.pend + tw1 - kr.bstart + 1 : 0;
+  auto wave_sees = [&](int v) { return (v < wa1) | ((v + 16 > wb0) & (v < wb1)); };   // a 16-key group
   KeyStager<KT, kFwdThreads> st;
   st.fetch(QKV, rowbase, D, h, kr, 0);
   float mx = -INFINITY, l = 0.f;
@@ -241,13 +247,17 @@ __global__ __launch_bounds__(kFwdThreads) void attn_fwd_mfma(const KT* __restric
     build_b<MODE, kKeyChunk, kFwdThreads>(Vf, Vb);
     __syncthreads();
     for (int kt0 = 0; kt0 < nv; kt0 += 64) {         // 4 key tiles of 16 per softmax update
+      bool used[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) used[u] = (kt0 + 16 * u < nv) && wave_sees(v0 + kt0 + 16 * u);
+      if (!(used[0] | used[1] | used[2] | used[3])) continue;   // no query of the wave sees these keys
       float s[16];
       float bmax = -INFINITY;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int kb = kt0 + 16 * u;
         floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-        if (kb < nv) acc = Op::mma(Ka[kb + c][g], qb, acc);   // S^T[key 4g+i][query c]
+        if (used[u]) acc = Op::mma(Ka[kb + c][g], qb, acc);   // S^T[key 4g+i][query c]
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const bool ok = vis(v0 + kb + 4 * g + i);   // keys past nv lie beyond kr.nk: never visible
@@ -273,7 +283,7 @@ __global__ __launch_bounds__(kFwdThreads) void attn_fwd_mfma(const KT* __restric
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int kb = kt0 + 16 * u;
-        if (kb < nv)   // A = V^T[dim c][keys kb+4g..+3], B = P^T[keys][query c]
+        if (used[u])   // A = V^T[dim c][keys kb+4g..+3], B = P^T[keys][query c]
           o = Op::mma(Vb[c][kb / 4 + g], Op::make(s[4 * u], s[4 * u + 1], s[4 * u + 2], s[4 * u + 3]), o);
       }
     }
