@@ -42,13 +42,7 @@ struct DecodeSmem {
   int8_t sbuf[kM][64];
 };
 
-__device__ __forceinline__ float reduce16(float v) {
-  v += __shfl_xor(v, 8, 16);
-  v += __shfl_xor(v, 4, 16);
-  v += __shfl_xor(v, 2, 16);
-  v += __shfl_xor(v, 1, 16);
-  return v;
-}
+__device__ __forceinline__ float reduce16(float v) { return row_sum16(v); }
 
 // LayerNorm of the kM residual rows into the MFMA operand buffer.
 template <int D, int MODE>
@@ -215,8 +209,8 @@ __device__ void decode_tile(DecodeSmem<D, MODE>& sm, const DecodeUnit& U, int lo
             float d = 0.f;
 #pragma unroll
             for (int i = 0; i < VEC; ++i) d += qv[i] * kc.v[i];
-            if (LPH >= 2) d += __shfl_xor(d, 1);
-            if (LPH >= 4) d += __shfl_xor(d, 2);
+            if (LPH >= 2) d += lane_xor(d, 1);
+            if (LPH >= 4) d += lane_xor(d, 2);
             sc[u] = s0 + u * RPL + lrow < nvis ? d : -INFINITY;
             mnew = fmaxf(mnew, sc[u]);
           }
@@ -239,15 +233,15 @@ __device__ void decode_tile(DecodeSmem<D, MODE>& sm, const DecodeUnit& U, int lo
             // merge the RPL row groups of the wave, then add the heads' outputs to h
 #pragma unroll
             for (int off = LPR; off < 64; off <<= 1) {
-              const float m2 = __shfl_xor(mx, off);
-              const float s2 = __shfl_xor(sum, off);
+              const float m2 = lane_xor(mx, off);
+              const float s2 = lane_xor(sum, off);
               const float mn = fmaxf(mx, m2);
               const float c1 = mx == -INFINITY ? 0.f : __builtin_amdgcn_exp2f(mx - mn);
               const float c2 = m2 == -INFINITY ? 0.f : __builtin_amdgcn_exp2f(m2 - mn);
               sum = sum * c1 + s2 * c2;
 #pragma unroll
               for (int i = 0; i < VEC; ++i) {
-                const float o2 = __shfl_xor(o[i], off);
+                const float o2 = lane_xor(o[i], off);
                 o[i] = o[i] * c1 + o2 * c2;
               }
               mx = mn;

@@ -232,6 +232,39 @@ __device__ __forceinline__ float max_xor32(float v) {
   return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
 }
 
+// v from lane l ^ off, without an LDS round trip where the hardware allows:
+// DPP quad permutes (off 1, 2) and row rotation by 8 (= xor 8 inside a 16-lane
+// row), the lane swaps for off 16 and 32; other offsets use ds_bpermute.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float lane_xor(float v, int off) {
+  switch (off) {
+    case 1: return dpp<0xB1>(v);             // quad_perm(1, 0, 3, 2)
+    case 2: return dpp<0x4E>(v);             // quad_perm(2, 3, 0, 1)
+    case 8: return dpp<0x128>(v);            // row_ror:8
+    case 16: {
+      const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+      return __uint_as_float((threadIdx.x & 16) ? r[0] : r[1]);
+    }
+    case 32: {
+      const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+      return __uint_as_float((threadIdx.x & 32) ? r[0] : r[1]);
+    }
+    default: return __shfl_xor(v, off);
+  }
+}
+// Sum over the 16 lanes of a row, the same in every lane of it (row rotations by
+// 8 and 4 pair lanes symmetrically within the rotation classes, then the quads).
+__device__ __forceinline__ float row_sum16(float v) {
+  v += dpp<0x128>(v);                        // row_ror:8
+  v += dpp<0x124>(v);                        // row_ror:4
+  v += dpp<0x4E>(v);
+  v += dpp<0xB1>(v);
+  return v;
+}
+
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float x) {
   // d/dx [x Phi(x)] = Phi(x) + x phi(x)
