@@ -502,14 +502,18 @@ static hipError_t backward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp
     const KT* QKV = reinterpret_cast<const KT*>(f.QKV) + (size_t)l * f.rows * 3 * D;
     const float* LSE = f.LSE + (size_t)l * f.rows * H;
     // ---- FFN: recompute LN2 and the pre-activation, then differentiate
+    // (LN2 output feature-major for dW1; the FFN1 GEMM recomputes LN2 itself)
     hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(rgrid), dim3(256), 0, s, XM, rows, lp + m->po.ln2_g,
-                       lp + m->po.ln2_b, (AT*)f.A, (AT*)f.T_c, f.ldT);
+                       lp + m->po.ln2_b, (AT*)nullptr, (AT*)f.T_c, f.ldT);
     EpiArgs e1{};
     e1.bias = lp + m->po.ffn1_b;
     e1.hpre_out = f.HPRE;
     e1.outT = f.T_b;
     e1.ldT = f.ldT;
-    if ((err = gemm_rows<MODE, D, 4 * D, EPI_GELU>((const AT*)f.A, rows, wl + m->pk.ffn1, e1, s))) return err;
+    e1.ln_x = XM;
+    e1.ln_g = lp + m->po.ln2_g;
+    e1.ln_b = lp + m->po.ln2_b;
+    if ((err = gemm_rows<MODE, D, 4 * D, EPI_GELU>(nullptr, rows, wl + m->pk.ffn1, e1, s))) return err;
     // with FP32 activations (FP32 and split modes) the row-major dY operand is dX itself
     constexpr bool kF32Act = sizeof(AT) == 4;
     const AT* dY = kF32Act ? (const AT*)f.dX : (const AT*)f.DY;

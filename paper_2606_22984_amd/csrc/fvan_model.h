@@ -33,14 +33,12 @@ struct fvan_model {
     int64_t chunk = 0, rows = 0;   // samples per chunk, rows = chunk * N
     float* X = nullptr;            // [(n_layers+1)][rows][D] layer inputs
     float* XM = nullptr;           // [n_layers][rows][D] residual after attention
-    float* O = nullptr;            // unused
     float* LSE = nullptr;          // [n_layers][rows][H] log-sum-exp of the scores (base 2)
     float* DELTA = nullptr;        // [rows][H] dO . O per head (backward)
     float* TMP = nullptr;          // [rows][D] LayerNorm-output gradients (backward)
     void* DY = nullptr;            // [rows][D] incoming gradient as a GEMM operand (backward)
     void* T_c = nullptr;           // [(D+16)][ldT] feature-major LN outputs (+ ones row) for weight gradients
     int64_t ldT = 0;               // row stride of the feature-major buffers (rows rounded up to 64)
-    void* A = nullptr;             // [rows][D] LN output (GEMM operand)
     void* QKV = nullptr;           // [n_layers][rows][3D] (K/V element type)
     float* HPRE = nullptr;         // [rows][4D] FFN pre-activation (backward)
     float* logp = nullptr;         // [rows] log p_t(s_t)

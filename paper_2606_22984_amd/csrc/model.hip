@@ -55,7 +55,7 @@ void model_free(fvan_model* m) {
 
 void model_free_fwd(fvan_model* m) {
   auto& f = m->fw;
-  dfree(f.X); dfree(f.XM); dfree(f.O); dfree(f.LSE); dfree(f.DELTA); dfree(f.TMP); dfree(f.DY); dfree(f.A);
+  dfree(f.X); dfree(f.XM); dfree(f.LSE); dfree(f.DELTA); dfree(f.TMP); dfree(f.DY);
   dfree(f.QKV); dfree(f.HPRE); dfree(f.logp); dfree(f.dX); dfree(f.dXM); dfree(f.dQKV); dfree(f.dH);
   dfree(f.T_a); dfree(f.T_b); dfree(f.T_c); dfree(f.part); dfree(f.colpart); dfree(f.colpart2);
   m->fw = fvan_model::Fwd();

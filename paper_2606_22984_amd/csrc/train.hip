@@ -49,7 +49,7 @@ int ensure_fwd_workspace(fvan_model* m) {
       {(void**)&f.X, (size_t)(L + 1) * R * D * 4, "X"},   {(void**)&f.XM, (size_t)L * R * D * 4, "XM"},
       {(void**)&f.LSE, (size_t)L * R * H * 4, "LSE"},
       {(void**)&f.DELTA, R * H * 4, "DELTA"},             {(void**)&f.TMP, R * D * 4, "TMP"},
-      {&f.DY, R * D * at, "DY"},                          {&f.A, R * D * at, "A"},
+      {&f.DY, R * D * at, "DY"},
       {&f.QKV, (size_t)L * R * 3 * D * kt, "QKV"},       {(void**)&f.HPRE, R * 4 * D * 4, "HPRE"},
       {(void**)&f.dX, R * D * 4, "dX"},                   {(void**)&f.dXM, R * D * 4, "dXM"},
       {&f.dQKV, R * 3 * D * at, "dQKV"},                  {&f.dH, R * 4 * D * at, "dH"},
