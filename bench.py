@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 --pmc runs, each scaled by the same counter's reading for a 1 GiB copy);
 # the record with the commands is profiles/decode_ea3d_L10_hbm_counters.md.
 # Set to None whenever decode_kernel changes until the counters are taken again.
-DECODE_TRAFFIC_BYTES = None
+DECODE_TRAFFIC_BYTES = 12353902815584
 # first learning rate of the paper's linear warm-up (SI Sec. III B); larger first
 # Adam steps collapse this random-init model within a few steps
 LR = 1e-5
