@@ -6,8 +6,9 @@ Glasses"): the autoregressive factorisation (Eq. 1, Eq. 11), the spin energies
 (Eq. 6, Eq. 8), the concatenated positional embedding (Eq. 15), the decoder
 blocks with masked multi-head attention and no output projection (Eqs. 2-3,
 Alg. 1, Alg. 2), the variational free energy (Eqs. 4-5) and its REINFORCE
-gradient (Eqs. 16-19), and the ordered Markov boundary that sets the sparse
-attention window (Methods, ordered Markov boundary; SI Sec. I A).
+gradient (Eqs. 16-19), the Muon update with Newton-Schulz orthogonalisation
+(Methods, comparison of optimisers), and the ordered Markov boundary that sets
+the sparse attention window (Methods, ordered Markov boundary; SI Sec. I A).
 
 Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  It shares no code with the HIP path: the two sides agree
@@ -16,4 +17,4 @@ definition), never by a common helper.
 
 Precision: float64 throughout; the sampling decision u < p uses float64 p.
 """
-from . import philox, physics, network, sampler, estimator, markov, exact  # noqa: F401
+from . import philox, physics, network, sampler, estimator, markov, exact, muon  # noqa: F401

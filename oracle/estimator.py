@@ -67,7 +67,7 @@ def adam_update(theta, grad, m, v, step: int, lr: float, beta1: float = 0.9,
                 beta2: float = 0.999, eps: float = 1e-8, weight_decay: float = 0.0):
     """One Adam step (Kingma & Ba) with bias correction; step counts from 1.
     Returns (theta, m, v) as float64 arrays.  The paper's default optimiser is
-    Muon; Adam is the update this build ships first (Methods, optimiser comparison)."""
+    Muon (oracle.muon); Adam is the alternative it is compared with (Methods, optimiser comparison)."""
     g = np.asarray(grad, np.float64) + weight_decay * np.asarray(theta, np.float64)
     m = beta1 * np.asarray(m, np.float64) + (1 - beta1) * g
     v = beta2 * np.asarray(v, np.float64) + (1 - beta2) * g * g
