@@ -28,9 +28,14 @@ HBM_PEAK_GBS = 8000.0
 # the record with the commands is profiles/decode_ea3d_L10_hbm_counters.md.
 # Set to None whenever decode_kernel changes until the counters are taken again.
 DECODE_TRAFFIC_BYTES = 12353902815584
-# first learning rate of the paper's linear warm-up (SI Sec. III B); larger first
-# Adam steps collapse this random-init model within a few steps
-LR = 1e-5
+# learning rate: the paper's eta = 1e-3 reached by a linear warm-up over 300 steps
+# (Methods, model configurations and training settings); the timed steps sit at
+# the start of the warm-up
+ETA, WARMUP_STEPS = 1e-3, 300
+
+
+def warmup_lr(step):
+    return ETA * min(1.0, step / WARMUP_STEPS)
 
 
 def kv_bytes_per_sample(N, L, D, W, P, kv_elem):
@@ -56,6 +61,8 @@ def main():
     ap.add_argument("--compare-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--optimizer", choices=("muon", "adam"), default="muon",
+                    help="parameter update of the training step (muon: the paper's default)")
     ap.add_argument("--batched", action="store_true",
                     help="measure the batched workload instead: 64 2D EA instances (L in 16/24/32, +/-J) x 8 "
                          "temperatures, 1024 samples each, sampled + energies + F_q in one graph replay")
@@ -106,11 +113,12 @@ def main():
         E = coup.empty_energy(B)
         stats = torch.zeros(4, dtype=torch.float64, device="cuda")
         w = torch.empty(B, dtype=torch.float32, device="cuda")
-        ev = []
+        ev, ev_opt = [], []
 
         def step(k, timed):
             if timed:
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                oa, ob = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 a.record(stream)
             m.sample(B, seed, k, spins, lq)
             if timed:
@@ -120,7 +128,15 @@ def main():
             fv.free_energy(E, lq, beta, N, stats[:2])
             fv.reinforce_weights(E, lq, beta, w)
             m.log_prob_backward(spins, w)
-            m.adam_step(k, lr=LR)
+            if timed:
+                oa.record(stream)
+            if args.optimizer == "muon":
+                m.muon_step(k, lr=warmup_lr(k), adam_lr=warmup_lr(k))
+            else:
+                m.adam_step(k, lr=warmup_lr(k))
+            if timed:
+                ob.record(stream)
+                ev_opt.append((oa, ob))
 
         for k in range(1, warmup + 1):
             step(k, False)
@@ -133,7 +149,8 @@ def main():
         wall = time.perf_counter() - t0
         dec = float(np.mean([a.elapsed_time(b) for a, b in ev]))
         st = stats.cpu().numpy()
-        res = dict(ms_per_step=1e3 * wall / steps, samples_per_s=B * steps / wall, decode_ms=dec,
+        opt_ms = float(np.mean([a.elapsed_time(b) for a, b in ev_opt]))
+        res = dict(ms_per_step=1e3 * wall / steps, samples_per_s=B * steps / wall, decode_ms=dec, optimizer_ms=opt_ms,
                    sample_only_samples_per_s=B / (dec * 1e-3), F_per_site=float(st[0]),
                    var_f=float(st[1]))
         m.close()
@@ -158,7 +175,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         progress("timing the FP64 oracle on the host")
-        cpu = cpu_baseline(cfg, theta, inst, beta)
+        cpu = cpu_baseline(cfg, theta, inst, beta, args.optimizer)
 
     out = {
         "metric": "spin samples/sec + train-step ms, BF16 vs FP32, 1 GPU, at |dF/N|<=1e-4",
@@ -178,6 +195,8 @@ def main():
                    "global_batch": B, "seq_len": N, "parallelism": "none (1 GPU)"},
         "sample_only_samples_per_s": round(head["sample_only_samples_per_s"], 1),
         "decode_ms": round(head["decode_ms"], 2),
+        "optimizer": args.optimizer,
+        "optimizer_ms": round(head["optimizer_ms"], 3),
         "precisions": {"bf16split": _round(head), **{k: _round(v) for k, v in others.items()}},
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -238,21 +257,28 @@ def _round(d):
     return {k: (round(v, 6) if isinstance(v, float) else v) for k, v in d.items()}
 
 
-def cpu_baseline(cfg, theta, inst, beta, n_samples=2):
+def cpu_baseline(cfg, theta, inst, beta, optimizer, n_samples=2):
     """The FP64 oracle (as it stands) running the same training step on a bounded
-    sample: KV-cached sampling of n_samples, energies, REINFORCE weights and the
-    reverse-mode gradient.  Throughput in samples/s of that step."""
+    sample: KV-cached sampling of n_samples, energies, REINFORCE weights, the
+    reverse-mode gradient and the parameter update.  Throughput in samples/s of
+    that step."""
+    import numpy as np
     import torch
-    from oracle import estimator, physics, sampler
+    from oracle import estimator, muon, physics, sampler
     t0 = time.perf_counter()
     spins, lq, _ = sampler.kv_sample(theta, cfg, n_samples, 12345, 1)
     E = physics.energy_edges(spins, inst.edges_i, inst.edges_j, inst.J)
     estimator.free_energy_stats(E, lq, beta, cfg.n_spins)
-    estimator.reinforce_gradient(theta, cfg, spins, E, lq, beta)
+    g = estimator.reinforce_gradient(theta, cfg, spins, E, lq, beta)
+    z = np.zeros_like(g)
+    if optimizer == "muon":
+        muon.muon_update(theta, g, z, z, 1, cfg, warmup_lr(1), adam_lr=warmup_lr(1))
+    else:
+        estimator.adam_update(theta, g, z, z, 1, warmup_lr(1))
     dt = time.perf_counter() - t0
     return {"value": round(n_samples / dt, 5), "unit": "samples/s", "cores": torch.get_num_threads(),
             "kind": "oracle", "sample": f"{n_samples} samples of the same workload through one FP64 training step "
-                                        f"(sampling, energy, estimator, gradient): {dt:.1f} s"}
+                                        f"(sampling, energy, estimator, gradient, {optimizer} update): {dt:.1f} s"}
 
 
 if __name__ == "__main__":

@@ -108,6 +108,21 @@ typedef struct {
   float lr, beta1, beta2, eps, weight_decay;
 } fvan_adam;
 
+/* Muon (Methods, comparison of optimisers: momentum M, Newton-Schulz
+ * orthogonalisation O of M, step W -= eta (s O + lambda W), with the weight
+ * decay and RMS scale alignment the paper takes from the Muon-at-scale work it
+ * cites).  Applies to the per-layer matrices W_qkv, W1, W2; every other
+ * parameter takes the Adam step given in `adam`. */
+typedef struct {
+  float lr;            /* eta >= 0 */
+  float momentum;      /* mu in [0, 1): M = mu M + G */
+  float weight_decay;  /* lambda >= 0, decoupled: adds lambda W to the step direction */
+  float rms_scale;     /* >= 0; s = rms_scale * sqrt(max(rows, cols)); 0.2 aligns the update RMS with Adam's */
+  float ns_eps;        /* > 0, added to ||M||_F before the first iteration */
+  int32_t ns_steps;    /* Newton-Schulz iterations, 0..16 (5 in the published method) */
+  fvan_adam adam;      /* embeddings, head, biases, LayerNorm gains and shifts */
+} fvan_muon;
+
 typedef struct fvan_model fvan_model;
 typedef struct fvan_group fvan_group;
 
@@ -135,7 +150,8 @@ int fvan_destroy_model(fvan_model* model);
 
 /* Attach the caller's FP32 parameter vector [n_params] and gradient vector
  * [n_params] (grads may be NULL if no backward is run).  The library reads
- * params, writes params only in fvan_adam_step / fvan_train_step, and
+ * params, writes params only in the optimiser steps (fvan_adam_step, fvan_muon_step
+ * and the train steps), and
  * accumulates into grads.  Call fvan_sync_params after the caller changes params. */
 int fvan_bind_params(fvan_model* model, float* params, float* grads);
 
@@ -196,6 +212,31 @@ int fvan_adam_step(fvan_model* model, const fvan_adam* opt, int64_t step, void* 
  * The model's grads must be bound; they are zeroed by the update. */
 int fvan_train_step(fvan_model* model, const fvan_couplings* couplings, double beta, int32_t batch,
                     uint64_t seed, uint64_t step, const fvan_adam* opt, double* stats, void* stream);
+
+/* Newton-Schulz orthogonalisation used by Muon (Methods, comparison of
+ * optimisers; quintic iteration published with the Muon optimiser the paper
+ * cites, coefficients (a, b, c) = (3.4445, -4.7750, 2.0315)):
+ *   X_0 = M / (||M||_F + eps);  a wide X (rows <= cols) is iterated as
+ *   X <- a X + (b A + c A^2) X with A = X X^T, a tall one as its transpose;
+ *   O = X after `steps` iterations.
+ * M, O: FP32 row-major [rows, cols]; O may be M (in place).  FP32 MFMA
+ * products with FP32 accumulation, one workgroup.  EINVAL if rows or cols < 1,
+ * min(rows, cols) > 128, rows * cols >= 2^31, steps outside 0..16, or eps not
+ * finite and > 0. */
+int fvan_newton_schulz(int32_t rows, int32_t cols, int32_t steps, float eps, const float* M, float* O,
+                       void* stream);
+
+/* One Muon step on the bound parameters with the bound gradients (fvan_muon),
+ * then zero the gradients and refresh the packed weights.  step counts from 1
+ * (Adam bias correction of the non-matrix parameters).  Optimiser state: the
+ * momentum of the matrices shares the storage of Adam's first moment, so
+ * switching between fvan_adam_step and fvan_muon_step carries it over as is. */
+int fvan_muon_step(fvan_model* model, const fvan_muon* opt, int64_t step, void* stream);
+
+/* fvan_train_step with the Muon update (the paper's default optimiser) in
+ * place of Adam; same stats. */
+int fvan_train_step_muon(fvan_model* model, const fvan_couplings* couplings, double beta, int32_t batch,
+                         uint64_t seed, uint64_t step, const fvan_muon* opt, double* stats, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched launches: many (instance, temperature, size) units sampled in ONE

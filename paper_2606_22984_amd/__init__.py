@@ -27,6 +27,7 @@ EXPORTS = (
     "fvan_num_params", "fvan_derive_mask", "fvan_create_model", "fvan_destroy_model", "fvan_bind_params",
     "fvan_sync_params", "fvan_sample", "fvan_log_prob", "fvan_log_prob_backward", "fvan_energy",
     "fvan_free_energy", "fvan_reinforce_weights", "fvan_adam_step", "fvan_train_step",
+    "fvan_newton_schulz", "fvan_muon_step", "fvan_train_step_muon",
     "fvan_group_create", "fvan_group_destroy", "fvan_group_run", "fvan_group_run_graph", "fvan_last_error",
 )
 
@@ -50,6 +51,17 @@ class CouplingsC(C.Structure):
 class AdamC(C.Structure):
     _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
                 ("weight_decay", C.c_float)]
+
+
+class MuonC(C.Structure):
+    _fields_ = [("lr", C.c_float), ("momentum", C.c_float), ("weight_decay", C.c_float), ("rms_scale", C.c_float),
+                ("ns_eps", C.c_float), ("ns_steps", C.c_int32), ("adam", AdamC)]
+
+
+def muon_struct(lr=1e-3, momentum=0.95, weight_decay=0.0, rms_scale=0.2, ns_eps=1e-7, ns_steps=5, adam_lr=1e-3,
+                adam_beta1=0.9, adam_beta2=0.999, adam_eps=1e-8, adam_weight_decay=0.0) -> MuonC:
+    return MuonC(lr, momentum, weight_decay, rms_scale, ns_eps, ns_steps,
+                 AdamC(adam_lr, adam_beta1, adam_beta2, adam_eps, adam_weight_decay))
 
 
 class GroupUnitC(C.Structure):
@@ -81,6 +93,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "fvan_reinforce_weights": [I32, D, I32, P, P, P, P],
         "fvan_adam_step": [P, C.POINTER(AdamC), I64, P],
         "fvan_train_step": [P, C.POINTER(CouplingsC), D, I32, U64, U64, C.POINTER(AdamC), P, P],
+        "fvan_newton_schulz": [I32, I32, I32, C.c_float, P, P, P],
+        "fvan_muon_step": [P, C.POINTER(MuonC), I64, P],
+        "fvan_train_step_muon": [P, C.POINTER(CouplingsC), D, I32, U64, U64, C.POINTER(MuonC), P, P],
         "fvan_group_create": [C.POINTER(GroupUnitC), I32, I32, C.POINTER(C.c_void_p)],
         "fvan_group_destroy": [P],
         "fvan_group_run": [P, P],
@@ -254,6 +269,20 @@ class Model:
                                      _ptr(stats), _stream(stream)))
         return stats
 
+    def muon_step(self, step: int, stream=None, **hyper):
+        """One Muon step (fvan_muon_step); hyper: the keyword arguments of muon_struct."""
+        o = muon_struct(**hyper)
+        _check(lib().fvan_muon_step(self.handle, C.byref(o), step, _stream(stream)))
+
+    def train_step_muon(self, coup: Couplings, beta: float, batch: int, seed: int, step: int, stats=None,
+                        stream=None, **hyper):
+        if stats is None:
+            stats = torch.zeros(4, dtype=torch.float64, device=self.params.device)
+        o = muon_struct(**hyper)
+        _check(lib().fvan_train_step_muon(self.handle, C.byref(coup.c), beta, batch, seed, step, C.byref(o),
+                                          _ptr(stats), _stream(stream)))
+        return stats
+
     def close(self):
         if getattr(self, "handle", None):
             lib().fvan_destroy_model(self.handle)
@@ -264,6 +293,20 @@ class Model:
             self.close()
         except Exception:
             pass
+
+
+def newton_schulz(M: torch.Tensor, steps: int = 5, eps: float = 1e-7, out=None, stream=None):
+    """O = NewtonSchulz(M) for an FP32 device matrix (fvan_newton_schulz); out may be M."""
+    _require_cuda(M)
+    if M.dim() != 2 or M.dtype != torch.float32:
+        raise ValueError("newton_schulz takes a 2-D float32 matrix")
+    if out is None:
+        out = torch.empty_like(M)
+    _require_cuda(out)
+    if out.shape != M.shape or out.dtype != torch.float32:
+        raise ValueError("out must match M")
+    _check(lib().fvan_newton_schulz(M.shape[0], M.shape[1], steps, eps, _ptr(M), _ptr(out), _stream(stream)))
+    return out
 
 
 def energy(coup: Couplings, spins: torch.Tensor, out=None, stream=None):
@@ -354,6 +397,20 @@ class Group:
 
     def run_graph(self, stream=None):
         _check(lib().fvan_group_run_graph(self.handle, _stream(stream)))
+
+    def muon_step(self, step: int, stream=None, **hyper):
+        """One Muon step (fvan_muon_step); hyper: the keyword arguments of muon_struct."""
+        o = muon_struct(**hyper)
+        _check(lib().fvan_muon_step(self.handle, C.byref(o), step, _stream(stream)))
+
+    def train_step_muon(self, coup: Couplings, beta: float, batch: int, seed: int, step: int, stats=None,
+                        stream=None, **hyper):
+        if stats is None:
+            stats = torch.zeros(4, dtype=torch.float64, device=self.params.device)
+        o = muon_struct(**hyper)
+        _check(lib().fvan_train_step_muon(self.handle, C.byref(coup.c), beta, batch, seed, step, C.byref(o),
+                                          _ptr(stats), _stream(stream)))
+        return stats
 
     def close(self):
         if getattr(self, "handle", None):

@@ -235,11 +235,31 @@ int fvan_adam_step(fvan_model* m, const fvan_adam* opt, int64_t step, void* stre
   if (!m || !opt) return fail(FVAN_EINVAL, "NULL argument");
   if (!m->params || !m->grads) return fail(FVAN_EINVAL, "parameters and gradients must be bound");
   if (step < 1) return fail(FVAN_EINVAL, "step counts from 1");
-  if (!(opt->lr >= 0.f) || !(opt->beta1 >= 0.f && opt->beta1 < 1.f) || !(opt->beta2 >= 0.f && opt->beta2 < 1.f) ||
-      !(opt->eps > 0.f))
-    return fail(FVAN_EINVAL, "Adam hyper-parameters out of range");
+  if (const char* why = check_adam(*opt)) return fail(FVAN_EINVAL, why);
   hipStream_t s = (hipStream_t)stream;
   FVAN_HIP(launch_adam(m->params, m->grads, m->adam_m, m->adam_v, m->n_params, *opt, step, s));
+  FVAN_HIP(launch_pack(m->cfg, m->params, m->wpack, s));
+  return FVAN_OK;
+}
+
+int fvan_newton_schulz(int32_t rows, int32_t cols, int32_t steps, float eps, const float* M, float* O,
+                       void* stream) {
+  if (!M || !O) return fail(FVAN_EINVAL, "NULL argument");
+  if (rows < 1 || cols < 1 || std::min(rows, cols) > 128 || (int64_t)rows * cols >= ((int64_t)1 << 31))
+    return fail(FVAN_EINVAL, "Newton-Schulz needs 1 <= min(rows, cols) <= 128 and rows * cols < 2^31");
+  if (steps < 0 || steps > 16) return fail(FVAN_EINVAL, "Newton-Schulz steps must be in 0..16");
+  if (!(eps > 0.f) || !std::isfinite(eps)) return fail(FVAN_EINVAL, "eps must be finite and > 0");
+  FVAN_HIP(launch_newton_schulz(M, O, rows, cols, steps, eps, (hipStream_t)stream));
+  return FVAN_OK;
+}
+
+int fvan_muon_step(fvan_model* m, const fvan_muon* opt, int64_t step, void* stream) {
+  if (!m || !opt) return fail(FVAN_EINVAL, "NULL argument");
+  if (!m->params || !m->grads) return fail(FVAN_EINVAL, "parameters and gradients must be bound");
+  if (step < 1) return fail(FVAN_EINVAL, "step counts from 1");
+  if (const char* why = check_muon(*opt)) return fail(FVAN_EINVAL, why);
+  hipStream_t s = (hipStream_t)stream;
+  FVAN_HIP(launch_muon(m->cfg, m->params, m->grads, m->adam_m, m->adam_v, m->n_params, *opt, step, s));
   FVAN_HIP(launch_pack(m->cfg, m->params, m->wpack, s));
   return FVAN_OK;
 }

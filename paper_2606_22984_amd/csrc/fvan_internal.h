@@ -2,6 +2,8 @@
 // launchers each kernel source file provides.
 #pragma once
 
+#include <cmath>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -96,6 +98,24 @@ hipError_t launch_reinforce(int32_t batch, double beta, int is_int, const void* 
 hipError_t launch_pack(const fvan_model_config& c, const float* theta, void* wpack, hipStream_t s);
 hipError_t launch_adam(float* theta, float* grads, float* m, float* v, int64_t n, const fvan_adam& o,
                        int64_t step, hipStream_t s);
+// Host checks of optimiser hyper-parameters: NULL when valid, else the reason.
+inline const char* check_adam(const fvan_adam& o) {
+  const bool ok = o.lr >= 0.f && o.beta1 >= 0.f && o.beta1 < 1.f && o.beta2 >= 0.f && o.beta2 < 1.f && o.eps > 0.f &&
+                  std::isfinite(o.lr) && std::isfinite(o.eps) && std::isfinite(o.weight_decay);
+  return ok ? nullptr : "Adam hyper-parameters out of range";
+}
+inline const char* check_muon(const fvan_muon& o) {
+  const bool ok = o.lr >= 0.f && std::isfinite(o.lr) && o.momentum >= 0.f && o.momentum < 1.f &&
+                  o.weight_decay >= 0.f && std::isfinite(o.weight_decay) && o.rms_scale >= 0.f &&
+                  std::isfinite(o.rms_scale) && o.ns_eps > 0.f && std::isfinite(o.ns_eps) && o.ns_steps >= 0 &&
+                  o.ns_steps <= 16;
+  if (!ok) return "Muon hyper-parameters out of range";
+  return check_adam(o.adam);
+}
+
+hipError_t launch_newton_schulz(const float* M, float* O, int rows, int cols, int steps, float eps, hipStream_t s);
+hipError_t launch_muon(const fvan_model_config& c, float* theta, float* grads, float* m, float* v, int64_t n,
+                       const fvan_muon& o, int64_t step, hipStream_t s);
 hipError_t launch_grad_norm(const float* g, int64_t n, double* out, double* scratch, hipStream_t s);
 hipError_t launch_mean_energy(int32_t batch, int32_t n, int is_int, const void* energy, double* out,
                               hipStream_t s);

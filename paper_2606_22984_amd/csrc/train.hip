@@ -124,12 +124,15 @@ int fvan_log_prob_backward(fvan_model* m, int32_t batch, const int8_t* spins, co
   return FVAN_OK;
 }
 
-int fvan_train_step(fvan_model* m, const fvan_couplings* c, double beta, int32_t batch, uint64_t seed,
-                    uint64_t step, const fvan_adam* opt, double* stats, void* stream) {
-  if (!m || !c || !opt || !stats) return fail(FVAN_EINVAL, "NULL argument");
+// Everything of a training step before the update: sample, energies, F_q
+// statistics, REINFORCE weights, backward and the gradient norm.
+static int train_step_gradient(fvan_model* m, const fvan_couplings* c, double beta, int32_t batch, uint64_t seed,
+                               uint64_t step, double* stats, void* stream) {
+  if (!m || !c || !stats) return fail(FVAN_EINVAL, "NULL argument");
   if (c->n_spins != m->cfg.n_spins) return fail(FVAN_EINVAL, "couplings and model disagree on n_spins");
   if (!(beta > 0.0)) return fail(FVAN_EINVAL, "beta must be > 0");
   if (step < 1) return fail(FVAN_EINVAL, "step counts from 1");
+  if (!m->params || !m->grads) return fail(FVAN_EINVAL, "parameters and gradients must be bound");
   hipStream_t s = (hipStream_t)stream;
   int rc = fvan_sample(m, batch, seed, step, m->ts_spins, m->ts_logq, stream);
   if (rc) return rc;
@@ -141,7 +144,25 @@ int fvan_train_step(fvan_model* m, const fvan_couplings* c, double beta, int32_t
   FVAN_HIP(launch_reinforce(batch, beta, is_int, m->ts_energy, m->ts_logq, m->ts_w, nullptr, s));
   if ((rc = fvan_log_prob_backward(m, batch, m->ts_spins, m->ts_w, stream))) return rc;
   FVAN_HIP(launch_grad_norm(m->grads, m->n_params, stats + 3, nullptr, s));
+  return FVAN_OK;
+}
+
+int fvan_train_step(fvan_model* m, const fvan_couplings* c, double beta, int32_t batch, uint64_t seed,
+                    uint64_t step, const fvan_adam* opt, double* stats, void* stream) {
+  if (!opt) return fail(FVAN_EINVAL, "NULL argument");
+  if (const char* why = check_adam(*opt)) return fail(FVAN_EINVAL, why);
+  int rc = train_step_gradient(m, c, beta, batch, seed, step, stats, stream);
+  if (rc) return rc;
   return fvan_adam_step(m, opt, (int64_t)step, stream);
+}
+
+int fvan_train_step_muon(fvan_model* m, const fvan_couplings* c, double beta, int32_t batch, uint64_t seed,
+                         uint64_t step, const fvan_muon* opt, double* stats, void* stream) {
+  if (!opt) return fail(FVAN_EINVAL, "NULL argument");
+  if (const char* why = check_muon(*opt)) return fail(FVAN_EINVAL, why);
+  int rc = train_step_gradient(m, c, beta, batch, seed, step, stats, stream);
+  if (rc) return rc;
+  return fvan_muon_step(m, opt, (int64_t)step, stream);
 }
 
 }  // extern "C"

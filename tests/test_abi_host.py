@@ -79,3 +79,24 @@ def test_null_arguments_are_rejected():
     assert lib.fvan_free_energy(4, 4, -1.0, 0, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), None) == -1
     assert lib.fvan_reinforce_weights(0, 1.0, 0, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), None) == -1
     assert lib.fvan_destroy_model(None) == -1
+
+
+def test_newton_schulz_and_muon_argument_checks():
+    """Rejected on the host before anything is enqueued (no GPU needed)."""
+    lib, p = fv.lib(), C.c_void_p(8)
+    f = C.c_float
+    assert lib.fvan_newton_schulz(0, 4, 5, f(1e-7), p, p, None) == -1
+    assert lib.fvan_newton_schulz(4, -1, 5, f(1e-7), p, p, None) == -1
+    assert lib.fvan_newton_schulz(129, 200, 5, f(1e-7), p, p, None) == -1
+    assert lib.fvan_newton_schulz(200, 129, 5, f(1e-7), p, p, None) == -1
+    assert lib.fvan_newton_schulz(1 << 7, 1 << 24, 5, f(1e-7), p, p, None) == -1
+    assert lib.fvan_newton_schulz(8, 8, 17, f(1e-7), p, p, None) == -1
+    assert lib.fvan_newton_schulz(8, 8, -1, f(1e-7), p, p, None) == -1
+    assert lib.fvan_newton_schulz(8, 8, 5, f(0.0), p, p, None) == -1
+    assert lib.fvan_newton_schulz(8, 8, 5, f(float("inf")), p, p, None) == -1
+    assert lib.fvan_newton_schulz(8, 8, 5, f(1e-7), None, p, None) == -1
+    assert "Newton-Schulz" in lib.fvan_last_error().decode() or "eps" in lib.fvan_last_error().decode() \
+        or "NULL" in lib.fvan_last_error().decode()
+    o = fv.muon_struct()
+    assert lib.fvan_muon_step(None, C.byref(o), 1, None) == -1
+    assert lib.fvan_train_step_muon(None, None, 1.0, 1, 0, 1, C.byref(o), None, None) == -1
