@@ -106,6 +106,28 @@ constexpr int kKeyChunk = 128;                               // keys staged in L
 constexpr int kFwdThreads = 256, kDqThreads = 512, kDkvThreads = 256;
 __host__ __device__ constexpr int attn_rows(int threads) { return threads / 4; }   // 16 rows per wave
 
+// Work item of a 1-D attention grid of ntile * H * nsamp workgroups.  The
+// hardware deals workgroups to the 8 XCDs round-robin by id, so XCD x runs ids
+// x, x+8, ...  Each XCD is given a contiguous range of the (head fastest, then
+// tile, then sample) order instead: the heads and neighbouring tiles of a
+// sample run on one XCD and share its L2 (a head's 16 dims fill only part of a
+// cache line of Q, K, V or dO), and every XCD gets the same mix of prefix and
+// band tiles.
+struct AttnItem {
+  int tile, h, b;
+};
+__device__ __forceinline__ AttnItem attn_item(int ntile, int H) {
+  const int T = gridDim.x, L = blockIdx.x;
+  const int x = L & 7, slot = L >> 3, q = T >> 3, r = T & 7;
+  const int v = x * q + min(x, r) + slot;
+  AttnItem it;
+  it.h = v % H;
+  const int rest = v / H;
+  it.tile = rest % ntile;
+  it.b = rest / ntile;
+  return it;
+}
+
 // The keys a query tile [t0, t1) can see: [0, pend) then [bstart, t1), as one
 // virtual index v -> position.
 struct KeyRange {
@@ -214,7 +236,9 @@ __global__ __launch_bounds__(kFwdThreads) void attn_fwd_mfma(const KT* __restric
   __shared__ __align__(16) OT Ka[kKeyChunk][4];               // K, A layout
   __shared__ __align__(16) OT Vb[16][kKeyChunk / 4 + 1];      // V^T as the A operand: [dim][key group]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
-  const int t0 = blockIdx.x * attn_rows(kFwdThreads), h = blockIdx.y, b = blockIdx.z;
+  constexpr int R = attn_rows(kFwdThreads);
+  const AttnItem it = attn_item((N + R - 1) / R, H);
+  const int t0 = it.tile * R, h = it.h, b = it.b;
   const int t1 = min(t0 + attn_rows(kFwdThreads), N);
   const int64_t rowbase = (int64_t)b * N;
   const int tq = t0 + 16 * wave + c;                 // this lane's query
@@ -316,7 +340,9 @@ __global__ __launch_bounds__(kDqThreads) void attn_bwd_dq_mfma(const KT* __restr
   __shared__ __align__(16) OT Va[kKeyChunk][4];
   __shared__ __align__(16) OT Kb[16][kKeyChunk / 4 + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
-  const int t0 = blockIdx.x * attn_rows(kDqThreads), h = blockIdx.y, b = blockIdx.z;
+  constexpr int R = attn_rows(kDqThreads);
+  const AttnItem it = attn_item((N + R - 1) / R, H);
+  const int t0 = it.tile * R, h = it.h, b = it.b;
   const int t1 = min(t0 + attn_rows(kDqThreads), N);
   const int64_t rowbase = (int64_t)b * N;
   const KeyRange kr(t0, t1, W, P);
@@ -415,7 +441,8 @@ __global__ __launch_bounds__(kDkvThreads) void attn_bwd_dkv_mfma(const KT* __res
   __shared__ __align__(16) float Ls[QB];
   __shared__ __align__(16) float Ds[QB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
-  const int h = blockIdx.x, j0 = blockIdx.y * QB, b = blockIdx.z;
+  const AttnItem it = attn_item((N + QB - 1) / QB, H);
+  const int h = it.h, j0 = it.tile * QB, b = it.b;
   const int j1 = min(j0 + QB, N);
   const int64_t rowbase = (int64_t)b * N;
   const int jk = j0 + 16 * wave + c;               // this lane's key (B-operand column)

@@ -535,11 +535,11 @@ static hipError_t backward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp
     colsum_add(f.colpart, rgrid, 2 * D, f.colpart2, gl + m->po.ln2_g, s);
     // ---- attention backward (dO = dXM: the heads' output is added to the residual directly);
     // probabilities are recomputed from Q, K and the saved log-sum-exp
-    hipLaunchKernelGGL((attn_bwd_dq_mfma<KT, AT, MODE>), dim3((N + attn_rows(kDqThreads) - 1) / attn_rows(kDqThreads), H, nsamp),
+    hipLaunchKernelGGL((attn_bwd_dq_mfma<KT, AT, MODE>), dim3((N + attn_rows(kDqThreads) - 1) / attn_rows(kDqThreads) * H * nsamp),
                        dim3(kDqThreads), 0, s, QKV, X,
                        XM, (const float*)f.dXM, LSE, f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window,
                        m->kg.P);
-    hipLaunchKernelGGL((attn_bwd_dkv_mfma<KT, AT, MODE>), dim3(H, (N + attn_rows(kDkvThreads) - 1) / attn_rows(kDkvThreads), nsamp),
+    hipLaunchKernelGGL((attn_bwd_dkv_mfma<KT, AT, MODE>), dim3((N + attn_rows(kDkvThreads) - 1) / attn_rows(kDkvThreads) * H * nsamp),
                        dim3(kDkvThreads), 0, s, QKV,
                        (const float*)f.dXM, LSE, (const float*)f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H,
                        c.window, m->kg.P);

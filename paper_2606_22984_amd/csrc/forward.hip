@@ -97,7 +97,7 @@ hipError_t forward_layer(fvan_model* m, int l, int64_t rows, int nsamp, hipStrea
   hipError_t err = gemm_rows<MODE, D, 3 * D, EPI_STORE_KV>(nullptr, rows, wl + m->pk.qkv, e, s);
   if (err != hipSuccess) return err;
   const int H = c.n_heads;
-  hipLaunchKernelGGL((attn_fwd_mfma<KT, MODE>), dim3((c.n_spins + attn_rows(kFwdThreads) - 1) / attn_rows(kFwdThreads), H, nsamp),
+  hipLaunchKernelGGL((attn_fwd_mfma<KT, MODE>), dim3((c.n_spins + attn_rows(kFwdThreads) - 1) / attn_rows(kFwdThreads) * H * nsamp),
                      dim3(kFwdThreads), 0, s,
                      (const KT*)QKV, X, XM, LSE, c.n_spins, D, H, c.window, m->kg.P);
   hipLaunchKernelGGL((ffn_fused_kernel<MODE, D>), dim3((int)((rows + kFfnRows - 1) / kFfnRows)), dim3(256), 0, s,
