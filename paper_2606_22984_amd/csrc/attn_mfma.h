@@ -106,20 +106,16 @@ constexpr int kKeyChunk = 128;                               // keys staged in L
 constexpr int kFwdThreads = 256, kDqThreads = 512, kDkvThreads = 256;
 __host__ __device__ constexpr int attn_rows(int threads) { return threads / 4; }   // 16 rows per wave
 
-// Work item of a 1-D attention grid of ntile * H * nsamp workgroups.  The
-// hardware deals workgroups to the 8 XCDs round-robin by id, so XCD x runs ids
-// x, x+8, ...  Each XCD is given a contiguous range of the (head fastest, then
-// tile, then sample) order instead: the heads and neighbouring tiles of a
-// sample run on one XCD and share its L2 (a head's 16 dims fill only part of a
-// cache line of Q, K, V or dO), and every XCD gets the same mix of prefix and
-// band tiles.
+// Work item of a 1-D attention grid of ntile * H * nsamp workgroups, in (head
+// fastest, then tile, then sample) order dealt to the XCDs in contiguous
+// ranges: the heads and neighbouring tiles of a sample run on one XCD and share
+// its L2 (a head's 16 dims fill only part of a cache line of Q, K, V or dO),
+// and every XCD gets the same mix of prefix and band tiles.
 struct AttnItem {
   int tile, h, b;
 };
 __device__ __forceinline__ AttnItem attn_item(int ntile, int H) {
-  const int T = gridDim.x, L = blockIdx.x;
-  const int x = L & 7, slot = L >> 3, q = T >> 3, r = T & 7;
-  const int v = x * q + min(x, r) + slot;
+  const int v = xcd_contiguous(blockIdx.x, gridDim.x);
   AttnItem it;
   it.h = v % H;
   const int rest = v / H;

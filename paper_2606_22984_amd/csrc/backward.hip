@@ -170,8 +170,8 @@ __global__ __launch_bounds__(256) void transpose_cast_kernel(const float* __rest
 // ---------------------------------------------------------------- weight-gradient GEMM
 // part[s][m][n] = sum_{k in slice s, k < K} A[m][k] B[n][k]; A [m_total x lda]
 // and B [NB x ldb] feature-major, K = rows of the chunk.  One workgroup (8 waves)
-// owns an M x NB block (rows blockIdx.y * M ..) of the output for its K slice, so
-// each operand element is read from HBM once per block; K chunks are staged in LDS (the next chunk is fetched into
+// owns an M x NB block of the output (row block mbi, column block nbi) for its K slice, so
+// the blocks of one K slice read its operand slices close in time on one XCD (L2 reuse); K chunks are staged in LDS (the next chunk is fetched into
 // registers while the current one is multiplied) and every wave keeps a block of
 // RT x CT accumulator tiles (rows split over WRG wave groups, columns over WCG).
 template <int MT>
@@ -185,7 +185,7 @@ template <int MODE, int M, int NB>
 __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::ActT* __restrict__ A, int64_t lda,
                                                     const typename Mode<MODE>::ActT* __restrict__ B, int64_t ldb,
                                                     int64_t K, int64_t kper, int m_total, int n_total,
-                                                    float* __restrict__ part) {
+                                                    int nsplit_m, int nsplit_n, float* __restrict__ part) {
   typedef typename Mode<MODE>::ActT AT;
   // split mode stages each operand already split into BF16 hi and lo planes, so a
   // K chunk is converted once instead of once per wave that multiplies it
@@ -204,9 +204,13 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
   __shared__ __attribute__((aligned(16))) ST Bs[NPL][NB][PADK];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave / WCG, wc = wave % WCG;
-  const int s = blockIdx.x;
-  A += (int64_t)blockIdx.y * M * lda;              // this workgroup's block of M output rows
-  B += (int64_t)blockIdx.z * NB * ldb;             // and of NB output columns
+  // 1-D grid over (column block fastest, then row block, then K slice), dealt to
+  // the XCDs in contiguous ranges: the workgroups of one K slice read the same
+  // operand slice close in time on one XCD
+  const int v = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int nbi = v % nsplit_n, mbi = (v / nsplit_n) % nsplit_m, s = v / (nsplit_n * nsplit_m);
+  A += (int64_t)mbi * M * lda;                     // this workgroup's block of M output rows
+  B += (int64_t)nbi * NB * ldb;                    // and of NB output columns
   const int64_t kb = (int64_t)s * kper;
   const int64_t ke = std::min<int64_t>(K, kb + kper);
   floatx4 acc[RT][CT];
@@ -313,7 +317,7 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
     }
     __syncthreads();
   }
-  float* out = part + ((size_t)s * m_total + (size_t)blockIdx.y * M) * n_total + (size_t)blockIdx.z * NB;
+  float* out = part + ((size_t)s * m_total + (size_t)mbi * M) * n_total + (size_t)nbi * NB;
 #pragma unroll
   for (int i = 0; i < RT; ++i) {
 #pragma unroll
@@ -358,8 +362,8 @@ static hipError_t wgrad(fvan_model* m, const void* A, const void* B, int64_t K, 
   // the smaller operand
   constexpr int MS = M >= 512 ? M / 2 : M;
   constexpr int NBS = NB >= 512 && NB % 48 == 0 ? NB / 3 : NB;
-  hipLaunchKernelGGL((wgrad_kernel<MODE, MS, NBS>), dim3(S, M / MS, NB / NBS), dim3(512), 0, s, (const AT*)A,
-                     f.ldT, (const AT*)B, f.ldT, K, kper, M, NB, f.part);
+  hipLaunchKernelGGL((wgrad_kernel<MODE, MS, NBS>), dim3(S * (M / MS) * (NB / NBS)), dim3(512), 0, s, (const AT*)A,
+                     f.ldT, (const AT*)B, f.ldT, K, kper, M, NB, M / MS, NB / NBS, f.part);
   const int total = M * (Nw + 1);
   hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(std::min(1024, (total + 255) / 256)), dim3(256), 0, s,
                      (const float*)f.part, S, M, NB, Nw, gW, gb);

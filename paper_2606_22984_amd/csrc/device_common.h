@@ -287,4 +287,16 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 }
 __device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * 5.9604644775390625e-8f; }
 
+
+// Index v of the work item a workgroup runs, for a 1-D grid of T workgroups
+// whose work items are numbered so that items sharing data are adjacent.  The
+// hardware deals workgroups to the 8 XCDs round-robin by id (XCD x runs ids
+// x, x+8, ...); this gives XCD x the contiguous range of items starting at
+// x * floor(T/8) + min(x, T mod 8), so adjacent items run on one XCD, close in
+// time, and share its L2.  A bijection of [0, T).
+__device__ __forceinline__ int xcd_contiguous(int L, int T) {
+  const int x = L & 7, slot = L >> 3, q = T >> 3, r = T & 7;
+  return x * q + min(x, r) + slot;
+}
+
 }  // namespace fvan
