@@ -148,22 +148,56 @@ static void colsum_add(const float* part, int n, int width, float* part2, float*
 
 // ---------------------------------------------------------------- transpose + cast
 // dY (float, [rows x D]) -> Yrm (ActT, row-major; skipped when NULL) and YT (ActT, [D x ldT]).
+// 16-byte loads and stores: each thread moves four consecutive features of a
+// row in, and four consecutive rows of a feature out (ldT is a multiple of 64).
 template <int D, typename AT>
 __global__ __launch_bounds__(256) void transpose_cast_kernel(const float* __restrict__ Y, int64_t rows,
                                                              AT* __restrict__ Yrm, AT* __restrict__ YT, int64_t ldT) {
   __shared__ float tile[64][D + 1];
+  constexpr int NV = 64 * D / 4 / 256;             // float4 per thread
   const int64_t r0 = (int64_t)blockIdx.x * 64;
-  for (int i = threadIdx.x; i < 64 * D; i += 256) {
-    const int rr = i / D, k = i % D;
+  float4 v[NV];
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    const int rr = i / (D / 4), k = 4 * (i % (D / 4));
     const int64_t r = r0 + rr;
-    const float v = r < rows ? Y[r * D + k] : 0.f;
-    tile[rr][k] = v;
-    if (Yrm && r < rows) Yrm[r * D + k] = from_f<AT>(v);
+    v[u] = r < rows ? *reinterpret_cast<const float4*>(Y + r * D + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    const int rr = i / (D / 4), k = 4 * (i % (D / 4));
+    tile[rr][k] = v[u].x;
+    tile[rr][k + 1] = v[u].y;
+    tile[rr][k + 2] = v[u].z;
+    tile[rr][k + 3] = v[u].w;
+    const int64_t r = r0 + rr;
+    if (Yrm && r < rows) {
+      AT* d = Yrm + r * D + k;
+      d[0] = from_f<AT>(v[u].x);
+      d[1] = from_f<AT>(v[u].y);
+      d[2] = from_f<AT>(v[u].z);
+      d[3] = from_f<AT>(v[u].w);
+    }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 64 * D; i += 256) {
-    const int k = i >> 6, rr = i & 63;
-    if (r0 + rr < rows) YT[(int64_t)k * ldT + r0 + rr] = from_f<AT>(tile[rr][k]);
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    const int k = i / 16, rr = 4 * (i % 16);
+    const int64_t r = r0 + rr;
+    AT* d = YT + (int64_t)k * ldT + r;
+    if (r + 3 < rows) {
+      if constexpr (sizeof(AT) == 4) {
+        *reinterpret_cast<float4*>(d) = make_float4(tile[rr][k], tile[rr + 1][k], tile[rr + 2][k], tile[rr + 3][k]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d[e] = from_f<AT>(tile[rr + e][k]);
+      }
+    } else {
+      for (int e = 0; e < 4 && r + e < rows; ++e) d[e] = from_f<AT>(tile[rr + e][k]);
+    }
   }
 }
 
@@ -333,15 +367,36 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
 }
 
 // grads: W[m][n] += sum_s part[s][m][n] for n < Nw; bias[m] += sum_s part[s][m][Nw].
-__global__ void wgrad_reduce_kernel(const float* __restrict__ part, int S, int M, int NB, int Nw,
-                                    float* __restrict__ gW, float* __restrict__ gb) {
+// A block owns 64 consecutive outputs; its four thread groups sum the slices
+// s = grp, grp + 4, ... (eight loads in flight each) and the four partial sums
+// are added in a fixed order: bitwise reproducible.
+constexpr int kRedOut = 64, kRedGroups = 4;
+__global__ __launch_bounds__(kRedOut * kRedGroups) void wgrad_reduce_kernel(const float* __restrict__ part, int S,
+                                                                            int M, int NB, int Nw,
+                                                                            float* __restrict__ gW,
+                                                                            float* __restrict__ gb) {
+  __shared__ float red[kRedGroups][kRedOut];
   const int total = M * (Nw + 1);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-    const int m = i / (Nw + 1), n = i % (Nw + 1);
-    float acc = 0.f;
-    for (int s = 0; s < S; ++s) acc += part[((size_t)s * M + m) * NB + n];
-    if (n < Nw) gW[(size_t)m * Nw + n] += acc;
-    else gb[m] += acc;
+  const int o = threadIdx.x % kRedOut, grp = threadIdx.x / kRedOut;
+  const int i = blockIdx.x * kRedOut + o;
+  const int m = i / (Nw + 1), n = i % (Nw + 1);
+  const size_t stride = (size_t)M * NB;
+  const float* p = part + (size_t)min(m, M - 1) * NB + n;
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (i < total) {
+    int s = grp;
+    for (; s + 7 * kRedGroups < S; s += 8 * kRedGroups) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += p[(size_t)(s + u * kRedGroups) * stride];
+    }
+    for (; s < S; s += kRedGroups) acc[0] += p[(size_t)s * stride];
+  }
+  red[grp][o] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  __syncthreads();
+  if (grp == 0 && i < total) {
+    const float v = ((red[0][o] + red[1][o]) + red[2][o]) + red[3][o];
+    if (n < Nw) gW[(size_t)m * Nw + n] += v;
+    else gb[m] += v;
   }
 }
 
@@ -365,7 +420,7 @@ static hipError_t wgrad(fvan_model* m, const void* A, const void* B, int64_t K, 
   hipLaunchKernelGGL((wgrad_kernel<MODE, MS, NBS>), dim3(S * (M / MS) * (NB / NBS)), dim3(512), 0, s, (const AT*)A,
                      f.ldT, (const AT*)B, f.ldT, K, kper, M, NB, M / MS, NB / NBS, f.part);
   const int total = M * (Nw + 1);
-  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(std::min(1024, (total + 255) / 256)), dim3(256), 0, s,
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((total + kRedOut - 1) / kRedOut), dim3(kRedOut * kRedGroups), 0, s,
                      (const float*)f.part, S, M, NB, Nw, gW, gb);
   return hipGetLastError();
 }
