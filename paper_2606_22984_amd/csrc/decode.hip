@@ -87,9 +87,23 @@ __device__ __forceinline__ void mfma_rowtiles(const typename Mode<MODE>::ActT* A
   const typename Mode<MODE>::ActT* arow = A + (lane & 15) * lda + (lane >> 4) * (KC / 4);
   const typename Mode<MODE>::ActT* arow1 = arow + 16 * lda;
   const uint4* bp = pack + (size_t)nt * NC * 64 + lane;
+  // the weight fragments of G chunks are loaded together, so one L2 latency
+  // is exposed per G chunks instead of per chunk
+  constexpr int GM = Mode<MODE>::SPLIT ? 2 : 4;
+  constexpr int G = NC < GM ? NC : GM;
+  static_assert(NC % G == 0, "K chunks in groups of G");
 #pragma unroll 1
-  for (int c = 0; c < NC; ++c)
-    Frag<MODE>::step2(arow + c * KC, arow1 + c * KC, bp + c * 64, bp + c * 64 + lo_u4, acc0, acc1);
+  for (int c0 = 0; c0 < NC; c0 += G) {
+    uint4 bh[G], bl[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      bh[u] = bp[(c0 + u) * 64];
+      bl[u] = Mode<MODE>::SPLIT ? bp[(c0 + u) * 64 + lo_u4] : bh[u];
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+      Frag<MODE>::step2v(arow + (c0 + u) * KC, arow1 + (c0 + u) * KC, bh[u], bl[u], acc0, acc1);
+  }
 }
 
 template <int D, int MODE>

@@ -117,7 +117,11 @@ template <> struct Frag<0> {
   // two 16-row A tiles against one B fragment (loaded once)
   static __device__ __forceinline__ void step2(const float* a0, const float* a1, const uint4* b, const uint4*,
                                                floatx4& acc0, floatx4& acc1) {
-    const uint4 bv = *b;
+    step2v(a0, a1, *b, *b, acc0, acc1);
+  }
+  // the same with the B fragment already in registers
+  static __device__ __forceinline__ void step2v(const float* a0, const float* a1, const uint4 bv, const uint4,
+                                                floatx4& acc0, floatx4& acc1) {
     const float4 x = *reinterpret_cast<const float4*>(a0), y = *reinterpret_cast<const float4*>(a1);
     const float b0 = __uint_as_float(bv.x), b1 = __uint_as_float(bv.y), b2 = __uint_as_float(bv.z),
                 b3 = __uint_as_float(bv.w);
@@ -137,7 +141,10 @@ template <> struct Frag<1> {
   }
   static __device__ __forceinline__ void step2(const __bf16* a0, const __bf16* a1, const uint4* b, const uint4*,
                                                floatx4& acc0, floatx4& acc1) {
-    const uint4 bv = *b;
+    step2v(a0, a1, *b, *b, acc0, acc1);
+  }
+  static __device__ __forceinline__ void step2v(const __bf16* a0, const __bf16* a1, const uint4 bv, const uint4,
+                                                floatx4& acc0, floatx4& acc1) {
     acc0 = mfma_bf16(*reinterpret_cast<const uint4*>(a0), bv, acc0);
     acc1 = mfma_bf16(*reinterpret_cast<const uint4*>(a1), bv, acc1);
   }
@@ -164,10 +171,13 @@ template <> struct Frag<2> {
   }
   static __device__ __forceinline__ void step2(const float* a0, const float* a1, const uint4* b, const uint4* blo,
                                                floatx4& acc0, floatx4& acc1) {
+    step2v(a0, a1, *b, *blo, acc0, acc1);
+  }
+  static __device__ __forceinline__ void step2v(const float* a0, const float* a1, const uint4 bh, const uint4 bl,
+                                                floatx4& acc0, floatx4& acc1) {
     uint4 xh, xl, yh, yl;
     split_a(a0, xh, xl);
     split_a(a1, yh, yl);
-    const uint4 bh = *b, bl = *blo;
     acc0 = mfma_bf16(xl, bh, acc0);
     acc1 = mfma_bf16(yl, bh, acc1);
     acc0 = mfma_bf16(xh, bl, acc0);
