@@ -76,7 +76,7 @@ int64_t fwd_chunk_samples(const fvan_model_config& c) {
   // about 2^21 rows (positions) per chunk of the teacher-forced passes
   int64_t s = std::max<int64_t>(1, (int64_t(1) << 21) / c.n_spins);
   s = std::min<int64_t>(s, c.max_batch);
-  return std::min<int64_t>(s, 65535);   // samples are the z index of the attention grids
+  return std::min<int64_t>(s, 65535);   // keeps the 1-D attention grids (tiles x heads x samples) in int range
 }
 
 static fvan_model_config clamp_mask(fvan_model_config c) {
