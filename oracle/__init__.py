@@ -7,8 +7,9 @@ Glasses"): the autoregressive factorisation (Eq. 1, Eq. 11), the spin energies
 blocks with masked multi-head attention and no output projection (Eqs. 2-3,
 Alg. 1, Alg. 2), the variational free energy (Eqs. 4-5) and its REINFORCE
 gradient (Eqs. 16-19), the Muon update with Newton-Schulz orthogonalisation
-(Methods, comparison of optimisers), and the ordered Markov boundary that sets
-the sparse attention window (Methods, ordered Markov boundary; SI Sec. I A).
+(Methods, comparison of optimisers), the local Monte Carlo refinement and the
+self-distillation weights of Eq. (loss2), and the ordered Markov boundary that
+sets the sparse attention window (Methods, ordered Markov boundary; SI Sec. I A).
 
 Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  It shares no code with the HIP path: the two sides agree
@@ -17,4 +18,4 @@ definition), never by a common helper.
 
 Precision: float64 throughout; the sampling decision u < p uses float64 p.
 """
-from . import philox, physics, network, sampler, estimator, markov, exact, muon  # noqa: F401
+from . import philox, physics, network, sampler, estimator, markov, exact, muon, refine  # noqa: F401
