@@ -108,6 +108,18 @@ typedef struct {
   float lr, beta1, beta2, eps, weight_decay;
 } fvan_adam;
 
+/* Neighbour graph for local Monte Carlo refinement: every neighbour of a site
+ * (both directions of each pair, unlike fvan_couplings), -1 for an empty slot,
+ * and a 2-colouring of the sites. */
+typedef struct {
+  int32_t degree;          /* slots per site, >= 1 */
+  const int32_t* nbr;      /* device int32 [n_spins, degree] */
+  const float* J;          /* device float [n_spins, degree]: bond of each slot (+-1.0 for +-J bonds) */
+  const int8_t* colour;    /* device int8 [n_spins], 0 or 1; a proper colouring (no bond inside a colour)
+                              makes every half-sweep exact sequential single-site Metropolis */
+  int32_t sweeps;          /* checkerboard sweeps, >= 0 */
+} fvan_lmc;
+
 /* Muon (Methods, comparison of optimisers: momentum M, Newton-Schulz
  * orthogonalisation O of M, step W -= eta (s O + lambda W), with the weight
  * decay and RMS scale alignment the paper takes from the Muon-at-scale work it
@@ -233,10 +245,45 @@ int fvan_newton_schulz(int32_t rows, int32_t cols, int32_t steps, float eps, con
  * switching between fvan_adam_step and fvan_muon_step carries it over as is. */
 int fvan_muon_step(fvan_model* model, const fvan_muon* opt, int64_t step, void* stream);
 
+/* Local Monte Carlo refinement (Results, 3D EA; Methods, training strategy;
+ * SI Sec. I C): lmc->sweeps checkerboard Metropolis sweeps at inverse
+ * temperature beta on each configuration of spins [batch, n_spins], in place.
+ * A sweep updates the sites of colour 0, then those of colour 1; within a
+ * half-sweep every local field h_i = sum_j J_ij s_j comes from the
+ * configuration at its start.  Flipping s_i changes E (Eq. 8) by
+ * dE = 2 s_i h_i; the flip is accepted iff u < exp(-beta dE) (FP32), with
+ *   u(b, k, i) = (word[i & 3] >> 8) * 2^-24 of Philox4x32-10,
+ *   key = (seed mod 2^32, seed >> 32), counter = (i >> 2, b, k, stream_tag).
+ * accepted: device int32 [batch] accepted flips per configuration, or NULL.
+ * EINVAL on NULL graph arrays, n_spins outside [1, 16384], degree < 1,
+ * sweeps < 0, batch < 1, or beta not finite and >= 0. */
+int fvan_lmc_refine(int32_t n_spins, const fvan_lmc* lmc, int32_t batch, double beta, uint64_t seed,
+                    uint32_t stream_tag, int8_t* spins, int32_t* accepted, void* stream);
+
+/* Weights of the self-distillation gradient, Eq. (loss2), on M = batch
+ * (refined) configurations with their energies and teacher-forced log q:
+ *   L_m = beta E_m + log_q_m,  Lbar = mean_m L_m (FP64),
+ *   weights[m] = (L_m - Lbar) / (beta M) - w / M,
+ * so that sum_m weights[m] grad ln q_m is the REINFORCE gradient of F_q plus
+ * w times the likelihood term (w = 0: fvan_reinforce_weights). */
+int fvan_distill_weights(int32_t batch, double beta, double w, int32_t energy_is_int, const void* energy,
+                         const float* log_q, float* weights, void* stream);
+
 /* fvan_train_step with the Muon update (the paper's default optimiser) in
  * place of Adam; same stats. */
 int fvan_train_step_muon(fvan_model* model, const fvan_couplings* couplings, double beta, int32_t batch,
                          uint64_t seed, uint64_t step, const fvan_muon* opt, double* stats, void* stream);
+
+/* One training step of the paper's 3D EA procedure (Results, 3D EA; Methods,
+ * training strategy): sample (seed, stream_id = step); energies and the F_q
+ * statistics of the raw samples (stats as fvan_train_step); refine the samples
+ * in place with fvan_lmc_refine (key seed, stream_tag = 2^31 | (step mod 2^31));
+ * energies and teacher-forced log q of the refined samples; weights of
+ * Eq. (loss2) with likelihood weight w; backward; gradient norm; Muon update.
+ * The refined samples stay in the model's sample buffer. */
+int fvan_train_step_distill(fvan_model* model, const fvan_couplings* couplings, const fvan_lmc* lmc, double beta,
+                            double w, int32_t batch, uint64_t seed, uint64_t step, const fvan_muon* opt,
+                            double* stats, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched launches: many (instance, temperature, size) units sampled in ONE

@@ -80,23 +80,33 @@ def local_fields(spins, adj) -> np.ndarray:
 
 
 def metropolis_checkerboard(spins, adj, colour, beta: float, sweeps: int, seed: int, stream: int, b0: int = 0,
-                            uniforms=None):
+                            uniforms=None, margins: bool = False):
     """Refined copy of spins (int8 +-1 [batch, n]) after `sweeps` checkerboard sweeps.
-    Returns (spins, accepted flips per sample).  uniforms(sweep) -> [batch, n] may
-    replace the Philox draw (tests)."""
+    Returns (spins, accepted flips per sample), plus with margins=True the
+    smallest |u - exp(-beta dE)| per sample over its decisions with
+    exp(-beta dE) < 1 (how close a decision came to the other outcome).
+    uniforms(sweep) -> [batch, n] may replace the Philox draw (tests)."""
     s = np.array(spins, dtype=np.int64)
     batch, n = s.shape
     colour = np.asarray(colour)
     acc = np.zeros(batch, dtype=np.int64)
+    marg = np.full(batch, np.inf)
     for k in range(sweeps):
         u = uniforms(k) if uniforms is not None else lmc_uniforms(seed, stream, batch, n, k, b0)
         for c in (0, 1):
             h = local_fields(s, adj)
             dE = 2.0 * s * h
+            mine = colour[None, :] == c
             with np.errstate(over="ignore"):
-                flip = (u < np.exp(-beta * dE)) & (colour[None, :] == c)
+                p = np.exp(-beta * dE)
+            flip = (u < p) & mine
+            if margins:
+                d = np.where(mine & (p < 1.0), np.abs(u - p), np.inf)
+                marg = np.minimum(marg, d.min(axis=1))
             s = np.where(flip, -s, s)
             acc += flip.sum(axis=1)
+    if margins:
+        return s.astype(np.int8), acc, marg
     return s.astype(np.int8), acc
 
 

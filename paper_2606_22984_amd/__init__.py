@@ -28,6 +28,7 @@ EXPORTS = (
     "fvan_sync_params", "fvan_sample", "fvan_log_prob", "fvan_log_prob_backward", "fvan_energy",
     "fvan_free_energy", "fvan_reinforce_weights", "fvan_adam_step", "fvan_train_step",
     "fvan_newton_schulz", "fvan_muon_step", "fvan_train_step_muon",
+    "fvan_lmc_refine", "fvan_distill_weights", "fvan_train_step_distill",
     "fvan_group_create", "fvan_group_destroy", "fvan_group_run", "fvan_group_run_graph", "fvan_last_error",
 )
 
@@ -64,6 +65,11 @@ def muon_struct(lr=1e-3, momentum=0.95, weight_decay=0.0, rms_scale=0.2, ns_eps=
                  AdamC(adam_lr, adam_beta1, adam_beta2, adam_eps, adam_weight_decay))
 
 
+class LmcC(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("nbr", C.c_void_p), ("J", C.c_void_p), ("colour", C.c_void_p),
+                ("sweeps", C.c_int32)]
+
+
 class GroupUnitC(C.Structure):
     _fields_ = [("model", C.c_void_p), ("couplings", C.c_void_p), ("beta", C.c_double), ("batch", C.c_int32),
                 ("seed", C.c_uint64), ("stream_id", C.c_uint64), ("spins", C.c_void_p), ("log_q", C.c_void_p),
@@ -96,6 +102,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "fvan_newton_schulz": [I32, I32, I32, C.c_float, P, P, P],
         "fvan_muon_step": [P, C.POINTER(MuonC), I64, P],
         "fvan_train_step_muon": [P, C.POINTER(CouplingsC), D, I32, U64, U64, C.POINTER(MuonC), P, P],
+        "fvan_lmc_refine": [I32, C.POINTER(LmcC), I32, D, U64, C.c_uint32, P, P, P],
+        "fvan_distill_weights": [I32, D, D, I32, P, P, P, P],
+        "fvan_train_step_distill": [P, C.POINTER(CouplingsC), C.POINTER(LmcC), D, D, I32, U64, U64,
+                                    C.POINTER(MuonC), P, P],
         "fvan_group_create": [C.POINTER(GroupUnitC), I32, I32, C.POINTER(C.c_void_p)],
         "fvan_group_destroy": [P],
         "fvan_group_run": [P, P],
@@ -179,6 +189,67 @@ class Couplings:
 
     def empty_energy(self, batch: int, device="cuda") -> torch.Tensor:
         return torch.empty(batch, dtype=torch.int32 if self.energy_is_int else torch.float32, device=device)
+
+
+@dataclass
+class LmcGraph:
+    """Device-resident neighbour table (both directions of every pair), bonds and
+    checkerboard colours for fvan_lmc_refine, and the C struct pointing at them."""
+    n: int
+    nbr: torch.Tensor
+    J: torch.Tensor
+    colour: torch.Tensor
+    c: LmcC
+
+
+def lmc_graph(instance, sweeps: int, device="cuda") -> LmcGraph:
+    """Neighbour graph of a lattice instance with its checkerboard colouring
+    (sum of the raster coordinates mod 2, last coordinate fastest)."""
+    if getattr(instance, "L", None) is None:
+        raise ValueError("checkerboard refinement needs a lattice instance")
+    n = instance.n
+    adj = [[] for _ in range(n)]
+    for a, b, w in zip(np.asarray(instance.edges_i).tolist(), np.asarray(instance.edges_j).tolist(),
+                       np.asarray(instance.J).tolist()):
+        adj[a].append((b, w))
+        adj[b].append((a, w))
+    deg = max(1, max(len(x) for x in adj))
+    nbr = -np.ones((n, deg), dtype=np.int32)
+    Jl = np.zeros((n, deg), dtype=np.float32)
+    for i, lst in enumerate(adj):
+        for k, (j, w) in enumerate(lst):
+            nbr[i, k] = j
+            Jl[i, k] = w
+    idx = np.arange(n)
+    col = np.zeros(n, dtype=np.int64)
+    for _ in range(instance.dim):
+        col += idx % instance.L
+        idx //= instance.L
+    t_nbr = torch.as_tensor(nbr, device=device)
+    t_J = torch.as_tensor(Jl, device=device)
+    t_col = torch.as_tensor((col % 2).astype(np.int8), device=device)
+    c = LmcC(degree=deg, nbr=t_nbr.data_ptr(), J=t_J.data_ptr(), colour=t_col.data_ptr(), sweeps=sweeps)
+    return LmcGraph(n, t_nbr, t_J, t_col, c)
+
+
+def lmc_refine(graph: LmcGraph, spins: torch.Tensor, beta: float, seed: int, stream_tag: int, accepted=None,
+               stream=None):
+    """Checkerboard Metropolis sweeps on spins [batch, n] in place (fvan_lmc_refine)."""
+    _require_cuda(spins, accepted)
+    _check(lib().fvan_lmc_refine(graph.n, C.byref(graph.c), spins.shape[0], beta, seed, stream_tag, _ptr(spins),
+                                 _ptr(accepted), _stream(stream)))
+    return spins
+
+
+def distill_weights(E: torch.Tensor, log_q: torch.Tensor, beta: float, w: float, out=None, stream=None):
+    """Weights of the self-distillation gradient, Eq. (loss2) (fvan_distill_weights)."""
+    _require_cuda(E, log_q)
+    if out is None:
+        out = torch.empty(log_q.shape[0], dtype=torch.float32, device=log_q.device)
+    is_int = 1 if E.dtype == torch.int32 else 0
+    _check(lib().fvan_distill_weights(log_q.shape[0], beta, w, is_int, _ptr(E), _ptr(log_q), _ptr(out),
+                                      _stream(stream)))
+    return out
 
 
 def couplings(instance, device="cuda", dense: Optional[bool] = None) -> Couplings:
@@ -281,6 +352,15 @@ class Model:
         o = muon_struct(**hyper)
         _check(lib().fvan_train_step_muon(self.handle, C.byref(coup.c), beta, batch, seed, step, C.byref(o),
                                           _ptr(stats), _stream(stream)))
+        return stats
+
+    def train_step_distill(self, coup: Couplings, graph: LmcGraph, beta: float, w: float, batch: int, seed: int,
+                           step: int, stats=None, stream=None, **hyper):
+        if stats is None:
+            stats = torch.zeros(4, dtype=torch.float64, device=self.params.device)
+        o = muon_struct(**hyper)
+        _check(lib().fvan_train_step_distill(self.handle, C.byref(coup.c), C.byref(graph.c), beta, w, batch, seed,
+                                             step, C.byref(o), _ptr(stats), _stream(stream)))
         return stats
 
     def close(self):
@@ -410,6 +490,15 @@ class Group:
         o = muon_struct(**hyper)
         _check(lib().fvan_train_step_muon(self.handle, C.byref(coup.c), beta, batch, seed, step, C.byref(o),
                                           _ptr(stats), _stream(stream)))
+        return stats
+
+    def train_step_distill(self, coup: Couplings, graph: LmcGraph, beta: float, w: float, batch: int, seed: int,
+                           step: int, stats=None, stream=None, **hyper):
+        if stats is None:
+            stats = torch.zeros(4, dtype=torch.float64, device=self.params.device)
+        o = muon_struct(**hyper)
+        _check(lib().fvan_train_step_distill(self.handle, C.byref(coup.c), C.byref(graph.c), beta, w, batch, seed,
+                                             step, C.byref(o), _ptr(stats), _stream(stream)))
         return stats
 
     def close(self):

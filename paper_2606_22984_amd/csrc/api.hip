@@ -242,6 +242,28 @@ int fvan_adam_step(fvan_model* m, const fvan_adam* opt, int64_t step, void* stre
   return FVAN_OK;
 }
 
+int fvan_lmc_refine(int32_t n, const fvan_lmc* g, int32_t batch, double beta, uint64_t seed, uint32_t tag,
+                    int8_t* spins, int32_t* accepted, void* stream) {
+  if (!g || !spins) return fail(FVAN_EINVAL, "NULL argument");
+  if (!g->nbr || !g->J || !g->colour) return fail(FVAN_EINVAL, "NULL neighbour graph array");
+  if (n < 1 || n > 16384) return fail(FVAN_EINVAL, "n_spins must be in [1, 16384] for refinement");
+  if (g->degree < 1 || g->sweeps < 0 || batch < 1) return fail(FVAN_EINVAL, "degree, sweeps or batch out of range");
+  if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(FVAN_EINVAL, "beta must be finite and >= 0");
+  if (g->sweeps == 0) return FVAN_OK;
+  FVAN_HIP(launch_lmc(n, g->degree, g->nbr, g->J, g->colour, batch, beta, g->sweeps, seed, tag, spins, accepted,
+                      (hipStream_t)stream));
+  return FVAN_OK;
+}
+
+int fvan_distill_weights(int32_t batch, double beta, double w, int32_t is_int, const void* energy,
+                         const float* log_q, float* weights, void* stream) {
+  if (!energy || !log_q || !weights) return fail(FVAN_EINVAL, "NULL argument");
+  if (batch < 1 || !(beta > 0.0) || !std::isfinite(beta) || !std::isfinite(w))
+    return fail(FVAN_EINVAL, "batch, beta or w out of range");
+  FVAN_HIP(launch_reinforce(batch, beta, is_int != 0, energy, log_q, weights, nullptr, (hipStream_t)stream, w));
+  return FVAN_OK;
+}
+
 int fvan_newton_schulz(int32_t rows, int32_t cols, int32_t steps, float eps, const float* M, float* O,
                        void* stream) {
   if (!M || !O) return fail(FVAN_EINVAL, "NULL argument");

@@ -47,10 +47,12 @@ __global__ __launch_bounds__(kRThreads) void free_energy_kernel(int batch, int n
   }
 }
 
+// wlik: weight of the likelihood term of Eq. (loss2); every weight is lowered by
+// wlik / batch (0 gives the REINFORCE weights of Eq. 19).
 __global__ __launch_bounds__(kRThreads) void reinforce_kernel(int batch, double beta, int is_int,
                                                               const void* __restrict__ energy,
                                                               const float* __restrict__ logq,
-                                                              float* __restrict__ w, double* Lmean_out) {
+                                                              float* __restrict__ w, double* Lmean_out, double wlik) {
   __shared__ double red[kRThreads / 64];
   double s = 0.0;
   for (int b = threadIdx.x; b < batch; b += kRThreads) s += beta * load_energy(energy, is_int, b) + (double)logq[b];
@@ -58,7 +60,7 @@ __global__ __launch_bounds__(kRThreads) void reinforce_kernel(int batch, double 
   const double scale = 1.0 / (beta * (double)batch);
   for (int b = threadIdx.x; b < batch; b += kRThreads) {
     const double L = beta * load_energy(energy, is_int, b) + (double)logq[b];
-    w[b] = (float)((L - Lbar) * scale);
+    w[b] = (float)((L - Lbar) * scale - wlik / (double)batch);
   }
   if (threadIdx.x == 0 && Lmean_out) *Lmean_out = Lbar;
 }
@@ -87,9 +89,9 @@ hipError_t launch_free_energy(int32_t batch, int32_t n, double beta, int is_int,
 }
 
 hipError_t launch_reinforce(int32_t batch, double beta, int is_int, const void* energy, const float* logq,
-                            float* weights, double* Lmean_out, hipStream_t s) {
+                            float* weights, double* Lmean_out, hipStream_t s, double wlik) {
   hipLaunchKernelGGL(reinforce_kernel, dim3(1), dim3(kRThreads), 0, s, batch, beta, is_int, energy, logq, weights,
-                     Lmean_out);
+                     Lmean_out, wlik);
   return hipGetLastError();
 }
 

@@ -156,6 +156,35 @@ int fvan_train_step(fvan_model* m, const fvan_couplings* c, double beta, int32_t
   return fvan_adam_step(m, opt, (int64_t)step, stream);
 }
 
+int fvan_train_step_distill(fvan_model* m, const fvan_couplings* c, const fvan_lmc* g, double beta, double w,
+                            int32_t batch, uint64_t seed, uint64_t step, const fvan_muon* opt, double* stats,
+                            void* stream) {
+  if (!m || !c || !g || !opt || !stats) return fail(FVAN_EINVAL, "NULL argument");
+  if (const char* why = check_muon(*opt)) return fail(FVAN_EINVAL, why);
+  if (c->n_spins != m->cfg.n_spins) return fail(FVAN_EINVAL, "couplings and model disagree on n_spins");
+  if (!(beta > 0.0) || !std::isfinite(beta) || !std::isfinite(w)) return fail(FVAN_EINVAL, "beta or w out of range");
+  if (step < 1) return fail(FVAN_EINVAL, "step counts from 1");
+  if (!m->params || !m->grads) return fail(FVAN_EINVAL, "parameters and gradients must be bound");
+  if (!g->nbr || !g->J || !g->colour || g->degree < 1 || g->sweeps < 0 || m->cfg.n_spins > 16384)
+    return fail(FVAN_EINVAL, "refinement graph or sweeps out of range");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = fvan_sample(m, batch, seed, step, m->ts_spins, m->ts_logq, stream);
+  if (rc) return rc;
+  const int is_int = c->kind == FVAN_BONDS_PM1;
+  if ((rc = fvan_energy(c, batch, m->ts_spins, m->ts_energy, stream))) return rc;
+  if ((rc = fvan_free_energy(batch, m->cfg.n_spins, beta, is_int, m->ts_energy, m->ts_logq, stats, stream)))
+    return rc;
+  FVAN_HIP(launch_mean_energy(batch, m->cfg.n_spins, is_int, m->ts_energy, stats + 2, s));
+  const uint32_t tag = 0x80000000u | (uint32_t)(step & 0x7FFFFFFFu);
+  if ((rc = fvan_lmc_refine(m->cfg.n_spins, g, batch, beta, seed, tag, m->ts_spins, nullptr, stream))) return rc;
+  if ((rc = fvan_energy(c, batch, m->ts_spins, m->ts_energy, stream))) return rc;
+  if ((rc = fvan_log_prob(m, batch, m->ts_spins, m->ts_logq, stream))) return rc;
+  FVAN_HIP(launch_reinforce(batch, beta, is_int, m->ts_energy, m->ts_logq, m->ts_w, nullptr, s, w));
+  if ((rc = fvan_log_prob_backward(m, batch, m->ts_spins, m->ts_w, stream))) return rc;
+  FVAN_HIP(launch_grad_norm(m->grads, m->n_params, stats + 3, nullptr, s));
+  return fvan_muon_step(m, opt, (int64_t)step, stream);
+}
+
 int fvan_train_step_muon(fvan_model* m, const fvan_couplings* c, double beta, int32_t batch, uint64_t seed,
                          uint64_t step, const fvan_muon* opt, double* stats, void* stream) {
   if (!opt) return fail(FVAN_EINVAL, "NULL argument");

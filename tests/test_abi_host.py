@@ -100,3 +100,20 @@ def test_newton_schulz_and_muon_argument_checks():
     o = fv.muon_struct()
     assert lib.fvan_muon_step(None, C.byref(o), 1, None) == -1
     assert lib.fvan_train_step_muon(None, None, 1.0, 1, 0, 1, C.byref(o), None, None) == -1
+
+
+def test_refinement_argument_checks():
+    lib, p = fv.lib(), C.c_void_p(8)
+    g = fv.LmcC(degree=4, nbr=8, J=8, colour=8, sweeps=1)
+    assert lib.fvan_lmc_refine(16, C.byref(g), 4, 1.0, 0, 0, None, None, None) == -1      # NULL spins
+    assert lib.fvan_lmc_refine(0, C.byref(g), 4, 1.0, 0, 0, p, None, None) == -1
+    assert lib.fvan_lmc_refine(16385, C.byref(g), 4, 1.0, 0, 0, p, None, None) == -1
+    assert lib.fvan_lmc_refine(16, C.byref(g), 4, float("nan"), 0, 0, p, None, None) == -1
+    assert lib.fvan_lmc_refine(16, C.byref(g), 4, -1.0, 0, 0, p, None, None) == -1
+    bad = fv.LmcC(degree=0, nbr=8, J=8, colour=8, sweeps=1)
+    assert lib.fvan_lmc_refine(16, C.byref(bad), 4, 1.0, 0, 0, p, None, None) == -1
+    nul = fv.LmcC(degree=4, nbr=None, J=8, colour=8, sweeps=1)
+    assert lib.fvan_lmc_refine(16, C.byref(nul), 4, 1.0, 0, 0, p, None, None) == -1
+    assert lib.fvan_distill_weights(4, 1.0, 0.1, 0, None, p, p, None) == -1
+    assert lib.fvan_distill_weights(4, 0.0, 0.1, 0, p, p, p, None) == -1
+    assert lib.fvan_train_step_distill(None, None, None, 1.0, 0.1, 1, 0, 1, None, None, None) == -1
