@@ -66,6 +66,11 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="measure the batched workload instead: 64 2D EA instances (L in 16/24/32, +/-J) x 8 "
                          "temperatures, 1024 samples each, sampled + energies + F_q in one graph replay")
+    ap.add_argument("--distill", action="store_true",
+                    help="measure the 3D EA training step with local Monte Carlo refinement and the "
+                         "self-distillation loss instead (Eq. loss2; --lmc-sweeps sweeps, likelihood weight --w)")
+    ap.add_argument("--lmc-sweeps", type=int, default=10)
+    ap.add_argument("--w", type=float, default=0.1)
     ap.add_argument("--profile-decode", action="store_true",
                     help="no benchmark: one 1 GiB device copy (counter scale) then one decode launch at the "
                          "benchmark shape, for hardware-counter runs")
@@ -103,6 +108,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"profile_decode": "done", "copy_bytes": 1 << 30,
                           "decode_algorithmic_bytes": kv_bytes_per_sample(N, L, D, W, P, 2) * B}))
+        return
+
+    if args.distill:
+        print(json.dumps(distill(args, cfg, theta, inst, coup, B, beta, seed, N)))
         return
 
     def run(prec, steps, warmup):
@@ -251,6 +260,51 @@ def batched(args):
             "dtype": "bf16-split-mfma+fp16-kv",
             "config": {"workload": "64 2D EA instances (L=16/24/32 round-robin, +/-J) x 8 betas in [0.2, 3.0], "
                                    "d_model=64, 4 layers, 4 heads, 1024 samples per unit, one graph replay"}}
+
+
+def distill(args, cfg, theta, inst, coup, B, beta, seed, N):
+    """The 3D EA training step of the paper's low-temperature procedure: sample,
+    refine by checkerboard Metropolis, teacher-forced log q of the refined
+    samples, Eq. (loss2) weights, backward, Muon (BF16_SPLIT)."""
+    import numpy as np
+    import torch
+    import paper_2606_22984_amd as fv
+    g = fv.lmc_graph(inst, args.lmc_sweeps)
+    m = fv.Model(cfg, B, fv.FVAN_BF16_SPLIT, theta)
+    stream = torch.cuda.current_stream()
+    stats = torch.zeros(4, dtype=torch.float64, device="cuda")
+    for k in range(1, args.warmup + 1):
+        m.train_step_distill(coup, g, beta, args.w, B, seed, k, stats, lr=warmup_lr(k), adam_lr=warmup_lr(k))
+    torch.cuda.synchronize()
+    progress("distillation step: warm-up done")
+    t0 = time.perf_counter()
+    for k in range(args.warmup + 1, args.warmup + args.steps + 1):
+        m.train_step_distill(coup, g, beta, args.w, B, seed, k, stats, lr=warmup_lr(k), adam_lr=warmup_lr(k))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # the refinement kernel alone, on the step's own samples, timed on its stream
+    spins, _ = m.sample(B, seed, 1)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fv.lmc_refine(g, spins, beta, seed, 0x80000001)
+    a.record(stream)
+    fv.lmc_refine(g, spins, beta, seed, 0x80000002)
+    b.record(stream)
+    torch.cuda.synchronize()
+    lmc_ms = a.elapsed_time(b)
+    updates = B * N * args.lmc_sweeps
+    st = stats.cpu().numpy()
+    m.close()
+    return {"metric": "spin samples/sec + train-step ms, 3D EA training step with local Monte Carlo refinement "
+                      "and self-distillation (Eq. loss2)",
+            "value": round(B * args.steps / wall, 2), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 2), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16-split-mfma+fp16-kv",
+            "data": "synthetic: seeded Gaussian 3D EA instance and seeded random-init parameters",
+            "config": {"workload": "3D EA L=10 PBC (N=1000), Gaussian J, beta=1, d_model=128, 8 layers, 8 heads, "
+                                   "batch 16384, %d checkerboard Metropolis sweeps, w=%g" % (args.lmc_sweeps, args.w),
+                       "global_batch": B, "seq_len": N, "parallelism": "none (1 GPU)"},
+            "lmc_ms": round(lmc_ms, 3), "lmc_spin_updates_per_s": round(updates / (lmc_ms * 1e-3), 1),
+            "F_per_site_raw": float(st[0])}
 
 
 def _round(d):
