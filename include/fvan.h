@@ -274,6 +274,23 @@ int fvan_distill_weights(int32_t batch, double beta, double w, int32_t energy_is
 int fvan_train_step_muon(fvan_model* model, const fvan_couplings* couplings, double beta, int32_t batch,
                          uint64_t seed, uint64_t step, const fvan_muon* opt, double* stats, void* stream);
 
+/* Overlap distribution (Eq. overlap_distribution): every pair a < b of the
+ * batch is a pair of independent replicas;
+ *   counts[k] = #{a < b : sum_i s_a,i s_b,i = 2k - n_spins},  k = 0..n_spins,
+ * i.e. the pairs with overlap q = 2k / n_spins - 1.  spins: device int8 +-1
+ * [batch, n_spins]; counts: device uint64 [n_spins + 1], overwritten.  Exact
+ * (integer MFMA products).  EINVAL on NULL, batch outside [1, 2^20] or
+ * n_spins outside [1, 16000]. */
+int fvan_overlap_histogram(int32_t batch, int32_t n_spins, const int8_t* spins, uint64_t* counts, void* stream);
+
+/* Annealing schedule (Methods, variational annealing; host only):
+ *   T = T0                                                 step <= n_warmup,
+ *   T = T0 - (T0 / n_anneal) min(floor((step - n_warmup) / n_eq), n_anneal)  otherwise,
+ * reaching 0 at step = n_warmup + n_eq * n_anneal (no finite beta there).
+ * EINVAL on T0 not finite and > 0, n_warmup < 0, n_eq < 1 or n_anneal < 1. */
+int fvan_anneal_temperature(int64_t step, double T0, int64_t n_warmup, int64_t n_eq, int32_t n_anneal,
+                            double* host_T);
+
 /* One training step of the paper's 3D EA procedure (Results, 3D EA; Methods,
  * training strategy): sample (seed, stream_id = step); energies and the F_q
  * statistics of the raw samples (stats as fvan_train_step); refine the samples

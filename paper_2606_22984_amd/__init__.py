@@ -29,6 +29,7 @@ EXPORTS = (
     "fvan_free_energy", "fvan_reinforce_weights", "fvan_adam_step", "fvan_train_step",
     "fvan_newton_schulz", "fvan_muon_step", "fvan_train_step_muon",
     "fvan_lmc_refine", "fvan_distill_weights", "fvan_train_step_distill",
+    "fvan_overlap_histogram", "fvan_anneal_temperature",
     "fvan_group_create", "fvan_group_destroy", "fvan_group_run", "fvan_group_run_graph", "fvan_last_error",
 )
 
@@ -102,6 +103,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "fvan_newton_schulz": [I32, I32, I32, C.c_float, P, P, P],
         "fvan_muon_step": [P, C.POINTER(MuonC), I64, P],
         "fvan_train_step_muon": [P, C.POINTER(CouplingsC), D, I32, U64, U64, C.POINTER(MuonC), P, P],
+        "fvan_overlap_histogram": [I32, I32, P, P, P],
+        "fvan_anneal_temperature": [I64, D, I64, I64, I32, C.POINTER(C.c_double)],
         "fvan_lmc_refine": [I32, C.POINTER(LmcC), I32, D, U64, C.c_uint32, P, P, P],
         "fvan_distill_weights": [I32, D, D, I32, P, P, P, P],
         "fvan_train_step_distill": [P, C.POINTER(CouplingsC), C.POINTER(LmcC), D, D, I32, U64, U64,
@@ -239,6 +242,26 @@ def lmc_refine(graph: LmcGraph, spins: torch.Tensor, beta: float, seed: int, str
     _check(lib().fvan_lmc_refine(graph.n, C.byref(graph.c), spins.shape[0], beta, seed, stream_tag, _ptr(spins),
                                  _ptr(accepted), _stream(stream)))
     return spins
+
+
+def overlap_histogram(spins: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """counts[k] = pairs a < b of the batch with k agreeing sites (fvan_overlap_histogram)."""
+    _require_cuda(spins)
+    n = spins.shape[1]
+    if out is None:
+        out = torch.empty(n + 1, dtype=torch.int64, device=spins.device)
+    _require_cuda(out)
+    if out.numel() != n + 1 or out.dtype != torch.int64:
+        raise ValueError("out must be int64 [n_spins + 1]")
+    _check(lib().fvan_overlap_histogram(spins.shape[0], n, _ptr(spins), _ptr(out), _stream(stream)))
+    return out
+
+
+def anneal_temperature(step: int, T0: float, n_warmup: int, n_eq: int, n_anneal: int) -> float:
+    """Temperature of a training step under the annealing schedule (fvan_anneal_temperature)."""
+    T = C.c_double()
+    _check(lib().fvan_anneal_temperature(step, T0, n_warmup, n_eq, n_anneal, C.byref(T)))
+    return T.value
 
 
 def distill_weights(E: torch.Tensor, log_q: torch.Tensor, beta: float, w: float, out=None, stream=None):

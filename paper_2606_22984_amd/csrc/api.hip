@@ -264,6 +264,28 @@ int fvan_distill_weights(int32_t batch, double beta, double w, int32_t is_int, c
   return FVAN_OK;
 }
 
+int fvan_overlap_histogram(int32_t batch, int32_t n, const int8_t* spins, uint64_t* counts, void* stream) {
+  if (!spins || !counts) return fail(FVAN_EINVAL, "NULL argument");
+  if (batch < 1 || batch > (1 << 20) || n < 1 || n > 16000)
+    return fail(FVAN_EINVAL, "overlap histogram needs batch in [1, 2^20] and n_spins in [1, 16000]");
+  FVAN_HIP(launch_overlap(batch, n, spins, reinterpret_cast<unsigned long long*>(counts), (hipStream_t)stream));
+  return FVAN_OK;
+}
+
+int fvan_anneal_temperature(int64_t step, double T0, int64_t n_warmup, int64_t n_eq, int32_t n_anneal,
+                            double* host_T) {
+  if (!host_T) return fail(FVAN_EINVAL, "NULL argument");
+  if (!(T0 > 0.0) || !std::isfinite(T0) || n_warmup < 0 || n_eq < 1 || n_anneal < 1)
+    return fail(FVAN_EINVAL, "annealing schedule parameters out of range");
+  if (step <= n_warmup) {
+    *host_T = T0;
+  } else {
+    const int64_t k = std::min<int64_t>((step - n_warmup) / n_eq, n_anneal);
+    *host_T = T0 - (T0 / n_anneal) * (double)k;
+  }
+  return FVAN_OK;
+}
+
 int fvan_newton_schulz(int32_t rows, int32_t cols, int32_t steps, float eps, const float* M, float* O,
                        void* stream) {
   if (!M || !O) return fail(FVAN_EINVAL, "NULL argument");

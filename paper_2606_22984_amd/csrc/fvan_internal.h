@@ -95,6 +95,7 @@ hipError_t launch_free_energy(int32_t batch, int32_t n, double beta, int is_int,
                               const float* logq, double* stats, hipStream_t s);
 hipError_t launch_reinforce(int32_t batch, double beta, int is_int, const void* energy, const float* logq,
                             float* weights, double* Lmean_out, hipStream_t s, double wlik = 0.0);
+hipError_t launch_overlap(int32_t batch, int32_t n, const int8_t* spins, unsigned long long* counts, hipStream_t s);
 hipError_t launch_lmc(int32_t n, int32_t degree, const int32_t* nbr, const float* J, const int8_t* colour,
                       int32_t batch, double beta, int32_t sweeps, uint64_t seed, uint32_t stream_tag, int8_t* spins,
                       int32_t* accepted, hipStream_t s);

@@ -117,3 +117,25 @@ def test_refinement_argument_checks():
     assert lib.fvan_distill_weights(4, 1.0, 0.1, 0, None, p, p, None) == -1
     assert lib.fvan_distill_weights(4, 0.0, 0.1, 0, p, p, p, None) == -1
     assert lib.fvan_train_step_distill(None, None, None, 1.0, 0.1, 1, 0, 1, None, None, None) == -1
+
+
+def test_annealing_schedule_matches_oracle():
+    """Host-only entry point: the library's schedule equals the oracle's at every step."""
+    from oracle import overlap
+    for T0, nw, neq, na in [(2.0, 1200, 5, 500), (1.5, 0, 1, 7), (0.3, 10, 3, 4)]:
+        for i in list(range(0, nw + neq * na + 12)) if nw < 100 else list(range(0, 4000, 7)):
+            assert fv.anneal_temperature(i, T0, nw, neq, na) == overlap.anneal_temperature(i, T0, nw, neq, na)
+    lib = fv.lib()
+    T = C.c_double()
+    assert lib.fvan_anneal_temperature(1, 0.0, 0, 1, 1, C.byref(T)) == -1
+    assert lib.fvan_anneal_temperature(1, 1.0, 0, 0, 1, C.byref(T)) == -1
+    assert lib.fvan_anneal_temperature(1, 1.0, 0, 1, 0, C.byref(T)) == -1
+    assert lib.fvan_anneal_temperature(1, 1.0, -1, 1, 1, C.byref(T)) == -1
+
+
+def test_overlap_histogram_argument_checks():
+    lib, p = fv.lib(), C.c_void_p(8)
+    assert lib.fvan_overlap_histogram(4, 10, None, p, None) == -1
+    assert lib.fvan_overlap_histogram(0, 10, p, p, None) == -1
+    assert lib.fvan_overlap_histogram((1 << 20) + 1, 10, p, p, None) == -1
+    assert lib.fvan_overlap_histogram(4, 16001, p, p, None) == -1
