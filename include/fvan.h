@@ -60,9 +60,9 @@ typedef enum {
   FVAN_EINVAL = -1,        /* bad argument: null pointer, size out of range, mismatch */
   FVAN_ENOMEM = -2,        /* workspace allocation failed at create time */
   FVAN_EDEVICE = -3,       /* a HIP runtime call failed (message names it) */
-  FVAN_ENONFINITE = -4,    /* reserved, not returned by this build: a NaN/Inf energy or log q
+  FVAN_ENONFINITE = -4,    /* reserved, not returned by this library: a NaN/Inf energy or log q
                               propagates into NaN statistics and weights instead */
-  FVAN_EUNSUPPORTED = -5   /* valid request this build does not implement */
+  FVAN_EUNSUPPORTED = -5   /* valid request this library does not implement */
 } fvan_status;
 
 /* Arithmetic of a model's kernels.  Every mode accumulates in FP32, keeps the

@@ -6,7 +6,7 @@ ordered Markov boundary of i is the set of past sites that are adjacent to i
 or joined to i by a path whose inner nodes all lie in F_i (Eqs. 11-13).  The
 autoregressive conditional of sigma_i depends on the past only through it.
 
-Mask rule (SI Sec. I A, with the boundary-condition reading of this build):
+Mask rule (SI Sec. I A, with the boundary-condition reading used here):
 position p carries the token of site p-1 and predicts site p, so site j < i is
 available to the query that predicts i iff position j+1 is visible from
 position i.  The paper's window is A_ij = 0 for i - j > W with W >= d_max

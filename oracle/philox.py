@@ -8,7 +8,7 @@ with M0 = 0xD2511F53, M1 = 0xCD9E8D57; between rounds the key is bumped by the
 Weyl constants (0x9E3779B9, 0xBB67AE85).  Ten rounds.
 
 Draw used by ancestral sampling (the method only says "Categorical(p_t)",
-Alg. 2; this build fixes the generator):
+Alg. 2; the generator is fixed here):
   key     = (seed mod 2^32, seed >> 32)
   counter = (t >> 2, b, stream mod 2^32, stream >> 32)
   u(b, t) = (word[t & 3] >> 8) * 2^-24        (exact in float32 and float64)
