@@ -336,7 +336,7 @@ def _round(d):
     return {k: (round(v, 6) if isinstance(v, float) else v) for k, v in d.items()}
 
 
-def cpu_baseline(cfg, theta, inst, beta, optimizer, n_samples=2):
+def cpu_baseline(cfg, theta, inst, beta, optimizer, n_samples=8):
     """The FP64 oracle (as it stands) running the same training step on a bounded
     sample: KV-cached sampling of n_samples, energies, REINFORCE weights, the
     reverse-mode gradient and the parameter update.  Throughput in samples/s of
