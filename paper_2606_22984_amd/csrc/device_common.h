@@ -84,15 +84,18 @@ __device__ __forceinline__ floatx4 mfma_bf16(const uint4& a, const uint4& b, flo
 }
 
 // Split 8 floats into bf16 hi and lo parts (x = hi + lo + O(2^-16 |x|)).
+// Vector conversions round two floats per instruction (round-to-nearest-even,
+// as the scalar cast); hi is widened back by shifting, not converted.
+typedef float f32x8_t __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ void split8(const float* x, uint4& hi, uint4& lo) {
-  bf16x8 h, l;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const __bf16 b = (__bf16)x[i];
-    h[i] = b;
-    l[i] = (__bf16)(x[i] - (float)b);
-  }
+  const f32x8_t v = {x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7]};
+  const bf16x8 h = __builtin_convertvector(v, bf16x8);
   __builtin_memcpy(&hi, &h, 16);
+  const f32x8_t hf = {__uint_as_float(hi.x << 16), __uint_as_float(hi.x & 0xFFFF0000u),
+                      __uint_as_float(hi.y << 16), __uint_as_float(hi.y & 0xFFFF0000u),
+                      __uint_as_float(hi.z << 16), __uint_as_float(hi.z & 0xFFFF0000u),
+                      __uint_as_float(hi.w << 16), __uint_as_float(hi.w & 0xFFFF0000u)};
+  const bf16x8 l = __builtin_convertvector(v - hf, bf16x8);
   __builtin_memcpy(&lo, &l, 16);
 }
 
