@@ -30,9 +30,12 @@ namespace fvan {
 
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// Round-to-nearest-even to bf16, two floats per conversion instruction.
 __device__ __forceinline__ bf16x4 bf4(float a, float b, float c, float d) {
-  bf16x4 v = {(__bf16)a, (__bf16)b, (__bf16)c, (__bf16)d};
-  return v;
+  const f32x4_t v = {a, b, c, d};
+  return __builtin_convertvector(v, bf16x4);
 }
 
 // MFMA operand of one lane (four k values) per precision mode.
@@ -59,10 +62,16 @@ struct SplitBf16x4 {
 };
 template <> struct AOp<2> {
   typedef SplitBf16x4 T;
+  // hi = bf16(x), lo = bf16(x - hi); hi is widened back by shifting, not converted
   static __device__ __forceinline__ T make(float a, float b, float c, float d) {
+    const f32x4_t v = {a, b, c, d};
     T t;
-    t.h = bf4(a, b, c, d);
-    t.l = bf4(a - (float)t.h[0], b - (float)t.h[1], c - (float)t.h[2], d - (float)t.h[3]);
+    t.h = __builtin_convertvector(v, bf16x4);
+    uint2 hw;
+    __builtin_memcpy(&hw, &t.h, 8);
+    const f32x4_t hf = {__uint_as_float(hw.x << 16), __uint_as_float(hw.x & 0xFFFF0000u),
+                        __uint_as_float(hw.y << 16), __uint_as_float(hw.y & 0xFFFF0000u)};
+    t.l = __builtin_convertvector(v - hf, bf16x4);
     return t;
   }
   // The contraction index of a 16x16x32 MFMA runs over (part, dim): lane g's
