@@ -287,16 +287,10 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
         ST* hi_dst = row < M ? &As[0][row][piece * VPL] : &Bs[0][row - M][piece * VPL];
         if constexpr (SPLIT) {
           ST* lo_dst = row < M ? &As[1][row][piece * VPL] : &Bs[1][row - M][piece * VPL];
-          const float f[4] = {__uint_as_float(pre[u].x), __uint_as_float(pre[u].y), __uint_as_float(pre[u].z),
-                              __uint_as_float(pre[u].w)};
-          bf16x4 hi, lo;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            hi[e] = (__bf16)f[e];
-            lo[e] = (__bf16)(f[e] - (float)hi[e]);
-          }
-          *reinterpret_cast<bf16x4*>(hi_dst) = hi;
-          *reinterpret_cast<bf16x4*>(lo_dst) = lo;
+          const SplitBf16x4 t = AOp<2>::make(__uint_as_float(pre[u].x), __uint_as_float(pre[u].y),
+                                             __uint_as_float(pre[u].z), __uint_as_float(pre[u].w));
+          *reinterpret_cast<bf16x4*>(hi_dst) = t.h;
+          *reinterpret_cast<bf16x4*>(lo_dst) = t.l;
         } else {
           *reinterpret_cast<uint4*>(hi_dst) = pre[u];
         }
