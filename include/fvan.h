@@ -278,9 +278,10 @@ int fvan_train_step_muon(fvan_model* model, const fvan_couplings* couplings, dou
  * batch is a pair of independent replicas;
  *   counts[k] = #{a < b : sum_i s_a,i s_b,i = 2k - n_spins},  k = 0..n_spins,
  * i.e. the pairs with overlap q = 2k / n_spins - 1.  spins: device int8 +-1
- * [batch, n_spins]; counts: device uint64 [n_spins + 1], overwritten.  Exact
- * (integer MFMA products).  EINVAL on NULL, batch outside [1, 2^20] or
- * n_spins outside [1, 16000]. */
+ * [batch, n_spins] (pairs whose product falls outside [-n_spins, n_spins],
+ * possible only for entries other than +-1, are not counted); counts: device
+ * uint64 [n_spins + 1], overwritten.  Exact (integer MFMA products).  EINVAL on
+ * NULL, batch outside [1, 2^20] or n_spins outside [1, 16000]. */
 int fvan_overlap_histogram(int32_t batch, int32_t n_spins, const int8_t* spins, uint64_t* counts, void* stream);
 
 /* Annealing schedule (Methods, variational annealing; host only):

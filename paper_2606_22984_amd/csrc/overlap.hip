@@ -74,7 +74,8 @@ __global__ __launch_bounds__(kOvThreads) void overlap_kernel(const int8_t* __res
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int ra = I * kOvBlock + 16 * wave + 4 * g + i, rb = J * kOvBlock + 16 * t + r;
-        if (ra < rb && rb < B) atomicAdd(&hist[(acc[t][i] + n) >> 1], 1u);
+        const int k = (acc[t][i] + n) >> 1;   // in [0, n] for +-1 spins; other values are not counted
+        if (ra < rb && rb < B && k >= 0 && k <= n) atomicAdd(&hist[k], 1u);
       }
   }
   __syncthreads();
