@@ -61,12 +61,25 @@ __global__ __launch_bounds__(kOvThreads) void overlap_kernel(const int8_t* __res
     int4v acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = int4v{0, 0, 0, 0};
-    for (int k0 = 0; k0 < n; k0 += 64) {
-      const int k = k0 + 16 * g;
-      const int4v fa = load16(arow, k, n, vec8);
+    // the next K step's fragments are loaded before the current step's products
+    int4v fa = load16(arow, 16 * g, n, vec8), fb[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        acc[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa, load16(brow[t], k, n, vec8), acc[t], 0, 0, 0);
+    for (int t = 0; t < 4; ++t) fb[t] = load16(brow[t], 16 * g, n, vec8);
+    for (int k0 = 0; k0 < n; k0 += 64) {
+      const int kn = k0 + 64 + 16 * g;
+      int4v na = int4v{0, 0, 0, 0}, nbv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) nbv[t] = na;
+      if (k0 + 64 < n) {
+        na = load16(arow, kn, n, vec8);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) nbv[t] = load16(brow[t], kn, n, vec8);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa, fb[t], acc[t], 0, 0, 0);
+      fa = na;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) fb[t] = nbv[t];
     }
     // lane holds Q(row 16w + 4g + i of block I, row 16t + r of block J)
 #pragma unroll
