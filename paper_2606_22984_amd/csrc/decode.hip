@@ -193,6 +193,10 @@ __device__ void decode_tile(DecodeSmem<D, MODE>& sm, const DecodeUnit& U, int lo
 #pragma unroll
           for (int u = 0; u < UNR; ++u) {
             const int s = s0 + u * RPL + lrow;
+            // rows past the visible keys are zero, so their (zero) probabilities
+            // multiply zeros, not stale register contents
+            kk[u] = make_uint4(0u, 0u, 0u, 0u);
+            vv[u] = kk[u];
             if (s < nvis) {
               kk[u] = *reinterpret_cast<const uint4*>(Kb + (size_t)s * D + lcol);
               vv[u] = *reinterpret_cast<const uint4*>(Kb + plane + (size_t)s * D + lcol);
@@ -240,7 +244,7 @@ __device__ void decode_tile(DecodeSmem<D, MODE>& sm, const DecodeUnit& U, int lo
             vc.unpack(vr[u]);
             sum += p;
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) o[i] += p * (ok ? vc.v[i] : 0.f);
+            for (int i = 0; i < VEC; ++i) o[i] += p * vc.v[i];
           }
           mx = mnew;
           if (part == per - 1) {
