@@ -10,7 +10,8 @@ gradient (Eqs. 16-19), the Muon update with Newton-Schulz orthogonalisation
 (Methods, comparison of optimisers), the local Monte Carlo refinement and the
 self-distillation weights of Eq. (loss2), the overlap distribution and the
 annealing schedule (Eq. overlap_distribution; Methods, variational annealing),
-and the ordered Markov boundary that sets the sparse attention window (Methods,
+the 2^D spin patching of the lattice models (Methods, model configurations and
+training settings), and the ordered Markov boundary that sets the sparse attention window (Methods,
 ordered Markov boundary; SI Sec. I A).
 
 Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
@@ -20,4 +21,4 @@ definition), never by a common helper.
 
 Precision: float64 throughout; the sampling decision u < p uses float64 p.
 """
-from . import philox, physics, network, sampler, estimator, markov, exact, muon, refine, overlap  # noqa: F401
+from . import philox, physics, network, sampler, estimator, markov, exact, muon, refine, overlap, patch  # noqa: F401
