@@ -119,6 +119,30 @@ def test_backward_sk512_sampled_coordinates(prec):
     assert _rel(g, ref) <= GRAD_TOL[prec]
 
 
+@pytest.mark.parametrize("prec", [FP32, SPLIT])
+def test_backward_full_batch_ea3d_sampled_rows(prec):
+    """The benchmark's launch: 3D L=10 model (d=128, 8 layers, 8 heads), 16384
+    samples, so the backward runs its row chunks (2097 samples each, a ragged last
+    one).  Weights are zero except on four samples (both sides of the first chunk
+    boundary and the two batch ends); zero-weight rows add exact zeros, so the GPU
+    gradient is the oracle's gradient of those four samples."""
+    cfg = lattice_cfg(10, 3, 128, 8, 8)
+    B = 16384
+    m, theta = make_model(cfg, B, prec, seed=21, style="default")
+    spins_np = random_spins(B, cfg.n_spins, 12)
+    rows = [0, 2096, 2097, B - 1]
+    c = np.zeros(B, dtype=np.float32)
+    c[rows] = [0.7, -1.3, 0.4, 1.1]
+    say(f"ea3d full-batch backward, prec {prec}")
+    m.grads.zero_()
+    m.log_prob_backward(torch.as_tensor(spins_np, device="cuda"), torch.as_tensor(c, device="cuda"))
+    g = to_np(m.grads).astype(np.float64)
+    ref = estimator.grad_surrogate(theta, cfg, spins_np[rows], c[rows].astype(np.float64), chunk=1)
+    rel = _rel(g, ref)
+    say(f"  relative gradient error {rel:.3e}")
+    assert rel <= GRAD_TOL[prec]
+
+
 def test_autograd_function_matches_direct_backward():
     cfg = ModelConfig(30, 32, 2, 2).with_mask(4, 2)
     m, theta = make_model(cfg, 12, FP32, seed=8)
