@@ -321,8 +321,9 @@ typedef struct {
   double* stats;                    /* device [2] as fvan_free_energy */
 } fvan_group_unit;
 
-/* Build the device unit table.  tile_samples: samples per work item (0 = the
- * tuned default).  EINVAL when the models disagree in shape. */
+/* Build the device unit table.  tile_samples: samples per work item; 0 or the
+ * decode kernel's tile of 32 samples (anything else is EUNSUPPORTED).  EINVAL
+ * when the models disagree in shape. */
 int fvan_group_create(const fvan_group_unit* units, int32_t n_units, int32_t tile_samples,
                       fvan_group** out);
 int fvan_group_destroy(fvan_group* group);

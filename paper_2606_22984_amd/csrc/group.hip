@@ -228,7 +228,7 @@ int fvan_group_create(const fvan_group_unit* units, int32_t n_units, int32_t til
   if (!units || !out || n_units < 1) return fail(FVAN_EINVAL, "units and out must be non-NULL, n_units >= 1");
   *out = nullptr;
   if (tile_samples != 0 && tile_samples != decode_tile_samples())
-    return fail(FVAN_EUNSUPPORTED, "tile_samples must be 0 or 16");
+    return fail(FVAN_EUNSUPPORTED, "tile_samples must be 0 or " + std::to_string(decode_tile_samples()));
   const fvan_model* m0 = units[0].model;
   if (!m0) return fail(FVAN_EINVAL, "unit 0 has no model");
   for (int i = 0; i < n_units; ++i)

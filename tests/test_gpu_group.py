@@ -79,3 +79,12 @@ def test_group_rejects_mismatched_models():
     b.append(dict(b[0]))
     with pytest.raises(fv.FvanError):
         fv.Group(b)
+
+
+def test_group_tile_size_is_the_decode_tile():
+    """tile_samples: 0 (default) and 32 build the same group; any other size is
+    refused with a message naming the supported one."""
+    a = _units(FP32, sizes=(4,), betas=(1.0,))
+    fv.Group(a, tile_samples=32)
+    with pytest.raises(fv.FvanError, match="32"):
+        fv.Group(a, tile_samples=16)
