@@ -83,12 +83,12 @@ typedef enum {
 } fvan_bond_kind;
 
 typedef struct {
-  int32_t n_spins;     /* N: sequence length (one site per position) */
+  int32_t n_spins;     /* N: sequence length (one site, or one patch token, per position) */
   int32_t d_model;     /* d = d_token + d_pos; 32, 64 or 128 */
   int32_t d_token;     /* token-embedding width (2 for single spins) */
   int32_t n_layers;
   int32_t n_heads;     /* d_model / n_heads must be 16 */
-  int32_t vocab;       /* 2 */
+  int32_t vocab;       /* 2 (single spins); up to 256 for patch tokens, fvan_log_prob_tokens only */
   int32_t window;      /* W of the mask, 0 <= W; values >= n_spins-1 mean full causal */
   int32_t prefix;      /* P of the mask, 0 <= P <= n_spins */
   int32_t max_batch;   /* largest batch any call on this model will pass */
@@ -184,6 +184,23 @@ int fvan_sample(fvan_model* model, int32_t batch, uint64_t seed, uint64_t stream
 
 /* Teacher-forced ln q(sigma) (Alg. 1), FP32 [batch]. */
 int fvan_log_prob(fvan_model* model, int32_t batch, const int8_t* spins, float* log_q, void* stream);
+
+/* Teacher-forced ln q of token sequences for a model over 2^D-spin patches
+ * (Methods, model configurations and training settings: each 2^D block of the
+ * lattice is one token, vocabulary 2^(2^D), sequence (L/2)^D).  tokens: device
+ * uint8 [batch, n_spins] (row-major, caller-owned), values in [0, vocab); the
+ * token fed at position t is tokens[t-1] (token 0 at t = 0) and the head has
+ * vocab outputs: ln q = sum_t (z_t[tok_t] - logsumexp(z_t)), FP32 [batch].  The
+ * spin-to-token map is the caller's: patches in raster order of their
+ * coordinates, the site at offset o in {0,1}^D giving bit sum_k o_k 2^(D-1-k),
+ * bit value (sigma + 1) / 2.  Any vocab in [2, 256]; with vocab 2 and
+ * tokens (sigma + 1) / 2 it equals fvan_log_prob up to FP32 rounding.  A token
+ * >= vocab makes its sample's ln q NaN (no read leaves the parameter vector).
+ * EINVAL for NULL pointers, unsynced parameters or batch outside [1, max_batch].
+ * A model with vocab > 2 supports only this call among the model entry points
+ * (sampling, fvan_log_prob, the backward, the optimiser steps, the training
+ * steps and groups return EUNSUPPORTED). */
+int fvan_log_prob_tokens(fvan_model* model, int32_t batch, const uint8_t* tokens, float* log_q, void* stream);
 
 /* grads += sum_b grad_log_q[b] * d ln q(sigma_b) / d theta.  Recomputes the
  * forward pass (attention included) in chunks of samples; nothing from an

@@ -25,7 +25,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", 
 # Every symbol include/fvan.h declares.
 EXPORTS = (
     "fvan_num_params", "fvan_derive_mask", "fvan_create_model", "fvan_destroy_model", "fvan_bind_params",
-    "fvan_sync_params", "fvan_sample", "fvan_log_prob", "fvan_log_prob_backward", "fvan_energy",
+    "fvan_sync_params", "fvan_sample", "fvan_log_prob", "fvan_log_prob_tokens", "fvan_log_prob_backward", "fvan_energy",
     "fvan_free_energy", "fvan_reinforce_weights", "fvan_adam_step", "fvan_train_step",
     "fvan_newton_schulz", "fvan_muon_step", "fvan_train_step_muon",
     "fvan_lmc_refine", "fvan_distill_weights", "fvan_train_step_distill",
@@ -94,6 +94,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "fvan_sync_params": [P, P],
         "fvan_sample": [P, I32, U64, U64, P, P, P],
         "fvan_log_prob": [P, I32, P, P, P],
+        "fvan_log_prob_tokens": [P, I32, P, P, P],
         "fvan_log_prob_backward": [P, I32, P, P, P],
         "fvan_energy": [C.POINTER(CouplingsC), I32, P, P, P],
         "fvan_free_energy": [I32, I32, D, I32, P, P, P, P],
@@ -343,6 +344,17 @@ class Model:
         if log_q is None:
             log_q = torch.empty(spins.shape[0], dtype=torch.float32, device=spins.device)
         _check(lib().fvan_log_prob(self.handle, spins.shape[0], _ptr(spins), _ptr(log_q), _stream(stream)))
+        return log_q
+
+    def log_prob_tokens(self, tokens: torch.Tensor, log_q=None, stream=None):
+        """Teacher-forced ln q of patch-token sequences (uint8 [batch, n_spins])."""
+        _require_cuda(tokens)
+        if (tokens.dtype != torch.uint8 or tokens.dim() != 2 or not tokens.is_contiguous()
+                or tokens.shape[1] != self.cfg.n_spins):
+            raise ValueError("tokens must be a contiguous uint8 [batch, n_spins] tensor")
+        if log_q is None:
+            log_q = torch.empty(tokens.shape[0], dtype=torch.float32, device=tokens.device)
+        _check(lib().fvan_log_prob_tokens(self.handle, tokens.shape[0], _ptr(tokens), _ptr(log_q), _stream(stream)))
         return log_q
 
     def log_prob_backward(self, spins: torch.Tensor, grad_log_q: torch.Tensor, stream=None):

@@ -63,7 +63,7 @@ static int check_config(const fvan_model_config* c) {
   if (c->n_heads < 1 || c->d_model != c->n_heads * kHeadDimHost)
     return fail(FVAN_EUNSUPPORTED, "d_model / n_heads must be 16");
   if (c->d_token < 1 || c->d_token >= c->d_model) return fail(FVAN_EINVAL, "d_token out of range");
-  if (c->vocab != 2) return fail(FVAN_EUNSUPPORTED, "vocab must be 2 (single-spin tokens)");
+  if (c->vocab < 2 || c->vocab > 256) return fail(FVAN_EUNSUPPORTED, "vocab must be in [2, 256]");
   if (c->n_layers < 0 || c->n_layers > 64) return fail(FVAN_EINVAL, "n_layers out of range");
   if (c->window < 0 || c->prefix < 0 || c->prefix > c->n_spins) return fail(FVAN_EINVAL, "mask out of range");
   if (c->max_batch < 1) return fail(FVAN_EINVAL, "max_batch must be >= 1");
@@ -195,6 +195,7 @@ int fvan_sync_params(fvan_model* m, void* stream) {
 int fvan_sample(fvan_model* m, int32_t batch, uint64_t seed, uint64_t stream_id, int8_t* spins, float* log_q,
                 void* stream) {
   if (!m || !spins || !log_q) return fail(FVAN_EINVAL, "NULL argument");
+  if (m->cfg.vocab != 2) return fail(FVAN_EUNSUPPORTED, kBinaryOnly);
   if (!m->params || !m->synced) return fail(FVAN_EINVAL, "parameters not bound/synced");
   if (batch < 1 || batch > m->cfg.max_batch) return fail(FVAN_EINVAL, "batch outside [1, max_batch]");
   DecodeUnit u = make_decode_unit(m, batch, seed, stream_id, spins, log_q, m->kv, 0);
@@ -233,6 +234,7 @@ int fvan_reinforce_weights(int32_t batch, double beta, int32_t is_int, const voi
 
 int fvan_adam_step(fvan_model* m, const fvan_adam* opt, int64_t step, void* stream) {
   if (!m || !opt) return fail(FVAN_EINVAL, "NULL argument");
+  if (m->cfg.vocab != 2) return fail(FVAN_EUNSUPPORTED, kBinaryOnly);
   if (!m->params || !m->grads) return fail(FVAN_EINVAL, "parameters and gradients must be bound");
   if (step < 1) return fail(FVAN_EINVAL, "step counts from 1");
   if (const char* why = check_adam(*opt)) return fail(FVAN_EINVAL, why);
@@ -299,6 +301,7 @@ int fvan_newton_schulz(int32_t rows, int32_t cols, int32_t steps, float eps, con
 
 int fvan_muon_step(fvan_model* m, const fvan_muon* opt, int64_t step, void* stream) {
   if (!m || !opt) return fail(FVAN_EINVAL, "NULL argument");
+  if (m->cfg.vocab != 2) return fail(FVAN_EUNSUPPORTED, kBinaryOnly);
   if (!m->params || !m->grads) return fail(FVAN_EINVAL, "parameters and gradients must be bound");
   if (step < 1) return fail(FVAN_EINVAL, "step counts from 1");
   if (const char* why = check_muon(*opt)) return fail(FVAN_EINVAL, why);

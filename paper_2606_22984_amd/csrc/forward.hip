@@ -7,6 +7,8 @@
 //   attn_fwd   band+prefix masked attention, online softmax; writes o, x + o
 //              and the per-(row, head) log-sum-exp the backward pass needs
 //   head_fwd   log p_t(s_t) summed per sample in a fixed order
+// and, for models over 2^D-spin patch tokens, the token embedding and the
+// vocab-way head (embed_tokens, head_vocab).
 #include <algorithm>
 
 #include "device_common.h"
@@ -74,6 +76,83 @@ __global__ __launch_bounds__(256) void head_fwd_kernel(const float* __restrict__
   }
 }
 
+// ---------------------------------------------------------------- patch tokens
+// Embedding of a token sequence: position t is fed tok_{t-1} (start token 0 at
+// t = 0).  A token >= vocab is clamped for the table read (its sample's ln q is
+// NaN, set by the head below), so no read leaves the token table.
+__global__ void embed_tokens_kernel(const float* __restrict__ theta, int64_t pos_off, int dt, int D, int N, int V,
+                                    const uint8_t* __restrict__ tokens, int64_t rows, float* __restrict__ X) {
+  const int64_t total = rows * D;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / D;
+    const int k = (int)(i % D);
+    const int t = (int)(r % N);
+    float v;
+    if (k < dt) {
+      const int tok = t == 0 ? 0 : min((int)tokens[r - 1], V - 1);
+      v = theta[tok * dt + k];
+    } else {
+      v = theta[pos_off + (int64_t)t * (D - dt) + (k - dt)];
+    }
+    X[i] = v;
+  }
+}
+
+// Vocab-way head: one workgroup per sample, thread v computes the logit
+// z_v = W_h[v] . h_t + b_v of every position; ln p_t(tok_t) = z_tok - logsumexp(z)
+// (FP32), summed over t in order.  A token >= vocab gives NaN for its sample.
+constexpr int kHeadVocabThreads = 256;
+template <int D>
+__global__ __launch_bounds__(kHeadVocabThreads) void head_vocab_kernel(const float* __restrict__ X,
+                                                                       const float* __restrict__ theta,
+                                                                       int64_t head_w, int64_t head_b, int V,
+                                                                       const uint8_t* __restrict__ tokens, int N,
+                                                                       float* __restrict__ logq) {
+  __shared__ __align__(16) float xs[D];
+  __shared__ float wmax[kHeadVocabThreads / 64], wsum[kHeadVocabThreads / 64];
+  __shared__ float zsel;
+  const int b = blockIdx.x, v = threadIdx.x, lane = v & 63, wave = v >> 6;
+  const bool live = v < V;
+  const float* wrow = theta + head_w + (int64_t)(live ? v : 0) * D;
+  const float bias = live ? theta[head_b + v] : 0.f;
+  float acc = 0.f;                                   // used by thread 0
+  for (int t = 0; t < N; ++t) {
+    const int64_t r = (int64_t)b * N + t;
+    if (v < D) xs[v] = X[r * D + v];
+    if (v == 0) zsel = __builtin_nanf("");
+    __syncthreads();
+    float z = -INFINITY;
+    if (live) {
+      float a = 0.f;
+#pragma unroll 8
+      for (int k = 0; k < D; ++k) a += wrow[k] * xs[k];   // the head's offset need not be 16-byte aligned
+      z = a + bias;
+      if (v == (int)tokens[r]) zsel = z;
+    }
+    float m = z;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if (lane == 0) wmax[wave] = m;
+    __syncthreads();
+    float mx = wmax[0];
+#pragma unroll
+    for (int w = 1; w < kHeadVocabThreads / 64; ++w) mx = fmaxf(mx, wmax[w]);
+    float e = live ? expf(z - mx) : 0.f;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+    if (lane == 0) wsum[wave] = e;
+    __syncthreads();
+    if (v == 0) {
+      float tot = 0.f;
+#pragma unroll
+      for (int w = 0; w < kHeadVocabThreads / 64; ++w) tot += wsum[w];
+      acc += zsel - (mx + logf(tot));
+    }
+    __syncthreads();                                 // xs, zsel and the partials are rewritten next
+  }
+  if (v == 0) logq[b] = acc;
+}
+
 // ---------------------------------------------------------------- drivers
 template <int MODE, int D>
 hipError_t forward_layer(fvan_model* m, int l, int64_t rows, int nsamp, hipStream_t s) {
@@ -125,6 +204,34 @@ static hipError_t forward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp,
                        m->po.head_b, spins, c.n_spins, logq);
   }
   return hipGetLastError();
+}
+
+template <int MODE, int D>
+static hipError_t forward_chunk_tokens_t(fvan_model* m, const uint8_t* tokens, int nsamp, float* logq, hipStream_t s) {
+  const fvan_model_config& c = m->cfg;
+  const int64_t rows = (int64_t)nsamp * c.n_spins;
+  const int grid = (int)std::min<int64_t>((rows * D + 255) / 256, 65536);
+  hipLaunchKernelGGL(embed_tokens_kernel, dim3(grid), dim3(256), 0, s, m->params, m->po.pos, c.d_token, D, c.n_spins,
+                     c.vocab, tokens, rows, m->fw.X);
+  for (int l = 0; l < c.n_layers; ++l) {
+    hipError_t e = forward_layer<MODE, D>(m, l, rows, nsamp, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((head_vocab_kernel<D>), dim3(nsamp), dim3(kHeadVocabThreads), 0, s,
+                     (const float*)(m->fw.X + (size_t)c.n_layers * m->fw.rows * D), m->params, m->po.head_w,
+                     m->po.head_b, c.vocab, tokens, c.n_spins, logq);
+  return hipGetLastError();
+}
+
+hipError_t forward_chunk_tokens(fvan_model* m, const uint8_t* tokens, int nsamp, float* logq, hipStream_t s) {
+  const int D = m->cfg.d_model;
+  if (m->cfg.vocab < 2 || m->cfg.vocab > kHeadVocabThreads) return hipErrorInvalidValue;
+#define TOK_CASE(MODE, DD) if (m->cfg.precision == MODE && D == DD) return forward_chunk_tokens_t<MODE, DD>(m, tokens, nsamp, logq, s);
+  TOK_CASE(0, 32) TOK_CASE(0, 64) TOK_CASE(0, 128)
+  TOK_CASE(1, 32) TOK_CASE(1, 64) TOK_CASE(1, 128)
+  TOK_CASE(2, 32) TOK_CASE(2, 64) TOK_CASE(2, 128)
+#undef TOK_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t forward_chunk(fvan_model* m, const int8_t* spins, int nsamp, float* logq, bool for_backward,

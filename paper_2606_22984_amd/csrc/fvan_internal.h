@@ -74,6 +74,9 @@ struct DecodeUnit {
   int32_t d_token;
 };
 
+// Message of the entry points that need single-spin tokens (vocab 2).
+constexpr const char* kBinaryOnly = "a model over patch tokens (vocab > 2) supports only fvan_log_prob_tokens";
+
 // ----- error slot -----
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);

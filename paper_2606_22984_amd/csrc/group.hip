@@ -232,6 +232,8 @@ int fvan_group_create(const fvan_group_unit* units, int32_t n_units, int32_t til
   const fvan_model* m0 = units[0].model;
   if (!m0) return fail(FVAN_EINVAL, "unit 0 has no model");
   for (int i = 0; i < n_units; ++i)
+    if (units[i].model && units[i].model->cfg.vocab != 2) return fail(FVAN_EUNSUPPORTED, kBinaryOnly);
+  for (int i = 0; i < n_units; ++i)
     for (int j = 0; j < i; ++j)
       if (units[i].model == units[j].model)
         return fail(FVAN_EINVAL, "units " + std::to_string(j) + " and " + std::to_string(i) +

@@ -73,6 +73,9 @@ template <int MODE> struct Epi<MODE, EPI_F32> {
 // logq (may be NULL): per-sample ln q.
 hipError_t forward_chunk(fvan_model* m, const int8_t* spins, int nsamp, float* logq, bool for_backward,
                          hipStream_t s);
+// The same forward for a model over patch tokens (vocab >= 2): tokens [nsamp, N]
+// in [0, vocab), a vocab-way head; logq (not NULL): per-sample ln q.
+hipError_t forward_chunk_tokens(fvan_model* m, const uint8_t* tokens, int nsamp, float* logq, hipStream_t s);
 // grads += sum_b w[b] d ln q_b / d theta for one chunk (recomputes the forward).
 hipError_t backward_chunk(fvan_model* m, const int8_t* spins, int nsamp, const float* w, hipStream_t s);
 // Allocate the forward/backward workspace on first use.

@@ -94,6 +94,7 @@ extern "C" {
 
 int fvan_log_prob(fvan_model* m, int32_t batch, const int8_t* spins, float* log_q, void* stream) {
   if (!m || !spins || !log_q) return fail(FVAN_EINVAL, "NULL argument");
+  if (m->cfg.vocab != 2) return fail(FVAN_EUNSUPPORTED, kBinaryOnly);
   if (!m->params || !m->synced) return fail(FVAN_EINVAL, "parameters not bound/synced");
   if (batch < 1 || batch > m->cfg.max_batch) return fail(FVAN_EINVAL, "batch outside [1, max_batch]");
   int rc = ensure_fwd_workspace(m);
@@ -107,9 +108,25 @@ int fvan_log_prob(fvan_model* m, int32_t batch, const int8_t* spins, float* log_
   return FVAN_OK;
 }
 
+int fvan_log_prob_tokens(fvan_model* m, int32_t batch, const uint8_t* tokens, float* log_q, void* stream) {
+  if (!m || !tokens || !log_q) return fail(FVAN_EINVAL, "NULL argument");
+  if (!m->params || !m->synced) return fail(FVAN_EINVAL, "parameters not bound/synced");
+  if (batch < 1 || batch > m->cfg.max_batch) return fail(FVAN_EINVAL, "batch outside [1, max_batch]");
+  int rc = ensure_fwd_workspace(m);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t N = m->cfg.n_spins;
+  for (int64_t b0 = 0; b0 < batch; b0 += m->fw.chunk) {
+    const int nb = (int)std::min<int64_t>(m->fw.chunk, batch - b0);
+    FVAN_HIP(forward_chunk_tokens(m, tokens + b0 * N, nb, log_q + b0, s));
+  }
+  return FVAN_OK;
+}
+
 int fvan_log_prob_backward(fvan_model* m, int32_t batch, const int8_t* spins, const float* grad_log_q,
                            void* stream) {
   if (!m || !spins || !grad_log_q) return fail(FVAN_EINVAL, "NULL argument");
+  if (m->cfg.vocab != 2) return fail(FVAN_EUNSUPPORTED, kBinaryOnly);
   if (!m->params || !m->synced) return fail(FVAN_EINVAL, "parameters not bound/synced");
   if (!m->grads) return fail(FVAN_EINVAL, "no gradient buffer bound");
   if (batch < 1 || batch > m->cfg.max_batch) return fail(FVAN_EINVAL, "batch outside [1, max_batch]");

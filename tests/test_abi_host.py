@@ -60,7 +60,7 @@ def test_mask_derivation_sk_and_errors():
 def test_invalid_configs_are_rejected_on_the_host():
     base = dict(n_spins=16, d_model=32, d_token=2, n_layers=2, n_heads=2, vocab=2, window=15, prefix=0,
                 max_batch=8, precision=0)
-    bad = [dict(d_model=48), dict(n_heads=4), dict(vocab=16), dict(window=-1), dict(prefix=17),
+    bad = [dict(d_model=48), dict(n_heads=4), dict(vocab=1), dict(vocab=257), dict(window=-1), dict(prefix=17),
            dict(max_batch=0), dict(precision=7)]
     for b in bad:
         c = fv.ModelConfigC(**{**base, **b})
