@@ -53,6 +53,60 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def patched(args, wl, cfg, theta, B):
+    """Teacher-forced ln q over 2^D patch tokens (the paper's EA models) at the 3D
+    workload's model size, in split and FP32 mode, beside the single-spin pass."""
+    import numpy as np
+    import torch
+
+    import paper_2606_22984_amd as fv
+    from workloads import ModelConfig, init_params
+    from workloads.instances import patch_edges, random_spins
+
+    T, pi, pj = patch_edges(wl.size, wl.dim)
+    W, P = fv.derive_mask(T, pi, pj)
+    pcfg = ModelConfig(T, cfg.d_model, cfg.n_layers, cfg.n_heads, vocab=2 ** (2 ** wl.dim)).with_mask(W, P)
+    ptheta = init_params(pcfg, wl.param_seed, "default")
+    tok = torch.as_tensor(np.random.default_rng(7).integers(0, pcfg.vocab, size=(B, T)).astype(np.uint8),
+                          device="cuda")
+    spins = torch.as_tensor(random_spins(B, cfg.n_spins, 7), device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / args.steps
+
+    out = {}
+    for name, prec in (("bf16split", fv.FVAN_BF16_SPLIT), ("fp32", fv.FVAN_FP32)):
+        mp = fv.Model(pcfg, B, prec, ptheta)
+        lq = torch.empty(B, dtype=torch.float32, device="cuda")
+        ms_p = timed(lambda: mp.log_prob_tokens(tok, lq))
+        del mp
+        ms_s = None
+        if name == "bf16split":
+            ms_ = fv.Model(cfg, B, prec, theta)
+            ms_s = timed(lambda: ms_.log_prob(spins, lq))
+            del ms_
+        out[name] = {"patched_ms": round(ms_p, 3), "patched_sequences_per_s": round(B / (ms_p * 1e-3), 1),
+                     "single_spin_ms": None if ms_s is None else round(ms_s, 3)}
+        print(f"[bench] patched ln q, {name}: {ms_p:.2f} ms per batch", file=sys.stderr, flush=True)
+    s = out["bf16split"]
+    return {"metric": "teacher-forced ln q of one batch over patch tokens", "value": s["patched_ms"], "unit": "ms",
+            "higher_is_better": False, "n_gpus": 1, "steps": args.steps, "dtype": "bf16-split-mfma+fp16-kv",
+            "data": "synthetic: seeded random tokens and random-init parameters",
+            "config": {"workload": f"3D EA L={wl.size} in 2x2x2 patches: {T} positions, vocabulary {pcfg.vocab}, "
+                                   f"d_model={cfg.d_model}, {cfg.n_layers} layers, {cfg.n_heads} heads, batch {B}, "
+                                   f"mask W={W} P={P}"},
+            "precisions": out, "speedup_vs_single_spin_pass": round(s["single_spin_ms"] / s["patched_ms"], 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +126,9 @@ def main():
     ap.add_argument("--overlap", action="store_true",
                     help="time the overlap histogram of the 3D EA batch (16384 sampled configurations of 1000 "
                          "spins, all pairs) instead")
+    ap.add_argument("--patched", action="store_true",
+                    help="time the teacher-forced ln q of the 3D EA model over 2x2x2 patch tokens (125 positions, "
+                         "vocabulary 256, batch 16384) instead, beside the single-spin pass over 1000 positions")
     ap.add_argument("--lmc-sweeps", type=int, default=10)
     ap.add_argument("--w", type=float, default=0.1)
     ap.add_argument("--profile-decode", action="store_true",
@@ -137,6 +194,9 @@ def main():
         return
     if args.distill:
         print(json.dumps(distill(args, cfg, theta, inst, coup, B, beta, seed, N)))
+        return
+    if args.patched:
+        print(json.dumps(patched(args, wl, cfg, theta, B)))
         return
 
     def run(prec, steps, warmup):

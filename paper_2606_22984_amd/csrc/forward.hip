@@ -99,54 +99,81 @@ __global__ void embed_tokens_kernel(const float* __restrict__ theta, int64_t pos
 }
 
 // Vocab-way head: one workgroup per sample, thread v computes the logit
-// z_v = W_h[v] . h_t + b_v of every position; ln p_t(tok_t) = z_tok - logsumexp(z)
-// (FP32), summed over t in order.  A token >= vocab gives NaN for its sample.
-constexpr int kHeadVocabThreads = 256;
+// z_v = W_h[v] . h_t + b_v; ln p_t(tok_t) = z_tok - logsumexp(z) (FP32), summed
+// over t in order.  Positions go kHeadPos at a time, so every weight a thread
+// reads feeds kHeadPos products and the barriers are paid once per group.  A
+// token >= vocab gives NaN for its sample.
+constexpr int kHeadVocabThreads = 256, kHeadPos = 16;
 template <int D>
 __global__ __launch_bounds__(kHeadVocabThreads) void head_vocab_kernel(const float* __restrict__ X,
                                                                        const float* __restrict__ theta,
                                                                        int64_t head_w, int64_t head_b, int V,
                                                                        const uint8_t* __restrict__ tokens, int N,
                                                                        float* __restrict__ logq) {
-  __shared__ __align__(16) float xs[D];
-  __shared__ float wmax[kHeadVocabThreads / 64], wsum[kHeadVocabThreads / 64];
-  __shared__ float zsel;
+  constexpr int NW = kHeadVocabThreads / 64;
+  __shared__ __align__(16) float xs[kHeadPos][D];
+  __shared__ float wmax[kHeadPos][NW], wsum[kHeadPos][NW];
+  __shared__ float zsel[kHeadPos];
   const int b = blockIdx.x, v = threadIdx.x, lane = v & 63, wave = v >> 6;
   const bool live = v < V;
   const float* wrow = theta + head_w + (int64_t)(live ? v : 0) * D;
   const float bias = live ? theta[head_b + v] : 0.f;
   float acc = 0.f;                                   // used by thread 0
-  for (int t = 0; t < N; ++t) {
-    const int64_t r = (int64_t)b * N + t;
-    if (v < D) xs[v] = X[r * D + v];
-    if (v == 0) zsel = __builtin_nanf("");
-    __syncthreads();
-    float z = -INFINITY;
-    if (live) {
-      float a = 0.f;
-#pragma unroll 8
-      for (int k = 0; k < D; ++k) a += wrow[k] * xs[k];   // the head's offset need not be 16-byte aligned
-      z = a + bias;
-      if (v == (int)tokens[r]) zsel = z;
+  for (int t0 = 0; t0 < N; t0 += kHeadPos) {
+    const int np = min(kHeadPos, N - t0);
+    const int64_t r0 = (int64_t)b * N + t0;
+    for (int i = v; i < kHeadPos * D; i += kHeadVocabThreads) {
+      const int p = i / D, k = i % D;
+      xs[p][k] = p < np ? X[(r0 + p) * D + k] : 0.f;
     }
-    float m = z;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-    if (lane == 0) wmax[wave] = m;
+    if (v < kHeadPos) zsel[v] = __builtin_nanf("");
     __syncthreads();
-    float mx = wmax[0];
+    float z[kHeadPos];
 #pragma unroll
-    for (int w = 1; w < kHeadVocabThreads / 64; ++w) mx = fmaxf(mx, wmax[w]);
-    float e = live ? expf(z - mx) : 0.f;
+    for (int p = 0; p < kHeadPos; ++p) z[p] = -INFINITY;
+    if (live) {
+      float a[kHeadPos];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
-    if (lane == 0) wsum[wave] = e;
+      for (int p = 0; p < kHeadPos; ++p) a[p] = 0.f;
+#pragma unroll 4
+      for (int k = 0; k < D; ++k) {                  // the head's offset need not be 16-byte aligned
+        const float w = wrow[k];
+#pragma unroll
+        for (int p = 0; p < kHeadPos; ++p) a[p] += w * xs[p][k];
+      }
+#pragma unroll
+      for (int p = 0; p < kHeadPos; ++p) {
+        z[p] = a[p] + bias;
+        if (p < np && v == (int)tokens[r0 + p]) zsel[p] = z[p];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < kHeadPos; ++p) {
+      float m = z[p];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+      if (lane == 0) wmax[p][wave] = m;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < kHeadPos; ++p) {
+      float mx = wmax[p][0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) mx = fmaxf(mx, wmax[p][w]);
+      float e = live ? expf(z[p] - mx) : 0.f;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+      if (lane == 0) wsum[p][wave] = e;
+      z[p] = mx;                                     // keep the maximum for the log-sum-exp
+    }
     __syncthreads();
     if (v == 0) {
-      float tot = 0.f;
+      for (int p = 0; p < np; ++p) {
+        float tot = 0.f;
 #pragma unroll
-      for (int w = 0; w < kHeadVocabThreads / 64; ++w) tot += wsum[w];
-      acc += zsel - (mx + logf(tot));
+        for (int w = 0; w < NW; ++w) tot += wsum[p][w];
+        acc += zsel[p] - (z[p] + logf(tot));
+      }
     }
     __syncthreads();                                 // xs, zsel and the partials are rewritten next
   }

@@ -60,6 +60,22 @@ def lattice_edges(L: int, dim: int, pbc: bool = True):
     return np.asarray(ei, np.int32), np.asarray(ej, np.int32)
 
 
+def patch_edges(L: int, dim: int, pbc: bool = True):
+    """Interaction graph of the (L/2)^dim patches of 2^dim sites (patches in raster
+    order of their coordinates): two patches are joined if any of their sites are
+    lattice neighbours.  Returns (n_patches, pi, pj), each pair once, pi < pj."""
+    if L % 2:
+        raise ValueError("patches need an even lattice side")
+    n = L ** dim
+    coords = np.stack(np.unravel_index(np.arange(n), (L,) * dim), axis=1)
+    owner = np.ravel_multi_index(tuple((coords // 2).T), (L // 2,) * dim)
+    ei, ej = lattice_edges(L, dim, pbc)
+    a, b = owner[ei], owner[ej]
+    keep = a != b
+    pairs = np.unique(np.sort(np.stack([a[keep], b[keep]], 1), axis=1), axis=0)
+    return (L // 2) ** dim, pairs[:, 0].astype(np.int32), pairs[:, 1].astype(np.int32)
+
+
 def ea_instance(L: int, dim: int, seed: int, bonds: str = "pm1", pbc: bool = True) -> Instance:
     if pbc and L < 3:
         raise ValueError("periodic lattices need L >= 3 (L = 2 would list a pair twice)")
