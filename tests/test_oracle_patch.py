@@ -132,3 +132,20 @@ def test_random_spins_round_trip_3d():
     tok = patch.spins_to_tokens(s, 6, 3)
     assert tok.shape == (7, 27) and tok.max() < 256
     assert np.array_equal(patch.tokens_to_spins(tok, 6, 3), s)
+
+
+@pytest.mark.parametrize("L,D", [(4, 2), (8, 2), (6, 3), (10, 3)])
+def test_patch_graph_of_the_inputs_by_brute_force(L, D):
+    """The patch graph the benchmark derives its mask from (workloads.patch_edges)
+    joins exactly the patches whose sites are lattice neighbours, found here by a
+    brute-force pass over the oracle's patch geometry."""
+    from workloads.instances import lattice_edges, patch_edges
+    T, pi, pj = patch_edges(L, D)
+    sites = patch.patch_sites(L, D)
+    assert T == sites.shape[0]
+    owner = {int(s): t for t in range(T) for s in sites[t]}
+    ei, ej = lattice_edges(L, D, True)
+    want = {tuple(sorted((owner[int(a)], owner[int(b)]))) for a, b in zip(ei, ej) if owner[int(a)] != owner[int(b)]}
+    got = list(zip(pi.tolist(), pj.tolist()))
+    assert len(got) == len(set(got)) and set(got) == want
+    assert all(a < b for a, b in got)
