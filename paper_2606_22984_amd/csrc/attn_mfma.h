@@ -108,6 +108,10 @@ __device__ __forceinline__ bool visible(int t, int j, int W, int P) {
 }
 
 constexpr float kScaleLog2 = 0.25f * 1.4426950408889634f;   // 1/sqrt(16) * log2(e)
+// A-layout operand tiles hold 4 operands per row padded to 5: an MFMA read of
+// rows r..r+15 at one g then starts every lane's 8- or 16-byte access at a
+// different bank offset (row strides of 4 operands put 16 lanes on 4 offsets).
+constexpr int kAStride = 5;
 constexpr int kKeyChunk = 128;                               // keys staged in LDS at a time
 // Workgroup shapes, measured per kernel at the 3D workload: the forward and the
 // dK/dV kernels run 4 waves x 16 rows, the dQ kernel 8 waves x 16 rows (its key
@@ -209,10 +213,12 @@ struct KeyStager {
 // the dim; one padding column against bank conflicts).  Built by all the
 // workgroup's threads from a float tile [row][dim].
 template <int MODE, int R, int NTHREADS>
-__device__ __forceinline__ void build_a(const float (*F)[20], typename AOp<MODE>::T (*A)[4]) {
+__device__ __forceinline__ void build_a(const float (*F)[20], typename AOp<MODE>::T (*A)[kAStride]) {
 #pragma unroll
   for (int idx = threadIdx.x; idx < R * 4; idx += NTHREADS) {
-    const int row = idx >> 2, g = idx & 3;
+    // consecutive lanes take consecutive rows at one g: the padded stride of 5
+    // operands and the 80-byte float rows put them on distinct banks
+    const int row = idx % R, g = idx / R;
     A[row][g] = aop<MODE>(*reinterpret_cast<const float4*>(&F[row][4 * g]));
   }
 }
@@ -238,7 +244,7 @@ __global__ __launch_bounds__(kFwdThreads) void attn_fwd_mfma(const KT* __restric
   typedef typename Op::T OT;
   __shared__ __align__(16) float Kf[kKeyChunk][20];
   __shared__ __align__(16) float Vf[kKeyChunk][20];
-  __shared__ __align__(16) OT Ka[kKeyChunk][4];               // K, A layout
+  __shared__ __align__(16) OT Ka[kKeyChunk][kAStride];        // K, A layout
   __shared__ __align__(16) OT Vb[16][kKeyChunk / 4 + 1];      // V^T as the A operand: [dim][key group]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
   constexpr int R = attn_rows(kFwdThreads);
@@ -341,8 +347,8 @@ __global__ __launch_bounds__(kDqThreads) void attn_bwd_dq_mfma(const KT* __restr
   typedef typename Op::T OT;
   __shared__ __align__(16) float Kf[kKeyChunk][20];
   __shared__ __align__(16) float Vf[kKeyChunk][20];
-  __shared__ __align__(16) OT Ka[kKeyChunk][4];
-  __shared__ __align__(16) OT Va[kKeyChunk][4];
+  __shared__ __align__(16) OT Ka[kKeyChunk][kAStride];
+  __shared__ __align__(16) OT Va[kKeyChunk][kAStride];
   __shared__ __align__(16) OT Kb[16][kKeyChunk / 4 + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
   constexpr int R = attn_rows(kDqThreads);
@@ -439,8 +445,8 @@ __global__ __launch_bounds__(kDkvThreads) void attn_bwd_dkv_mfma(const KT* __res
   constexpr int QC = 16 / QE;                       // 16-byte chunks per query row slice
   __shared__ __align__(16) float Qf[QB][20];
   __shared__ __align__(16) float Gf[QB][20];
-  __shared__ __align__(16) OT Qa[QB][4];            // Q, A layout (S = Q K^T)
-  __shared__ __align__(16) OT Ga[QB][4];            // dO, A layout (dP = dO V^T)
+  __shared__ __align__(16) OT Qa[QB][kAStride];     // Q, A layout (S = Q K^T)
+  __shared__ __align__(16) OT Ga[QB][kAStride];     // dO, A layout (dP = dO V^T)
   __shared__ __align__(16) OT Qb[16][QB / 4 + 1];   // Q, B layout (dK += dS^T Q)
   __shared__ __align__(16) OT Gb[16][QB / 4 + 1];   // dO, B layout (dV += P^T dO)
   __shared__ __align__(16) float Ls[QB];
