@@ -155,6 +155,17 @@ def _require_cuda(*ts):
             raise ValueError("tensors passed to libfvan must be contiguous device tensors")
 
 
+def _spins_arg(spins, n: int):
+    """The C side reads batch x n int8 spins from the pointer: check that much is there."""
+    if spins.dtype != torch.int8 or spins.dim() != 2 or spins.shape[1] != n or spins.shape[0] < 1:
+        raise ValueError(f"spins must be an int8 [batch, {n}] tensor (got {tuple(spins.shape)}, {spins.dtype})")
+
+
+def _vec_arg(t, batch: int, name: str, dtypes=(torch.float32,)):
+    if t is not None and (t.dtype not in dtypes or t.numel() < batch):
+        raise ValueError(f"{name} must hold at least {batch} values of type {dtypes[0]}")
+
+
 def num_params(cfg) -> int:
     c = config_struct(cfg, max_batch=1)
     out = C.c_int64()
@@ -240,6 +251,8 @@ def lmc_refine(graph: LmcGraph, spins: torch.Tensor, beta: float, seed: int, str
                stream=None):
     """Checkerboard Metropolis sweeps on spins [batch, n] in place (fvan_lmc_refine)."""
     _require_cuda(spins, accepted)
+    _spins_arg(spins, graph.n)
+    _vec_arg(accepted, spins.shape[0], "accepted", (torch.int32,))
     _check(lib().fvan_lmc_refine(graph.n, C.byref(graph.c), spins.shape[0], beta, seed, stream_tag, _ptr(spins),
                                  _ptr(accepted), _stream(stream)))
     return spins
@@ -248,7 +261,10 @@ def lmc_refine(graph: LmcGraph, spins: torch.Tensor, beta: float, seed: int, str
 def overlap_histogram(spins: torch.Tensor, out=None, stream=None) -> torch.Tensor:
     """counts[k] = pairs a < b of the batch with k agreeing sites (fvan_overlap_histogram)."""
     _require_cuda(spins)
+    if spins.dim() != 2:
+        raise ValueError("spins must be an int8 [batch, n] tensor")
     n = spins.shape[1]
+    _spins_arg(spins, n)
     if out is None:
         out = torch.empty(n + 1, dtype=torch.int64, device=spins.device)
     _require_cuda(out)
@@ -336,6 +352,10 @@ class Model:
         if log_q is None:
             log_q = torch.empty(batch, dtype=torch.float32, device=self.params.device)
         _require_cuda(spins, log_q)
+        _spins_arg(spins, self.cfg.n_spins)
+        if spins.shape[0] < batch:
+            raise ValueError(f"spins holds {spins.shape[0]} rows, batch is {batch}")
+        _vec_arg(log_q, batch, "log_q")
         _check(lib().fvan_sample(self.handle, batch, seed, stream_id, _ptr(spins), _ptr(log_q), _stream(stream)))
         return spins, log_q
 
@@ -343,6 +363,8 @@ class Model:
         _require_cuda(spins)
         if log_q is None:
             log_q = torch.empty(spins.shape[0], dtype=torch.float32, device=spins.device)
+        _spins_arg(spins, self.cfg.n_spins)
+        _vec_arg(log_q, spins.shape[0], "log_q")
         _check(lib().fvan_log_prob(self.handle, spins.shape[0], _ptr(spins), _ptr(log_q), _stream(stream)))
         return log_q
 
@@ -359,6 +381,8 @@ class Model:
 
     def log_prob_backward(self, spins: torch.Tensor, grad_log_q: torch.Tensor, stream=None):
         _require_cuda(spins, grad_log_q)
+        _spins_arg(spins, self.cfg.n_spins)
+        _vec_arg(grad_log_q, spins.shape[0], "grad_log_q")
         _check(lib().fvan_log_prob_backward(self.handle, spins.shape[0], _ptr(spins), _ptr(grad_log_q),
                                             _stream(stream)))
 
@@ -428,6 +452,8 @@ def energy(coup: Couplings, spins: torch.Tensor, out=None, stream=None):
     _require_cuda(spins)
     if out is None:
         out = coup.empty_energy(spins.shape[0], spins.device)
+    _spins_arg(spins, coup.n)
+    _vec_arg(out, spins.shape[0], "out", (torch.int32,) if coup.energy_is_int else (torch.float32,))
     _check(lib().fvan_energy(C.byref(coup.c), spins.shape[0], _ptr(spins), _ptr(out), _stream(stream)))
     return out
 

@@ -45,3 +45,25 @@ def test_zero_layer_model(prec):
         m.muon_step(1, lr=1e-2, adam_lr=1e-3)
         torch.cuda.synchronize()
         assert np.max(np.abs(to_np(m.params) - new)) <= 1e-6
+
+
+def test_binding_refuses_malformed_spin_tensors():
+    """The C entry points read batch x n int8 spins from a pointer; the binding
+    refuses tensors of another width or dtype, or too few rows, before any launch."""
+    from workloads import ModelConfig, init_params
+    cfg = ModelConfig(16, 32, 2, 2).with_mask(4, 4)
+    m = fv.Model(cfg, 8, fv.FVAN_FP32, init_params(cfg, 1, "random"))
+    good = torch.ones(8, 16, dtype=torch.int8, device="cuda")
+    for bad in (torch.ones(8, 15, dtype=torch.int8, device="cuda"), torch.ones(8, 16, dtype=torch.int32, device="cuda"),
+                torch.ones(16, dtype=torch.int8, device="cuda")):
+        with pytest.raises(ValueError):
+            m.log_prob(bad)
+        with pytest.raises(ValueError):
+            m.log_prob_backward(bad, torch.zeros(8, device="cuda"))
+    with pytest.raises(ValueError):
+        m.log_prob_backward(good, torch.zeros(7, device="cuda"))
+    with pytest.raises(ValueError):
+        m.sample(8, 1, 1, spins=torch.empty(4, 16, dtype=torch.int8, device="cuda"))
+    with pytest.raises(ValueError):
+        m.log_prob(good, log_q=torch.empty(8, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
