@@ -166,6 +166,14 @@ def _vec_arg(t, batch: int, name: str, dtypes=(torch.float32,)):
         raise ValueError(f"{name} must hold at least {batch} values of type {dtypes[0]}")
 
 
+def _energy_logq_args(energy_t, log_q, out, out_len: int, out_dtype=torch.float32):
+    """E [batch] (int32 or float32) and ln q [batch] float32 of one length; out holds out_len values."""
+    if log_q.dim() != 1 or log_q.dtype != torch.float32 or log_q.shape[0] < 1:
+        raise ValueError("log_q must be a float32 [batch] tensor")
+    _vec_arg(energy_t, log_q.shape[0], "energy", (torch.int32, torch.float32))
+    _vec_arg(out, out_len, "out", (out_dtype,))
+
+
 def num_params(cfg) -> int:
     c = config_struct(cfg, max_batch=1)
     out = C.c_int64()
@@ -286,6 +294,7 @@ def distill_weights(E: torch.Tensor, log_q: torch.Tensor, beta: float, w: float,
     _require_cuda(E, log_q)
     if out is None:
         out = torch.empty(log_q.shape[0], dtype=torch.float32, device=log_q.device)
+    _energy_logq_args(E, log_q, out, log_q.shape[0])
     is_int = 1 if E.dtype == torch.int32 else 0
     _check(lib().fvan_distill_weights(log_q.shape[0], beta, w, is_int, _ptr(E), _ptr(log_q), _ptr(out),
                                       _stream(stream)))
@@ -462,6 +471,7 @@ def free_energy(energy_t: torch.Tensor, log_q: torch.Tensor, beta: float, n_spin
     _require_cuda(energy_t, log_q)
     if out is None:
         out = torch.zeros(2, dtype=torch.float64, device=log_q.device)
+    _energy_logq_args(energy_t, log_q, out, 2, torch.float64)
     is_int = 1 if energy_t.dtype == torch.int32 else 0
     _check(lib().fvan_free_energy(log_q.shape[0], n_spins, beta, is_int, _ptr(energy_t), _ptr(log_q), _ptr(out),
                                   _stream(stream)))
@@ -472,6 +482,7 @@ def reinforce_weights(energy_t: torch.Tensor, log_q: torch.Tensor, beta: float, 
     _require_cuda(energy_t, log_q)
     if out is None:
         out = torch.empty_like(log_q)
+    _energy_logq_args(energy_t, log_q, out, log_q.shape[0])
     is_int = 1 if energy_t.dtype == torch.int32 else 0
     _check(lib().fvan_reinforce_weights(log_q.shape[0], beta, is_int, _ptr(energy_t), _ptr(log_q), _ptr(out),
                                         _stream(stream)))
