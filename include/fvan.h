@@ -13,15 +13,22 @@
  * Conventions shared by every call:
  *  - Pointers are DEVICE memory unless the argument name starts with host_.
  *    The caller owns every input/output buffer and the FP32 parameter and
- *    gradient vectors; the library owns its workspaces (KV cache, activations,
- *    packed weight copies, optimiser state), allocated at create time from
- *    max_batch and freed at destroy.  No hot call allocates device memory.
+ *    gradient vectors; the library owns its workspaces (KV cache, activations
+ *    of the teacher-forced passes, packed weight copies, optimiser state),
+ *    allocated and initialised by fvan_create_model from max_batch and freed
+ *    by fvan_destroy_model.  No other call allocates device memory.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
- *    asynchronously on it; argument checks happen on the host, synchronously,
- *    before anything is enqueued.  A call that fails its checks enqueues
- *    nothing.
+ *    asynchronously on it and on no other stream; argument checks happen on
+ *    the host, synchronously, before anything is enqueued.  A call that fails
+ *    its checks enqueues nothing.  Only fvan_model_status and the training
+ *    steps (which wait for the previous training step of their model, see
+ *    fvan_train_step) synchronise with the device.
  *  - Every call returns an fvan_status.  On failure fvan_last_error() returns
  *    a thread-local message.  No C++ exception crosses the ABI.
+ *  - Non-finite values: the model calls (sampling, log q, backward, training
+ *    steps) check their results on the device (ln q, the gradient vector, the
+ *    step statistics) and set a per-model flag on a NaN or Inf; the flag is
+ *    reported as FVAN_ENONFINITE by the next synchronising call on that model.
  *  - One model is used by one stream at a time; calls on one model must not
  *    overlap (they share its workspaces).
  *  - Spins are int8 +1/-1, row-major [batch, n_spins] (sample-major).  Token
@@ -60,8 +67,8 @@ typedef enum {
   FVAN_EINVAL = -1,        /* bad argument: null pointer, size out of range, mismatch */
   FVAN_ENOMEM = -2,        /* workspace allocation failed at create time */
   FVAN_EDEVICE = -3,       /* a HIP runtime call failed (message names it) */
-  FVAN_ENONFINITE = -4,    /* reserved, not returned by this library: a NaN/Inf energy or log q
-                              propagates into NaN statistics and weights instead */
+  FVAN_ENONFINITE = -4,    /* a kernel of this model produced a NaN or Inf (ln q, energy, gradient
+                              or step statistics) since the last synchronising call */
   FVAN_EUNSUPPORTED = -5   /* valid request this library does not implement */
 } fvan_status;
 
@@ -69,12 +76,21 @@ typedef enum {
  * residual stream, LayerNorm statistics, logits, log-softmax and log q in FP32,
  * and leaves the batch reductions (F_q, variance, baseline) to FP64.
  *   FVAN_FP32        FP32 MFMA GEMMs, FP32 K/V cache: the plain path.
- *   FVAN_BF16        BF16 MFMA GEMMs (operands rounded to BF16), BF16 K/V cache.
  *   FVAN_BF16_SPLIT  BF16 MFMA GEMMs on split operands (x = hi + lo, both BF16;
  *                    three MFMAs per step: FP32-level GEMM accuracy), FP16 K/V
  *                    cache and attention operands (the paper runs attention in
- *                    FP16, SI Sec. II A).  Same K/V bytes as FVAN_BF16. */
-typedef enum { FVAN_FP32 = 0, FVAN_BF16 = 1, FVAN_BF16_SPLIT = 2 } fvan_precision;
+ *                    FP16, SI Sec. II A): half the K/V bytes of FVAN_FP32.
+ * Value 1 is not a mode: GEMM operands rounded to plain BF16 bias ln q by about
+ * 1e-3 per site at the 3D EA L=10 workload, ten times the free-energy
+ * tolerance (|dF_q / N| <= 1e-4) this library is held to. */
+typedef enum { FVAN_FP32 = 0, FVAN_BF16_SPLIT = 2 } fvan_precision;
+
+/* Workspaces fvan_create_model allocates (bit set). */
+enum {
+  FVAN_WS_SAMPLER = 1,     /* KV cache of fvan_sample (and of group launches) */
+  FVAN_WS_TEACHER = 2      /* activations of the teacher-forced passes: fvan_log_prob, fvan_log_prob_tokens,
+                              fvan_log_prob_backward and the training steps */
+};
 
 typedef enum {
   FVAN_BONDS_PM1 = 0,      /* ELL, int8 J in {-1, 0, +1}; energy int32, exact */
@@ -93,6 +109,8 @@ typedef struct {
   int32_t prefix;      /* P of the mask, 0 <= P <= n_spins */
   int32_t max_batch;   /* largest batch any call on this model will pass */
   int32_t precision;   /* fvan_precision */
+  int32_t workspaces;  /* FVAN_WS_* bits; a call whose workspace was not requested returns EUNSUPPORTED.
+                          The training steps need both. */
 } fvan_model_config;
 
 typedef struct {
@@ -154,9 +172,13 @@ int fvan_num_params(const fvan_model_config* cfg, int64_t* n_params);
 int fvan_derive_mask(int32_t n_spins, int64_t n_edges, const int32_t* host_i, const int32_t* host_j,
                      int32_t* window, int32_t* prefix);
 
-/* Create a model on the current HIP device and allocate its workspaces for
- * cfg->max_batch samples.  EINVAL on an unsupported shape, ENOMEM when the
- * workspaces do not fit. */
+/* Create a model on the current HIP device, allocate the workspaces
+ * cfg->workspaces asks for, sized for cfg->max_batch samples, and initialise
+ * them (synchronously: this call waits for its own device work).  The
+ * teacher-forced workspace holds one chunk of about 2^21 positions
+ * (min(max_batch, 2^21 / n_spins) samples); longer batches run chunk by chunk.
+ * EINVAL on a bad shape, EUNSUPPORTED on a shape the kernels do not cover,
+ * ENOMEM when the workspaces do not fit. */
 int fvan_create_model(const fvan_model_config* cfg, fvan_model** out);
 int fvan_destroy_model(fvan_model* model);
 
@@ -238,7 +260,13 @@ int fvan_adam_step(fvan_model* model, const fvan_adam* opt, int64_t step, void* 
  *   sample batch (seed, stream_id = step) -> energies -> F_q stats ->
  *   REINFORCE weights from the sampled log q -> backward -> Adam.
  * stats: device double [4] = { F_q/N, Var[f], <E>/N, ||grad||_2 }.
- * The model's grads must be bound; they are zeroed by the update. */
+ * The model's grads must be bound; they are zeroed by the update.  The model
+ * needs both workspaces (FVAN_WS_SAMPLER | FVAN_WS_TEACHER).
+ * A training step first waits for the previous training step of the same
+ * model to finish and returns FVAN_ENONFINITE, enqueuing nothing, if that
+ * step's statistics were not finite (the flag is then cleared); otherwise it
+ * enqueues its own work asynchronously, ending with a device copy of its
+ * finiteness check for the next call to read. */
 int fvan_train_step(fvan_model* model, const fvan_couplings* couplings, double beta, int32_t batch,
                     uint64_t seed, uint64_t step, const fvan_adam* opt, double* stats, void* stream);
 
@@ -280,9 +308,10 @@ int fvan_lmc_refine(int32_t n_spins, const fvan_lmc* lmc, int32_t batch, double 
 /* Weights of the self-distillation gradient, Eq. (loss2), on M = batch
  * (refined) configurations with their energies and teacher-forced log q:
  *   L_m = beta E_m + log_q_m,  Lbar = mean_m L_m (FP64),
- *   weights[m] = (L_m - Lbar) / (beta M) - w / M,
- * so that sum_m weights[m] grad ln q_m is the REINFORCE gradient of F_q plus
- * w times the likelihood term (w = 0: fvan_reinforce_weights). */
+ *   weights[m] = ((L_m - Lbar) - w) / (beta M),
+ * i.e. Eq. (loss2)'s (1/M) sum_m ((L - Lbar) - w) grad ln q_m with the 1/beta
+ * of the exact F_q gradient (Eq. 18) as its proportionality constant, applied
+ * to both terms; w = 0 gives fvan_reinforce_weights. */
 int fvan_distill_weights(int32_t batch, double beta, double w, int32_t energy_is_int, const void* energy,
                          const float* log_q, float* weights, void* stream);
 
@@ -349,6 +378,11 @@ int fvan_group_destroy(fvan_group* group);
 int fvan_group_run(fvan_group* group, void* stream);
 /* Capture fvan_group_run into a HIP graph on `stream` (once) and replay it. */
 int fvan_group_run_graph(fvan_group* group, void* stream);
+
+/* Synchronise `stream`, then report and clear the model's non-finite flag:
+ * FVAN_ENONFINITE if any kernel of this model found a NaN or Inf in its
+ * results since the flag was last reported, else FVAN_OK. */
+int fvan_model_status(fvan_model* model, void* stream);
 
 /* Thread-local message describing the last failure on this thread. */
 const char* fvan_last_error(void);

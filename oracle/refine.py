@@ -21,10 +21,11 @@ neither the Monte Carlo move, the number of sweeps nor w; the readings here:
     (seed mod 2^32, seed >> 32), counter (i >> 2, b, k, stream), word i & 3,
     u = (word >> 8) 2^-24 -- the sampler's generator with the sweep index and a
     32-bit stream tag in the last two counter words.
-  * Weights: c_m = (L_m - Lbar) / (beta M) - w / M, so that with w = 0 they are
-    the REINFORCE weights of the exact grad F_q estimator (estimator.py) and
-    sum_m c_m grad ln q_m is the loss2 gradient with the likelihood term scaled
-    by w.  Lbar is the batch mean of L over the refined samples; ln q of a
+  * Weights: c_m = ((L_m - Lbar) - w) / (beta M): Eq. (loss2) is
+    (1/M) sum_m ((L - Lbar) - w) grad ln q_m up to a constant factor, and the
+    factor is taken to be the 1/beta of the exact grad F_q estimator
+    (estimator.py, Eq. 18), applied to both terms, so that with w = 0 these are
+    its REINFORCE weights.  Lbar is the batch mean of L over the refined samples; ln q of a
     refined sample is its teacher-forced log-likelihood.
 """
 from __future__ import annotations
@@ -111,7 +112,7 @@ def metropolis_checkerboard(spins, adj, colour, beta: float, sweeps: int, seed: 
 
 
 def distill_weights(E, logq, beta: float, w: float) -> np.ndarray:
-    """c_m = (L_m - Lbar) / (beta M) - w / M, L = beta E + ln q (float64)."""
+    """c_m = ((L_m - Lbar) - w) / (beta M), L = beta E + ln q (float64)."""
     L = beta * np.asarray(E, dtype=np.float64) + np.asarray(logq, dtype=np.float64)
     M = L.shape[0]
-    return (L - L.mean()) / (beta * M) - w / M
+    return ((L - L.mean()) - w) / (beta * M)

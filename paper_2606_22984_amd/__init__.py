@@ -17,8 +17,9 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfvan.so")
 
-FVAN_FP32, FVAN_BF16, FVAN_BF16_SPLIT = 0, 1, 2
-PRECISION_NAMES = {0: "fp32", 1: "bf16", 2: "bf16split"}
+FVAN_FP32, FVAN_BF16_SPLIT = 0, 2
+PRECISION_NAMES = {0: "fp32", 2: "bf16split"}
+WS_SAMPLER, WS_TEACHER = 1, 2
 BONDS_PM1, BONDS_F32, BONDS_DENSE = 0, 1, 2
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "EUNSUPPORTED"}
 
@@ -30,7 +31,8 @@ EXPORTS = (
     "fvan_newton_schulz", "fvan_muon_step", "fvan_train_step_muon",
     "fvan_lmc_refine", "fvan_distill_weights", "fvan_train_step_distill",
     "fvan_overlap_histogram", "fvan_anneal_temperature",
-    "fvan_group_create", "fvan_group_destroy", "fvan_group_run", "fvan_group_run_graph", "fvan_last_error",
+    "fvan_group_create", "fvan_group_destroy", "fvan_group_run", "fvan_group_run_graph", "fvan_model_status",
+    "fvan_last_error",
 )
 
 
@@ -42,7 +44,7 @@ class FvanError(RuntimeError):
 
 class ModelConfigC(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("n_spins", "d_model", "d_token", "n_layers", "n_heads", "vocab",
-                                         "window", "prefix", "max_batch", "precision")]
+                                         "window", "prefix", "max_batch", "precision", "workspaces")]
 
 
 class CouplingsC(C.Structure):
@@ -114,6 +116,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "fvan_group_destroy": [P],
         "fvan_group_run": [P, P],
         "fvan_group_run_graph": [P, P],
+        "fvan_model_status": [P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -190,10 +193,11 @@ def derive_mask(n: int, edges_i, edges_j) -> Tuple[int, int]:
     return w.value, p.value
 
 
-def config_struct(cfg, max_batch: int, precision: int = FVAN_FP32) -> ModelConfigC:
+def config_struct(cfg, max_batch: int, precision: int = FVAN_FP32,
+                  workspaces: int = WS_SAMPLER | WS_TEACHER) -> ModelConfigC:
     return ModelConfigC(n_spins=cfg.n_spins, d_model=cfg.d_model, d_token=cfg.d_token, n_layers=cfg.n_layers,
                         n_heads=cfg.n_heads, vocab=cfg.vocab, window=cfg.window, prefix=cfg.prefix,
-                        max_batch=max_batch, precision=precision)
+                        max_batch=max_batch, precision=precision, workspaces=workspaces)
 
 
 @dataclass
@@ -248,9 +252,17 @@ def lmc_graph(instance, sweeps: int, device="cuda") -> LmcGraph:
     for _ in range(instance.dim):
         col += idx % instance.L
         idx //= instance.L
+    col %= 2
+    ei, ej = np.asarray(instance.edges_i), np.asarray(instance.edges_j)
+    if ei.size and np.any(col[ei] == col[ej]):
+        # e.g. periodic boundaries with odd L: the sites x = L-1 and x = 0 share a colour, so a
+        # half-sweep would update two neighbours from stale fields (not sequential Metropolis)
+        raise ValueError("the checkerboard colouring is not proper on this lattice (a bond joins two sites "
+                         "of one colour); refinement needs a bipartite lattice, e.g. even L under periodic "
+                         "boundaries")
     t_nbr = torch.as_tensor(nbr, device=device)
     t_J = torch.as_tensor(Jl, device=device)
-    t_col = torch.as_tensor((col % 2).astype(np.int8), device=device)
+    t_col = torch.as_tensor(col.astype(np.int8), device=device)
     c = LmcC(degree=deg, nbr=t_nbr.data_ptr(), J=t_J.data_ptr(), colour=t_col.data_ptr(), sweeps=sweeps)
     return LmcGraph(n, t_nbr, t_J, t_col, c)
 
@@ -331,13 +343,15 @@ def couplings(instance, device="cuda", dense: Optional[bool] = None) -> Coupling
 
 
 class Model:
-    """Owns one fvan_model handle plus the caller-side FP32 parameter and gradient tensors."""
+    """Owns one fvan_model handle plus the caller-side FP32 parameter and gradient tensors.
+    workspaces: WS_SAMPLER (KV cache) and/or WS_TEACHER (teacher-forced passes), allocated at creation."""
 
-    def __init__(self, cfg, max_batch: int, precision: int = FVAN_FP32, params=None, device="cuda"):
+    def __init__(self, cfg, max_batch: int, precision: int = FVAN_FP32, params=None, device="cuda",
+                 workspaces: int = WS_SAMPLER | WS_TEACHER):
         self.cfg = cfg
         self.precision = precision
         self.max_batch = max_batch
-        self._c = config_struct(cfg, max_batch, precision)
+        self._c = config_struct(cfg, max_batch, precision, workspaces)
         h = C.c_void_p()
         _check(lib().fvan_create_model(C.byref(self._c), C.byref(h)))
         self.handle = h
@@ -430,6 +444,11 @@ class Model:
         _check(lib().fvan_train_step_distill(self.handle, C.byref(coup.c), C.byref(graph.c), beta, w, batch, seed,
                                              step, C.byref(o), _ptr(stats), _stream(stream)))
         return stats
+
+    def status(self, stream=None):
+        """Synchronise and raise FvanError(ENONFINITE) if a kernel of this model produced a NaN or Inf
+        since the last report (fvan_model_status)."""
+        _check(lib().fvan_model_status(self.handle, _stream(stream)))
 
     def close(self):
         if getattr(self, "handle", None):
@@ -549,29 +568,6 @@ class Group:
 
     def run_graph(self, stream=None):
         _check(lib().fvan_group_run_graph(self.handle, _stream(stream)))
-
-    def muon_step(self, step: int, stream=None, **hyper):
-        """One Muon step (fvan_muon_step); hyper: the keyword arguments of muon_struct."""
-        o = muon_struct(**hyper)
-        _check(lib().fvan_muon_step(self.handle, C.byref(o), step, _stream(stream)))
-
-    def train_step_muon(self, coup: Couplings, beta: float, batch: int, seed: int, step: int, stats=None,
-                        stream=None, **hyper):
-        if stats is None:
-            stats = torch.zeros(4, dtype=torch.float64, device=self.params.device)
-        o = muon_struct(**hyper)
-        _check(lib().fvan_train_step_muon(self.handle, C.byref(coup.c), beta, batch, seed, step, C.byref(o),
-                                          _ptr(stats), _stream(stream)))
-        return stats
-
-    def train_step_distill(self, coup: Couplings, graph: LmcGraph, beta: float, w: float, batch: int, seed: int,
-                           step: int, stats=None, stream=None, **hyper):
-        if stats is None:
-            stats = torch.zeros(4, dtype=torch.float64, device=self.params.device)
-        o = muon_struct(**hyper)
-        _check(lib().fvan_train_step_distill(self.handle, C.byref(coup.c), C.byref(graph.c), beta, w, batch, seed,
-                                             step, C.byref(o), _ptr(stats), _stream(stream)))
-        return stats
 
     def close(self):
         if getattr(self, "handle", None):

@@ -8,6 +8,7 @@
 
 #include "fvan_internal.h"
 #include "fvan_model.h"
+#include "passes.h"
 
 namespace fvan {
 
@@ -67,8 +68,9 @@ static int check_config(const fvan_model_config* c) {
   if (c->n_layers < 0 || c->n_layers > 64) return fail(FVAN_EINVAL, "n_layers out of range");
   if (c->window < 0 || c->prefix < 0 || c->prefix > c->n_spins) return fail(FVAN_EINVAL, "mask out of range");
   if (c->max_batch < 1) return fail(FVAN_EINVAL, "max_batch must be >= 1");
-  if (c->precision != FVAN_FP32 && c->precision != FVAN_BF16 && c->precision != FVAN_BF16_SPLIT)
-    return fail(FVAN_EINVAL, "unknown precision");
+  if (c->precision != FVAN_FP32 && c->precision != FVAN_BF16_SPLIT)
+    return fail(FVAN_EINVAL, "unknown precision (FVAN_FP32 = 0 or FVAN_BF16_SPLIT = 2)");
+  if (c->workspaces & ~(FVAN_WS_SAMPLER | FVAN_WS_TEACHER)) return fail(FVAN_EINVAL, "unknown workspace bits");
   return FVAN_OK;
 }
 
@@ -196,11 +198,13 @@ int fvan_sample(fvan_model* m, int32_t batch, uint64_t seed, uint64_t stream_id,
                 void* stream) {
   if (!m || !spins || !log_q) return fail(FVAN_EINVAL, "NULL argument");
   if (m->cfg.vocab != 2) return fail(FVAN_EUNSUPPORTED, kBinaryOnly);
+  if (!has_sampler(m)) return fail(FVAN_EUNSUPPORTED, kNoSampler);
   if (!m->params || !m->synced) return fail(FVAN_EINVAL, "parameters not bound/synced");
   if (batch < 1 || batch > m->cfg.max_batch) return fail(FVAN_EINVAL, "batch outside [1, max_batch]");
   DecodeUnit u = make_decode_unit(m, batch, seed, stream_id, spins, log_q, m->kv, 0);
   const int tiles = (batch + decode_tile_samples() - 1) / decode_tile_samples();
   FVAN_HIP(launch_decode_single(m->cfg.d_model, m->cfg.precision, u, tiles, (hipStream_t)stream));
+  FVAN_HIP(check_finite(m, log_q, batch, (hipStream_t)stream));
   return FVAN_OK;
 }
 
@@ -235,6 +239,7 @@ int fvan_reinforce_weights(int32_t batch, double beta, int32_t is_int, const voi
 int fvan_adam_step(fvan_model* m, const fvan_adam* opt, int64_t step, void* stream) {
   if (!m || !opt) return fail(FVAN_EINVAL, "NULL argument");
   if (m->cfg.vocab != 2) return fail(FVAN_EUNSUPPORTED, kBinaryOnly);
+  if (!has_teacher(m)) return fail(FVAN_EUNSUPPORTED, kNoTeacher);
   if (!m->params || !m->grads) return fail(FVAN_EINVAL, "parameters and gradients must be bound");
   if (step < 1) return fail(FVAN_EINVAL, "step counts from 1");
   if (const char* why = check_adam(*opt)) return fail(FVAN_EINVAL, why);
@@ -302,6 +307,7 @@ int fvan_newton_schulz(int32_t rows, int32_t cols, int32_t steps, float eps, con
 int fvan_muon_step(fvan_model* m, const fvan_muon* opt, int64_t step, void* stream) {
   if (!m || !opt) return fail(FVAN_EINVAL, "NULL argument");
   if (m->cfg.vocab != 2) return fail(FVAN_EUNSUPPORTED, kBinaryOnly);
+  if (!has_teacher(m)) return fail(FVAN_EUNSUPPORTED, kNoTeacher);
   if (!m->params || !m->grads) return fail(FVAN_EINVAL, "parameters and gradients must be bound");
   if (step < 1) return fail(FVAN_EINVAL, "step counts from 1");
   if (const char* why = check_muon(*opt)) return fail(FVAN_EINVAL, why);

@@ -16,8 +16,7 @@
 // four consecutive rows of a dim), so the tile loops only load and multiply.
 //
 // Precision of the tile products (mode = fvan_precision): FP32 MFMA
-// (16x16x4, four per tile) for FVAN_FP32, BF16 MFMA (16x16x16) for FVAN_BF16,
-// and for FVAN_BF16_SPLIT the three products hi*hi + lo*hi + hi*lo of hi/lo
+// (16x16x4, four per tile) for FVAN_FP32, and for FVAN_BF16_SPLIT the three products hi*hi + lo*hi + hi*lo of hi/lo
 // BF16 operand splits (the dropped lo*lo term is below 2^-16 relative), issued
 // as two 16x16x32 MFMAs.
 #pragma once
@@ -48,13 +47,6 @@ template <> struct AOp<0> {
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
-  }
-};
-template <> struct AOp<1> {
-  typedef bf16x4 T;
-  static __device__ __forceinline__ T make(float a, float b, float c, float d) { return bf4(a, b, c, d); }
-  static __device__ __forceinline__ floatx4 mma(const T& a, const T& b, floatx4 acc) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
   }
 };
 struct SplitBf16x4 {

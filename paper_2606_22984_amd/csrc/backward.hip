@@ -31,11 +31,6 @@ template <> struct FragAB<0> {
     return Frag<0>::step(a, reinterpret_cast<const uint4*>(b), nullptr, acc);
   }
 };
-template <> struct FragAB<1> {
-  static __device__ __forceinline__ floatx4 step(const __bf16* a, const __bf16* b, floatx4 acc) {
-    return mfma_bf16(*reinterpret_cast<const uint4*>(a), *reinterpret_cast<const uint4*>(b), acc);
-  }
-};
 template <> struct FragAB<2> {
   static __device__ __forceinline__ floatx4 step(const float* a, const float* b, floatx4 acc) {
     float x[8], y[8];
@@ -567,11 +562,11 @@ static hipError_t backward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp
     e1.ln_g = lp + m->po.ln2_g;
     e1.ln_b = lp + m->po.ln2_b;
     if ((err = gemm_rows<MODE, D, 4 * D, EPI_GELU>(nullptr, rows, wl + m->pk.ffn1, e1, s))) return err;
-    // with FP32 activations (FP32 and split modes) the row-major dY operand is dX itself
-    constexpr bool kF32Act = sizeof(AT) == 4;
-    const AT* dY = kF32Act ? (const AT*)f.dX : (const AT*)f.DY;
+    // activations are FP32 in both modes: the row-major dY operand is dX itself
+    static_assert(sizeof(AT) == 4, "FP32 activations");
+    const AT* dY = (const AT*)f.dX;
     hipLaunchKernelGGL((transpose_cast_kernel<D, AT>), dim3(rgrid), dim3(256), 0, s, (const float*)f.dX, rows,
-                       kF32Act ? (AT*)nullptr : (AT*)f.DY, (AT*)f.T_a, f.ldT);
+                       (AT*)nullptr, (AT*)f.T_a, f.ldT);
     if ((err = wgrad<MODE, D, 4 * D>(m, f.T_a, f.T_b, rows, gl + m->po.ffn2_w, gl + m->po.ffn2_b, s))) return err;
     EpiArgs e2{};
     e2.hpre_in = f.HPRE;
@@ -622,7 +617,6 @@ hipError_t backward_chunk(fvan_model* m, const int8_t* spins, int nsamp, const f
   const int D = m->cfg.d_model;
 #define BWD_CASE(MODE, DD) if (m->cfg.precision == MODE && D == DD) return backward_chunk_t<MODE, DD>(m, spins, nsamp, w, s);
   BWD_CASE(0, 32) BWD_CASE(0, 64) BWD_CASE(0, 128)
-  BWD_CASE(1, 32) BWD_CASE(1, 64) BWD_CASE(1, 128)
   BWD_CASE(2, 32) BWD_CASE(2, 64) BWD_CASE(2, 128)
 #undef BWD_CASE
   return hipErrorInvalidValue;

@@ -392,7 +392,6 @@ static hipError_t dispatch_mode(int precision, const DecodeUnit& u0, const Decod
                                 int total_tiles, int* queue, int grid, hipStream_t s) {
   switch (precision) {
     case FVAN_FP32: return launch_d<D, 0>(u0, table, n_units, total_tiles, queue, grid, s);
-    case FVAN_BF16: return launch_d<D, 1>(u0, table, n_units, total_tiles, queue, grid, s);
     case FVAN_BF16_SPLIT: return launch_d<D, 2>(u0, table, n_units, total_tiles, queue, grid, s);
     default: return hipErrorInvalidValue;
   }

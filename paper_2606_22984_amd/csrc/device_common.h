@@ -15,7 +15,7 @@ constexpr int kHeadDim = 16;
 
 typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
 
-// Precision modes (fvan_precision).  KvT: K/V cache element; ActT: stored GEMM
+// Precision modes (fvan_precision: 0 and 2).  KvT: K/V cache element; ActT: stored GEMM
 // A operand (activations); WT: packed weight element; KC: K consumed per
 // 16x16 MFMA fragment step; SPLIT: weights and activations are carried as
 // bf16 hi + lo pairs and each step issues hi*hi + hi*lo + lo*hi.
@@ -23,10 +23,6 @@ template <int MODE> struct Mode;
 template <> struct Mode<0> {            // FP32: FP32 MFMA, FP32 K/V
   typedef float KvT; typedef float ActT; typedef float WT;
   static constexpr int KC = 16; static constexpr bool SPLIT = false;
-};
-template <> struct Mode<1> {            // BF16: BF16 MFMA (FP32 accumulation), BF16 K/V
-  typedef __bf16 KvT; typedef __bf16 ActT; typedef __bf16 WT;
-  static constexpr int KC = 32; static constexpr bool SPLIT = false;
 };
 template <> struct Mode<2> {            // BF16 split-operand MFMA, FP16 K/V
   typedef _Float16 KvT; typedef float ActT; typedef __bf16 WT;
@@ -138,20 +134,6 @@ template <> struct Frag<0> {
     acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(y.w, b3, acc1, 0, 0, 0);
   }
 };
-template <> struct Frag<1> {
-  static __device__ __forceinline__ floatx4 step(const __bf16* a, const uint4* b, const uint4*, floatx4 acc) {
-    return mfma_bf16(*reinterpret_cast<const uint4*>(a), *b, acc);
-  }
-  static __device__ __forceinline__ void step2(const __bf16* a0, const __bf16* a1, const uint4* b, const uint4*,
-                                               floatx4& acc0, floatx4& acc1) {
-    step2v(a0, a1, *b, *b, acc0, acc1);
-  }
-  static __device__ __forceinline__ void step2v(const __bf16* a0, const __bf16* a1, const uint4 bv, const uint4,
-                                                floatx4& acc0, floatx4& acc1) {
-    acc0 = mfma_bf16(*reinterpret_cast<const uint4*>(a0), bv, acc0);
-    acc1 = mfma_bf16(*reinterpret_cast<const uint4*>(a1), bv, acc1);
-  }
-};
 template <> struct Frag<2> {
   static __device__ __forceinline__ floatx4 step(const float* a, const uint4* b, const uint4* blo, floatx4 acc) {
     float x[8];
@@ -204,13 +186,6 @@ template <> struct FragA<0> {
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v.y, __uint_as_float(bv.y), acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v.z, __uint_as_float(bv.z), acc, 0, 0, 0);
     return __builtin_amdgcn_mfma_f32_16x16x4f32(v.w, __uint_as_float(bv.w), acc, 0, 0, 0);
-  }
-};
-template <> struct FragA<1> {
-  uint4 v;
-  __device__ __forceinline__ void load(const __bf16* a) { v = *reinterpret_cast<const uint4*>(a); }
-  __device__ __forceinline__ floatx4 mma(const uint4* b, const uint4*, floatx4 acc) const {
-    return mfma_bf16(v, *b, acc);
   }
 };
 template <> struct FragA<2> {

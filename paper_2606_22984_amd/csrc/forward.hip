@@ -255,7 +255,6 @@ hipError_t forward_chunk_tokens(fvan_model* m, const uint8_t* tokens, int nsamp,
   if (m->cfg.vocab < 2 || m->cfg.vocab > kHeadVocabThreads) return hipErrorInvalidValue;
 #define TOK_CASE(MODE, DD) if (m->cfg.precision == MODE && D == DD) return forward_chunk_tokens_t<MODE, DD>(m, tokens, nsamp, logq, s);
   TOK_CASE(0, 32) TOK_CASE(0, 64) TOK_CASE(0, 128)
-  TOK_CASE(1, 32) TOK_CASE(1, 64) TOK_CASE(1, 128)
   TOK_CASE(2, 32) TOK_CASE(2, 64) TOK_CASE(2, 128)
 #undef TOK_CASE
   return hipErrorInvalidValue;
@@ -266,7 +265,6 @@ hipError_t forward_chunk(fvan_model* m, const int8_t* spins, int nsamp, float* l
   const int D = m->cfg.d_model;
 #define FWD_CASE(MODE, DD) if (m->cfg.precision == MODE && D == DD) return forward_chunk_t<MODE, DD>(m, spins, nsamp, logq, for_backward, s);
   FWD_CASE(0, 32) FWD_CASE(0, 64) FWD_CASE(0, 128)
-  FWD_CASE(1, 32) FWD_CASE(1, 64) FWD_CASE(1, 128)
   FWD_CASE(2, 32) FWD_CASE(2, 64) FWD_CASE(2, 128)
 #undef FWD_CASE
   return hipErrorInvalidValue;

@@ -33,9 +33,10 @@ struct PackOffsets {
 };
 PackOffsets pack_offsets(const fvan_model_config& c);
 
-// Bytes per K/V cache element and per packed weight (split packs hold hi and lo).
+// Bytes per K/V cache element and per packed weight (FP32, or a split pack's
+// BF16 hi and lo).
 inline int kv_elem_bytes(int precision) { return precision == FVAN_FP32 ? 4 : 2; }
-inline int w_elem_bytes(int precision) { return precision == FVAN_BF16 ? 2 : 4; }
+inline int w_elem_bytes(int) { return 4; }
 
 // KV cache geometry of the sampler: per (sample, layer) [2][S][D], slots
 // [0, P) hold prefix positions, [P, P+R) a ring of the last R band positions.
@@ -74,8 +75,11 @@ struct DecodeUnit {
   int32_t d_token;
 };
 
-// Message of the entry points that need single-spin tokens (vocab 2).
+// Messages of the entry points a model's configuration does not provide.
 constexpr const char* kBinaryOnly = "a model over patch tokens (vocab > 2) supports only fvan_log_prob_tokens";
+constexpr const char* kNoSampler = "the model was created without FVAN_WS_SAMPLER (no KV cache)";
+constexpr const char* kNoTeacher = "the model was created without FVAN_WS_TEACHER (no teacher-forced workspace)";
+constexpr const char* kNoTrain = "a training step needs FVAN_WS_SAMPLER | FVAN_WS_TEACHER";
 
 // ----- error slot -----
 void set_error(const std::string& msg);

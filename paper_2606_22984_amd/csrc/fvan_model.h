@@ -18,6 +18,10 @@ struct fvan_model {
 
   // library-owned device workspaces
   void* wpack = nullptr;        // packed weight copies (precision-specific)
+  int* nf_flag = nullptr;       // device: set to nonzero by a kernel that finds a non-finite result
+  int* nf_host = nullptr;       // pinned host copy of nf_flag taken at the end of a training step
+  hipEvent_t nf_event = nullptr;  // recorded after that copy
+  bool nf_pending = false;      // a training step's copy is in flight
   void* kv = nullptr;           // sampler KV cache [max_batch][n_layers][2][S][D]
   size_t kv_bytes = 0;
   float* adam_m = nullptr;
@@ -36,7 +40,6 @@ struct fvan_model {
     float* LSE = nullptr;          // [n_layers][rows][H] log-sum-exp of the scores (base 2)
     float* DELTA = nullptr;        // [rows][H] dO . O per head (backward)
     float* TMP = nullptr;          // [rows][D] LayerNorm-output gradients (backward)
-    void* DY = nullptr;            // [rows][D] incoming gradient as a GEMM operand (backward)
     void* T_c = nullptr;           // [(D+16)][ldT] feature-major LN outputs (+ ones row) for weight gradients
     int64_t ldT = 0;               // row stride of the feature-major buffers (rows rounded up to 64)
     void* QKV = nullptr;           // [n_layers][rows][3D] (K/V element type)
@@ -58,7 +61,10 @@ struct fvan_model {
 };
 
 namespace fvan {
+// Allocate and initialise every workspace cfg.workspaces asks for (synchronous).
 int model_allocate(fvan_model* m);
+inline bool has_sampler(const fvan_model* m) { return (m->cfg.workspaces & FVAN_WS_SAMPLER) != 0; }
+inline bool has_teacher(const fvan_model* m) { return (m->cfg.workspaces & FVAN_WS_TEACHER) != 0; }
 void model_free(fvan_model* m);
 void model_free_fwd(fvan_model* m);
 DecodeUnit make_decode_unit(const fvan_model* m, int32_t batch, uint64_t seed, uint64_t stream_id, int8_t* spins,

@@ -40,11 +40,11 @@ struct GroupStatUnit {
 };
 
 // One workgroup per (unit, sample); ELL bonds only (dense SK units use the
-// per-unit path).  Same arithmetic and order as the single-model kernel.
+// per-unit path).  Same arithmetic and summation order as the single-model
+// kernel (energy_ell_kernel), so the energies are bitwise equal to fvan_energy's.
 __global__ __launch_bounds__(256) void group_energy_kernel(const GroupEnergyUnit* __restrict__ units,
                                                            const int64_t* __restrict__ first, int n_units) {
   __shared__ int8_t srow[4096];
-  __shared__ double red[4];
   const int64_t item = blockIdx.x;
   int lo = 0, hi = n_units - 1;
   while (lo < hi) {
@@ -72,15 +72,29 @@ __global__ __launch_bounds__(256) void group_energy_kernel(const GroupEnergyUnit
     iacc += srow[i] * ip;
     facc += (float)srow[i] * fp;
   }
-  double v = pm1 ? (double)iacc : (double)facc;
+  // the single-model kernel's reduction: lanes, then the waves in order, in the
+  // accumulation type (int32 for +-J bonds, float otherwise)
+  __shared__ int ired[4];
+  __shared__ float fred[4];
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  for (int off = 32; off > 0; off >>= 1) {
+    iacc += __shfl_xor(iacc, off);
+    facc += __shfl_xor(facc, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    ired[threadIdx.x >> 6] = iacc;
+    fred[threadIdx.x >> 6] = facc;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double tot = red[0] + red[1] + red[2] + red[3];
-    if (pm1) reinterpret_cast<int*>(u.energy)[b] = -(int)tot;
-    else reinterpret_cast<float*>(u.energy)[b] = -(float)tot;
+    int it = 0;
+    float ft = 0.f;
+    for (int w = 0; w < 4; ++w) {
+      it += ired[w];
+      ft += fred[w];
+    }
+    if (pm1) reinterpret_cast<int*>(u.energy)[b] = -it;
+    else reinterpret_cast<float*>(u.energy)[b] = -ft;
   }
 }
 
@@ -265,6 +279,10 @@ int fvan_group_create(const fvan_group_unit* units, int32_t n_units, int32_t til
     if (!m || !m->params || !m->synced || !u.couplings || !u.spins || !u.log_q || !u.energy || !u.stats) {
       delete g;
       return fail(FVAN_EINVAL, "unit " + std::to_string(i) + ": model not bound/synced or NULL buffer");
+    }
+    if (!has_sampler(m)) {
+      delete g;
+      return fail(FVAN_EUNSUPPORTED, "unit " + std::to_string(i) + ": " + kNoSampler);
     }
     if (m->cfg.d_model != g->d_model || m->cfg.precision != g->precision || m->cfg.n_heads != m0->cfg.n_heads) {
       delete g;

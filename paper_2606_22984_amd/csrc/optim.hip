@@ -62,7 +62,6 @@ static hipError_t pack_all(const fvan_model_config& c, const float* theta, void*
 hipError_t launch_pack(const fvan_model_config& c, const float* theta, void* wpack, hipStream_t s) {
   switch (c.precision) {
     case FVAN_FP32: return pack_all<0>(c, theta, wpack, s);
-    case FVAN_BF16: return pack_all<1>(c, theta, wpack, s);
     case FVAN_BF16_SPLIT: return pack_all<2>(c, theta, wpack, s);
     default: return hipErrorInvalidValue;
   }

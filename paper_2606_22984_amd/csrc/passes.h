@@ -78,7 +78,9 @@ hipError_t forward_chunk(fvan_model* m, const int8_t* spins, int nsamp, float* l
 hipError_t forward_chunk_tokens(fvan_model* m, const uint8_t* tokens, int nsamp, float* logq, hipStream_t s);
 // grads += sum_b w[b] d ln q_b / d theta for one chunk (recomputes the forward).
 hipError_t backward_chunk(fvan_model* m, const int8_t* spins, int nsamp, const float* w, hipStream_t s);
-// Allocate the forward/backward workspace on first use.
-int ensure_fwd_workspace(fvan_model* m);
+// Enqueue a check of n floats / doubles: the model's non-finite flag is set if
+// any is NaN or Inf.
+hipError_t check_finite(fvan_model* m, const float* v, int64_t n, hipStream_t s);
+hipError_t check_finite(fvan_model* m, const double* v, int64_t n, hipStream_t s);
 
 }  // namespace fvan

@@ -47,8 +47,9 @@ __global__ __launch_bounds__(kRThreads) void free_energy_kernel(int batch, int n
   }
 }
 
-// wlik: weight of the likelihood term of Eq. (loss2); every weight is lowered by
-// wlik / batch (0 gives the REINFORCE weights of Eq. 19).
+// wlik: weight w of the likelihood term of Eq. (loss2): weights are
+// ((L - Lbar) - w) / (beta batch), the 1/beta of the exact gradient scaling both
+// of its terms (w = 0 gives the REINFORCE weights of Eq. 19).
 __global__ __launch_bounds__(kRThreads) void reinforce_kernel(int batch, double beta, int is_int,
                                                               const void* __restrict__ energy,
                                                               const float* __restrict__ logq,
@@ -60,7 +61,7 @@ __global__ __launch_bounds__(kRThreads) void reinforce_kernel(int batch, double 
   const double scale = 1.0 / (beta * (double)batch);
   for (int b = threadIdx.x; b < batch; b += kRThreads) {
     const double L = beta * load_energy(energy, is_int, b) + (double)logq[b];
-    w[b] = (float)((L - Lbar) * scale - wlik / (double)batch);
+    w[b] = (float)(((L - Lbar) - wlik) * scale);
   }
   if (threadIdx.x == 0 && Lmean_out) *Lmean_out = Lbar;
 }

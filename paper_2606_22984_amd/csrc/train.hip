@@ -7,82 +7,26 @@
 
 namespace fvan {
 
-template <typename T>
-__global__ void set_rows_kernel(T* p, int64_t ld, int row0, int nrows, int64_t cols, float value) {
-  const int64_t total = (int64_t)nrows * cols;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
-    p[(int64_t)(row0 + i / cols) * ld + i % cols] = from_f<T>(value);
-}
-
-template <typename T>
-static hipError_t set_rows(void* p, int64_t ld, int row0, int nrows, int64_t cols, float v) {
-  const int64_t total = (int64_t)nrows * cols;
-  hipLaunchKernelGGL((set_rows_kernel<T>), dim3((int)std::min<int64_t>((total + 255) / 256, 4096)), dim3(256), 0,
-                     nullptr, (T*)p, ld, row0, nrows, cols, v);
-  return hipGetLastError();
-}
-
-static int walloc(void** p, size_t bytes, const char* what) {
-  if (hipMalloc(p, std::max<size_t>(bytes, 16)) != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    return fail(FVAN_ENOMEM, std::string("hipMalloc failed for the forward/backward workspace (") + what + ", " +
-                                 std::to_string(bytes) + " bytes)");
+// Training steps: wait for the previous step of this model and report its
+// finiteness check (see fvan_train_step); FVAN_OK when it was finite.
+static int previous_step_status(fvan_model* m) {
+  if (!m->nf_pending) return FVAN_OK;
+  if (hipEventSynchronize(m->nf_event) != hipSuccess) return fail(FVAN_EDEVICE, "hipEventSynchronize failed");
+  m->nf_pending = false;
+  if (*m->nf_host) {
+    *m->nf_host = 0;
+    if (hipMemset(m->nf_flag, 0, 4) != hipSuccess) return fail(FVAN_EDEVICE, "hipMemset of the flag failed");
+    return fail(FVAN_ENONFINITE, "the previous training step of this model produced a non-finite value");
   }
   return FVAN_OK;
 }
 
-int ensure_fwd_workspace(fvan_model* m) {
-  auto& f = m->fw;
-  if (f.X) return FVAN_OK;
-  const fvan_model_config& c = m->cfg;
-  const int64_t D = c.d_model, H = c.n_heads, L = c.n_layers, N = c.n_spins;
-  f.chunk = fwd_chunk_samples(c);
-  f.rows = f.chunk * N;
-  f.ldT = (f.rows + 63) / 64 * 64;
-  const size_t R = (size_t)f.rows, ldT = (size_t)f.ldT;
-  const size_t at = c.precision == FVAN_BF16 ? 2 : 4;
-  const size_t kt = kv_elem_bytes(c.precision);
-  f.part_floats = (size_t)512 * 4 * D * (D + 16);
-  f.colpart_floats = std::max<size_t>((size_t)f.chunk * (2 * D + 2), ((R + 63) / 64) * 2 * D);
-  struct A { void** p; size_t bytes; const char* what; } allocs[] = {
-      {(void**)&f.X, (size_t)(L + 1) * R * D * 4, "X"},   {(void**)&f.XM, (size_t)L * R * D * 4, "XM"},
-      {(void**)&f.LSE, (size_t)L * R * H * 4, "LSE"},
-      {(void**)&f.DELTA, R * H * 4, "DELTA"},             {(void**)&f.TMP, R * D * 4, "TMP"},
-      {&f.DY, R * D * at, "DY"},
-      {&f.QKV, (size_t)L * R * 3 * D * kt, "QKV"},       {(void**)&f.HPRE, R * 4 * D * 4, "HPRE"},
-      {(void**)&f.dX, R * D * 4, "dX"},                   {(void**)&f.dXM, R * D * 4, "dXM"},
-      {&f.dQKV, R * 3 * D * at, "dQKV"},                  {&f.dH, R * 4 * D * at, "dH"},
-      {&f.T_a, 4 * D * ldT * at, "T_a"},
-      {&f.T_b, (4 * D + 16) * ldT * at, "T_b"},           {&f.T_c, (D + 16) * ldT * at, "T_c"},
-      {(void**)&f.part, f.part_floats * 4, "partials"},   {(void**)&f.colpart, f.colpart_floats * 4, "column partials"},
-      {(void**)&f.colpart2, (size_t)64 * (2 * D + 2) * 4, "column slices"},
-  };
-  for (auto& a : allocs) {
-    int rc = walloc(a.p, a.bytes, a.what);
-    if (rc) {
-      model_free_fwd(m);
-      return rc;
-    }
-  }
-  // ones row (bias gradients) and zero rows of the padded right operands
-  hipError_t e;
-  if (at == 2) {
-    e = set_rows<__bf16>(f.T_b, f.ldT, 4 * D, 1, f.ldT, 1.f);
-    if (e == hipSuccess) e = set_rows<__bf16>(f.T_b, f.ldT, 4 * D + 1, 15, f.ldT, 0.f);
-    if (e == hipSuccess) e = set_rows<__bf16>(f.T_c, f.ldT, D, 1, f.ldT, 1.f);
-    if (e == hipSuccess) e = set_rows<__bf16>(f.T_c, f.ldT, D + 1, 15, f.ldT, 0.f);
-  } else {
-    e = set_rows<float>(f.T_b, f.ldT, 4 * D, 1, f.ldT, 1.f);
-    if (e == hipSuccess) e = set_rows<float>(f.T_b, f.ldT, 4 * D + 1, 15, f.ldT, 0.f);
-    if (e == hipSuccess) e = set_rows<float>(f.T_c, f.ldT, D, 1, f.ldT, 1.f);
-    if (e == hipSuccess) e = set_rows<float>(f.T_c, f.ldT, D + 1, 15, f.ldT, 0.f);
-  }
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e != hipSuccess) {
-    model_free_fwd(m);
-    return fail(FVAN_EDEVICE, std::string("workspace initialisation: ") + hipGetErrorString(e));
-  }
+// End of a training step: check the statistics and hand the flag to the host.
+static int finish_step(fvan_model* m, const double* stats, hipStream_t s) {
+  FVAN_HIP(check_finite(m, stats, 4, s));
+  FVAN_HIP(hipMemcpyAsync(m->nf_host, m->nf_flag, 4, hipMemcpyDeviceToHost, s));
+  FVAN_HIP(hipEventRecord(m->nf_event, s));
+  m->nf_pending = true;
   return FVAN_OK;
 }
 
@@ -95,25 +39,24 @@ extern "C" {
 int fvan_log_prob(fvan_model* m, int32_t batch, const int8_t* spins, float* log_q, void* stream) {
   if (!m || !spins || !log_q) return fail(FVAN_EINVAL, "NULL argument");
   if (m->cfg.vocab != 2) return fail(FVAN_EUNSUPPORTED, kBinaryOnly);
+  if (!has_teacher(m)) return fail(FVAN_EUNSUPPORTED, kNoTeacher);
   if (!m->params || !m->synced) return fail(FVAN_EINVAL, "parameters not bound/synced");
   if (batch < 1 || batch > m->cfg.max_batch) return fail(FVAN_EINVAL, "batch outside [1, max_batch]");
-  int rc = ensure_fwd_workspace(m);
-  if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   const int64_t N = m->cfg.n_spins;
   for (int64_t b0 = 0; b0 < batch; b0 += m->fw.chunk) {
     const int nb = (int)std::min<int64_t>(m->fw.chunk, batch - b0);
     FVAN_HIP(forward_chunk(m, spins + b0 * N, nb, log_q + b0, false, s));
   }
+  FVAN_HIP(check_finite(m, log_q, batch, s));
   return FVAN_OK;
 }
 
 int fvan_log_prob_tokens(fvan_model* m, int32_t batch, const uint8_t* tokens, float* log_q, void* stream) {
   if (!m || !tokens || !log_q) return fail(FVAN_EINVAL, "NULL argument");
+  if (!has_teacher(m)) return fail(FVAN_EUNSUPPORTED, kNoTeacher);
   if (!m->params || !m->synced) return fail(FVAN_EINVAL, "parameters not bound/synced");
   if (batch < 1 || batch > m->cfg.max_batch) return fail(FVAN_EINVAL, "batch outside [1, max_batch]");
-  int rc = ensure_fwd_workspace(m);
-  if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   const int64_t N = m->cfg.n_spins;
   for (int64_t b0 = 0; b0 < batch; b0 += m->fw.chunk) {
@@ -129,15 +72,15 @@ int fvan_log_prob_backward(fvan_model* m, int32_t batch, const int8_t* spins, co
   if (m->cfg.vocab != 2) return fail(FVAN_EUNSUPPORTED, kBinaryOnly);
   if (!m->params || !m->synced) return fail(FVAN_EINVAL, "parameters not bound/synced");
   if (!m->grads) return fail(FVAN_EINVAL, "no gradient buffer bound");
+  if (!has_teacher(m)) return fail(FVAN_EUNSUPPORTED, kNoTeacher);
   if (batch < 1 || batch > m->cfg.max_batch) return fail(FVAN_EINVAL, "batch outside [1, max_batch]");
-  int rc = ensure_fwd_workspace(m);
-  if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   const int64_t N = m->cfg.n_spins;
   for (int64_t b0 = 0; b0 < batch; b0 += m->fw.chunk) {
     const int nb = (int)std::min<int64_t>(m->fw.chunk, batch - b0);
     FVAN_HIP(backward_chunk(m, spins + b0 * N, nb, grad_log_q + b0, s));
   }
+  FVAN_HIP(check_finite(m, m->grads, m->n_params, s));
   return FVAN_OK;
 }
 
@@ -150,8 +93,11 @@ static int train_step_gradient(fvan_model* m, const fvan_couplings* c, double be
   if (!(beta > 0.0)) return fail(FVAN_EINVAL, "beta must be > 0");
   if (step < 1) return fail(FVAN_EINVAL, "step counts from 1");
   if (!m->params || !m->grads) return fail(FVAN_EINVAL, "parameters and gradients must be bound");
+  if (!has_sampler(m) || !has_teacher(m)) return fail(FVAN_EUNSUPPORTED, kNoTrain);
   hipStream_t s = (hipStream_t)stream;
-  int rc = fvan_sample(m, batch, seed, step, m->ts_spins, m->ts_logq, stream);
+  int rc = previous_step_status(m);
+  if (rc) return rc;
+  rc = fvan_sample(m, batch, seed, step, m->ts_spins, m->ts_logq, stream);
   if (rc) return rc;
   if ((rc = fvan_energy(c, batch, m->ts_spins, m->ts_energy, stream))) return rc;
   const int is_int = c->kind == FVAN_BONDS_PM1;
@@ -170,7 +116,8 @@ int fvan_train_step(fvan_model* m, const fvan_couplings* c, double beta, int32_t
   if (const char* why = check_adam(*opt)) return fail(FVAN_EINVAL, why);
   int rc = train_step_gradient(m, c, beta, batch, seed, step, stats, stream);
   if (rc) return rc;
-  return fvan_adam_step(m, opt, (int64_t)step, stream);
+  if ((rc = fvan_adam_step(m, opt, (int64_t)step, stream))) return rc;
+  return finish_step(m, stats, (hipStream_t)stream);
 }
 
 int fvan_train_step_distill(fvan_model* m, const fvan_couplings* c, const fvan_lmc* g, double beta, double w,
@@ -184,8 +131,11 @@ int fvan_train_step_distill(fvan_model* m, const fvan_couplings* c, const fvan_l
   if (!m->params || !m->grads) return fail(FVAN_EINVAL, "parameters and gradients must be bound");
   if (!g->nbr || !g->J || !g->colour || g->degree < 1 || g->sweeps < 0 || m->cfg.n_spins > 16384)
     return fail(FVAN_EINVAL, "refinement graph or sweeps out of range");
+  if (!has_sampler(m) || !has_teacher(m)) return fail(FVAN_EUNSUPPORTED, kNoTrain);
   hipStream_t s = (hipStream_t)stream;
-  int rc = fvan_sample(m, batch, seed, step, m->ts_spins, m->ts_logq, stream);
+  int rc = previous_step_status(m);
+  if (rc) return rc;
+  rc = fvan_sample(m, batch, seed, step, m->ts_spins, m->ts_logq, stream);
   if (rc) return rc;
   const int is_int = c->kind == FVAN_BONDS_PM1;
   if ((rc = fvan_energy(c, batch, m->ts_spins, m->ts_energy, stream))) return rc;
@@ -199,7 +149,22 @@ int fvan_train_step_distill(fvan_model* m, const fvan_couplings* c, const fvan_l
   FVAN_HIP(launch_reinforce(batch, beta, is_int, m->ts_energy, m->ts_logq, m->ts_w, nullptr, s, w));
   if ((rc = fvan_log_prob_backward(m, batch, m->ts_spins, m->ts_w, stream))) return rc;
   FVAN_HIP(launch_grad_norm(m->grads, m->n_params, stats + 3, nullptr, s));
-  return fvan_muon_step(m, opt, (int64_t)step, stream);
+  if ((rc = fvan_muon_step(m, opt, (int64_t)step, stream))) return rc;
+  return finish_step(m, stats, s);
+}
+
+int fvan_model_status(fvan_model* m, void* stream) {
+  if (!m) return fail(FVAN_EINVAL, "model is NULL");
+  FVAN_HIP(hipStreamSynchronize((hipStream_t)stream));
+  m->nf_pending = false;                       // a training step's copy, if any, has landed
+  *m->nf_host = 0;
+  int v = 0;
+  FVAN_HIP(hipMemcpy(&v, m->nf_flag, 4, hipMemcpyDeviceToHost));
+  if (v) {
+    FVAN_HIP(hipMemset(m->nf_flag, 0, 4));
+    return fail(FVAN_ENONFINITE, "a kernel of this model produced a non-finite value");
+  }
+  return FVAN_OK;
 }
 
 int fvan_train_step_muon(fvan_model* m, const fvan_couplings* c, double beta, int32_t batch, uint64_t seed,
@@ -208,7 +173,8 @@ int fvan_train_step_muon(fvan_model* m, const fvan_couplings* c, double beta, in
   if (const char* why = check_muon(*opt)) return fail(FVAN_EINVAL, why);
   int rc = train_step_gradient(m, c, beta, batch, seed, step, stats, stream);
   if (rc) return rc;
-  return fvan_muon_step(m, opt, (int64_t)step, stream);
+  if ((rc = fvan_muon_step(m, opt, (int64_t)step, stream))) return rc;
+  return finish_step(m, stats, (hipStream_t)stream);
 }
 
 }  // extern "C"

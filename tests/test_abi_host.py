@@ -61,7 +61,7 @@ def test_invalid_configs_are_rejected_on_the_host():
     base = dict(n_spins=16, d_model=32, d_token=2, n_layers=2, n_heads=2, vocab=2, window=15, prefix=0,
                 max_batch=8, precision=0)
     bad = [dict(d_model=48), dict(n_heads=4), dict(vocab=1), dict(vocab=257), dict(window=-1), dict(prefix=17),
-           dict(max_batch=0), dict(precision=7)]
+           dict(max_batch=0), dict(precision=7), dict(precision=1), dict(workspaces=4)]
     for b in bad:
         c = fv.ModelConfigC(**{**base, **b})
         h = C.c_void_p()
@@ -139,3 +139,21 @@ def test_overlap_histogram_argument_checks():
     assert lib.fvan_overlap_histogram(0, 10, p, p, None) == -1
     assert lib.fvan_overlap_histogram((1 << 20) + 1, 10, p, p, None) == -1
     assert lib.fvan_overlap_histogram(4, 16001, p, p, None) == -1
+
+
+def test_model_status_and_group_argument_checks():
+    lib = fv.lib()
+    assert lib.fvan_model_status(None, None) == -1
+    assert lib.fvan_group_create(None, 1, 0, None) == -1
+
+
+def test_refinement_graph_needs_a_proper_colouring():
+    """Odd L under periodic boundaries puts the neighbours x = L-1 and x = 0 in one
+    checkerboard colour: the graph builder refuses it (host only, CPU tensors)."""
+    from workloads import ea_instance
+    g = fv.lmc_graph(ea_instance(6, 2, 1, "pm1"), 1, device="cpu")
+    assert g.colour.shape == (36,)
+    for L, dim in ((5, 2), (3, 3)):
+        with pytest.raises(ValueError, match="colouring"):
+            fv.lmc_graph(ea_instance(L, dim, 1, "pm1"), 1, device="cpu")
+    fv.lmc_graph(ea_instance(5, 2, 1, "pm1", pbc=False), 1, device="cpu")   # open boundaries: bipartite

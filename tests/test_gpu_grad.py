@@ -6,14 +6,14 @@ import torch
 
 import paper_2606_22984_amd as fv
 from oracle import estimator, exact, network as net, physics
-from tests.gpu_util import ALL_PRECISIONS, BF16, FP32, SITE_TOL, SPLIT, lattice_cfg, make_model, say, to_np
+from tests.gpu_util import ALL_PRECISIONS, FP32, SITE_TOL, SPLIT, lattice_cfg, make_model, say, to_np
 from workloads import ModelConfig, ea_instance, init_params, sk_instance
 from workloads.instances import random_spins
 
 pytestmark = pytest.mark.gpu
 
 # relative L2 error of a gradient vector, by precision
-GRAD_TOL = {FP32: 2e-4, BF16: 6e-2, SPLIT: 5e-3}
+GRAD_TOL = {FP32: 2e-4, SPLIT: 5e-3}
 
 
 def _rel(a, b):
@@ -29,7 +29,7 @@ def test_log_prob_normalised_by_enumeration_sk16(prec):
     lq = to_np(m.log_prob(sig)).astype(np.float64)
     total = np.exp(lq).sum()
     say(f"prec {prec}: sum q = {total:.8f}")
-    assert abs(total - 1.0) <= {FP32: 1e-5, BF16: 5e-2, SPLIT: 1e-3}[prec]
+    assert abs(total - 1.0) <= {FP32: 1e-5, SPLIT: 1e-3}[prec]
     ref = net.log_q(net.as_theta(theta), cfg, to_np(sig)[::257], chunk=256).numpy()
     assert np.max(np.abs(lq[::257] - ref)) / 16 <= SITE_TOL[prec]
 

@@ -6,8 +6,8 @@ import pytest
 import torch
 
 import paper_2606_22984_amd as fv
-from oracle import estimator, physics
-from tests.gpu_util import FP32, SPLIT, lattice_cfg, say, to_np
+from oracle import estimator, network as net, philox, physics
+from tests.gpu_util import DECISION_TOL, FP32, SITE_TOL, SPLIT, lattice_cfg, say, to_np
 from workloads import ea_instance, init_params
 
 pytestmark = pytest.mark.gpu
@@ -21,7 +21,7 @@ def _units(prec, sizes=(4, 6, 8), betas=(0.5, 1.5), batch=40, d=64):
         for beta in betas:
             inst = ea_instance(L, 2, 500 + k, "pm1")
             theta = init_params(cfg, 10 + k, "random")
-            m = fv.Model(cfg, batch + 8, prec, theta)
+            m = fv.Model(cfg, batch + 8, prec, theta, workspaces=fv.WS_SAMPLER)
             units.append(dict(model=m, couplings=fv.couplings(inst), beta=beta, batch=batch - 3 * k, seed=99,
                               stream_id=1000 + k, inst=inst, theta=theta, cfg=cfg))
             k += 1
@@ -88,3 +88,73 @@ def test_group_tile_size_is_the_decode_tile():
     fv.Group(a, tile_samples=32)
     with pytest.raises(fv.FvanError, match="32"):
         fv.Group(a, tile_samples=16)
+
+
+@pytest.mark.parametrize("prec", [FP32, SPLIT])
+def test_group_matches_oracle_at_batched_workload_shape(prec):
+    """The batched workload's unit shape (2D EA, d_model 64, 4 layers, 4 heads,
+    1024 samples per unit) at L = 16, 24 and 32 in one group, each unit checked
+    against the FP64 oracle directly: the teacher-forced decision check and the
+    per-site ln q on rows of the first tile, both sides of a tile boundary and
+    the last tile; energies exact and F_q statistics against the oracle."""
+    B = 1024
+    units = []
+    for k, L in enumerate((16, 24, 32)):
+        inst = ea_instance(L, 2, 900 + k, "pm1")
+        cfg = lattice_cfg(L, 2, 64, 4, 4)
+        assert (cfg.window, cfg.prefix) == (L, L + 1)
+        theta = init_params(cfg, 40 + k, "default")
+        m = fv.Model(cfg, B, prec, theta, workspaces=fv.WS_SAMPLER)
+        units.append(dict(model=m, couplings=fv.couplings(inst), beta=0.2 + 1.4 * k, batch=B, seed=17,
+                          stream_id=300 + k, inst=inst, theta=theta, cfg=cfg))
+    g = fv.Group(units)
+    g.run_graph()
+    torch.cuda.synchronize()
+    rows = [0, 31, 32, 500, B - 1]
+    for u, out in zip(units, g.outputs):
+        cfg = u["cfg"]
+        say(f"group unit L={int(round(cfg.n_spins ** 0.5))} prec {prec}: oracle on rows {rows}")
+        sp = to_np(out["spins"])
+        lq = to_np(out["log_q"]).astype(np.float64)
+        assert set(np.unique(sp)).issubset({-1, 1}) and np.all(np.isfinite(lq))
+        sub = sp[rows]
+        th = net.as_theta(u["theta"])
+        pp = net.cond_plus(th, cfg, sub, chunk=8).numpy()
+        uu = np.concatenate([philox.uniforms(u["seed"], u["stream_id"], 1, cfg.n_spins, b) for b in rows])
+        wrong = (uu < pp) != (sub > 0)
+        gap = np.abs(uu - pp)
+        bad = int((wrong & (gap >= DECISION_TOL[prec])).sum())
+        say(f"  decision mismatches outside tol {bad}, inside {int(wrong.sum()) - bad}")
+        assert bad == 0
+        ref = net.log_q(th, cfg, sub, chunk=8).numpy()
+        per_site = np.abs(lq[rows] - ref) / cfg.n_spins
+        say(f"  max per-site |d ln q| {per_site.max():.3e}")
+        assert per_site.max() <= SITE_TOL[prec]
+        Eref = physics.energy_edges_int(sp, u["inst"].edges_i, u["inst"].edges_j, u["inst"].J)
+        assert np.array_equal(to_np(out["energy"]).astype(np.int64), Eref)
+        mean, var = estimator.free_energy_stats(Eref, lq, u["beta"], cfg.n_spins)
+        st = to_np(out["stats"])
+        assert abs(st[0] - mean) <= 1e-12 * abs(mean) and abs(st[1] - var) <= 1e-9 * var
+
+
+def test_group_gaussian_bond_energies_equal_single_kernel():
+    """Float (Gaussian) bonds: the group's energy kernel sums in the single-model
+    kernel's order, so its energies equal fvan_energy's bitwise."""
+    units = []
+    for k, L in enumerate((4, 6)):
+        cfg = lattice_cfg(L, 2, 32, 2, 2)
+        inst = ea_instance(L, 2, 70 + k, "gauss")
+        m = fv.Model(cfg, 48, FP32, init_params(cfg, 3 + k, "random"), workspaces=fv.WS_SAMPLER)
+        units.append(dict(model=m, couplings=fv.couplings(inst), beta=1.0, batch=45, seed=2, stream_id=k,
+                          inst=inst))
+    g = fv.Group(units)
+    g.run()
+    torch.cuda.synchronize()
+    for u, out in zip(units, g.outputs):
+        E = fv.energy(u["couplings"], out["spins"])
+        torch.cuda.synchronize()
+        assert out["energy"].dtype == torch.float32
+        assert torch.equal(out["energy"], E)
+        ref = physics.energy_edges(to_np(out["spins"]), u["inst"].edges_i, u["inst"].edges_j,
+                                   u["inst"].J.astype(np.float32).astype(np.float64))
+        assert np.max(np.abs(to_np(E).astype(np.float64) - ref)) <= 1e-5 * u["inst"].n

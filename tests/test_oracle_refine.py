@@ -90,6 +90,6 @@ def test_distill_weights_sum_rule_and_reinforce_limit():
     E, lq = rng.standard_normal(33) * 5, rng.standard_normal(33) * 3 - 10
     for w in (0.0, 0.3, 2.0):
         c = refine.distill_weights(E, lq, 0.7, w)
-        assert abs(c.sum() + w) < 1e-12
+        assert abs(c.sum() + w / 0.7) < 1e-12           # the likelihood term carries the 1/beta too
     assert np.allclose(refine.distill_weights(E, lq, 0.7, 0.0), estimator.reinforce_weights(E, lq, 0.7),
                        rtol=0, atol=1e-15)
