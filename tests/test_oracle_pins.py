@@ -165,6 +165,31 @@ def test_conditionals_ignore_future_and_masked_past():
                 assert abs(net.cond_plus(th, cfg, flip).numpy()[0, t] - ref[t]) < 1e-13
 
 
+def test_one_layer_conditionals_depend_exactly_on_the_visible_sites():
+    """One decoder layer: the conditional at position t reads the spin carried by
+    key position j (site j - 1) only through attention, so it must change when
+    that spin flips iff j <= t and (t - j <= W or j < P) -- the band of SI Eq. S1
+    (A_tj = 0 only for t - j > W) plus the always-visible prefix (reading 11).
+    Written from that statement, not from the oracle's mask: a band one key
+    too narrow or too wide, or a lost prefix, fails here."""
+    n, W, P = 14, 3, 2
+    cfg = ModelConfig(n_spins=n, d_model=32, n_layers=1, n_heads=2).with_mask(W, P)
+    th = _theta(cfg, 8)
+    base = random_spins(1, n, 4)
+    ref = net.cond_plus(th, cfg, base).numpy()[0]
+    for site in range(n - 1):
+        flip = base.copy()
+        flip[0, site] *= -1
+        got = net.cond_plus(th, cfg, flip).numpy()[0]
+        j = site + 1
+        for t in range(n):
+            seen = j <= t and (t - j <= W or j < P)
+            if seen:
+                assert abs(got[t] - ref[t]) > 1e-9, (site, t)
+            else:
+                assert abs(got[t] - ref[t]) < 1e-13, (site, t)
+
+
 # ---------------------------------------------------------------- energy
 
 def _pair_loop_energy(sig, ei, ej, J):
