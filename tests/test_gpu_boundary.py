@@ -78,10 +78,12 @@ def test_nonfinite_parameters_are_reported():
     with pytest.raises(fv.FvanError, match="ENONFINITE"):
         m.train_step_muon(c, 1.0, 64, 3, 4)    # reports step 3 and enqueues nothing
     m.status()                                 # that report cleared the flag
-    # a sampling call alone: reported by the synchronising status call
+    # a sampling call alone: reported by the synchronising status call.  (An
+    # infinite head weight would not do: it saturates p to 0 or 1 and the drawn
+    # spin's log-probability is then exactly 0, a finite ln q.)
     m2, th2 = make_model(cfg, 32, FP32, seed=5)
     th2 = th2.copy()
-    th2[-5] = np.inf
+    th2[-5] = np.nan
     m2.set_params(th2)
     m2.sample(32, 1, 1)
     with pytest.raises(fv.FvanError, match="ENONFINITE"):

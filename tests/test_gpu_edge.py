@@ -37,7 +37,7 @@ def test_zero_layer_model(prec):
     gref = estimator.grad_surrogate(theta, cfg, to_np(s), to_np(w).astype(np.float64))
     rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
     say(f"  gradient rel. error {rel:.2e}")
-    assert rel <= {fv.FVAN_FP32: 2e-4, fv.FVAN_BF16: 6e-2, fv.FVAN_BF16_SPLIT: 5e-3}[prec]
+    assert rel <= {fv.FVAN_FP32: 2e-4, fv.FVAN_BF16_SPLIT: 5e-3}[prec]
     if prec == FP32:
         n = g.size
         new, _, _ = muon.muon_update(theta.astype(np.float64), g, np.zeros(n), np.zeros(n), 1, cfg, 1e-2,
