@@ -379,6 +379,27 @@ int fvan_group_run(fvan_group* group, void* stream);
 /* Capture fvan_group_run into a HIP graph on `stream` (once) and replay it. */
 int fvan_group_run_graph(fvan_group* group, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): fvan_sample
+ * with its KV cache in a static device array of the library, of
+ * FVAN_NOALLOC_KV_BYTES (64 MiB) per GPU, instead of the model's sampler
+ * workspace.  fvan_create_model sets the array up on its device (the runtime
+ * backs it with device memory then), and the GPU holds it until the process
+ * ends.  The model
+ * needs no FVAN_WS_SAMPLER.  Same kernel and same outputs (bitwise) as
+ * fvan_sample; this call allocates nothing and enqueues only on `stream`.
+ * A sample's cache takes n_layers * 2 * S * d_model * e bytes, S = P + min(W + 1,
+ * N - P) slots (P = min(prefix, N), W = window) and e = 4 (FVAN_FP32) or 2
+ * (FVAN_BF16_SPLIT).  EINVAL (nothing enqueued) when batch times that exceeds
+ * FVAN_NOALLOC_KV_BYTES, when the current HIP device is not the model's, or as
+ * fvan_sample.  Every call on one GPU shares that GPU's array, which keeps the
+ * last call's contents (nothing in it needs clearing: a sample's keys are
+ * written before they are read): calls that overlap in time on one GPU (other
+ * streams, threads or models) race on it and must be serialised by the caller. */
+#define FVAN_NOALLOC_KV_BYTES ((size_t)64 << 20)
+int fvan_sample_noalloc(fvan_model* model, int32_t batch, uint64_t seed, uint64_t stream_id,
+                        int8_t* spins, float* log_q, void* stream);
+
 /* Synchronise `stream`, then report and clear the model's non-finite flag:
  * FVAN_ENONFINITE if any kernel of this model found a NaN or Inf in its
  * results since the flag was last reported, else FVAN_OK. */

@@ -20,13 +20,15 @@ LIB_PATH = os.path.join(_HERE, "libfvan.so")
 FVAN_FP32, FVAN_BF16_SPLIT = 0, 2
 PRECISION_NAMES = {0: "fp32", 2: "bf16split"}
 WS_SAMPLER, WS_TEACHER = 1, 2
+# bytes of the static KV cache of fvan_sample_noalloc (FVAN_NOALLOC_KV_BYTES), per GPU
+NOALLOC_KV_BYTES = 64 << 20
 BONDS_PM1, BONDS_F32, BONDS_DENSE = 0, 1, 2
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "EUNSUPPORTED"}
 
 # Every symbol include/fvan.h declares.
 EXPORTS = (
     "fvan_num_params", "fvan_derive_mask", "fvan_create_model", "fvan_destroy_model", "fvan_bind_params",
-    "fvan_sync_params", "fvan_sample", "fvan_log_prob", "fvan_log_prob_tokens", "fvan_log_prob_backward", "fvan_energy",
+    "fvan_sync_params", "fvan_sample", "fvan_sample_noalloc", "fvan_log_prob", "fvan_log_prob_tokens", "fvan_log_prob_backward", "fvan_energy",
     "fvan_free_energy", "fvan_reinforce_weights", "fvan_adam_step", "fvan_train_step",
     "fvan_newton_schulz", "fvan_muon_step", "fvan_train_step_muon",
     "fvan_lmc_refine", "fvan_distill_weights", "fvan_train_step_distill",
@@ -117,6 +119,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "fvan_group_run": [P, P],
         "fvan_group_run_graph": [P, P],
         "fvan_model_status": [P, P],
+        "fvan_sample_noalloc": [P, I32, U64, U64, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -380,6 +383,19 @@ class Model:
             raise ValueError(f"spins holds {spins.shape[0]} rows, batch is {batch}")
         _vec_arg(log_q, batch, "log_q")
         _check(lib().fvan_sample(self.handle, batch, seed, stream_id, _ptr(spins), _ptr(log_q), _stream(stream)))
+        return spins, log_q
+
+    def sample_noalloc(self, batch: int, seed: int, stream_id: int, spins: torch.Tensor, log_q: torch.Tensor,
+                       stream=None):
+        """fvan_sample with the library's static KV cache (no device allocation in the
+        call; the caller passes the output tensors)."""
+        _require_cuda(spins, log_q)
+        _spins_arg(spins, self.cfg.n_spins)
+        if spins.shape[0] < batch:
+            raise ValueError(f"spins holds {spins.shape[0]} rows, batch is {batch}")
+        _vec_arg(log_q, batch, "log_q")
+        _check(lib().fvan_sample_noalloc(self.handle, batch, seed, stream_id, _ptr(spins), _ptr(log_q),
+                                         _stream(stream)))
         return spins, log_q
 
     def log_prob(self, spins: torch.Tensor, log_q=None, stream=None):

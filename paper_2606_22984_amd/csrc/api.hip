@@ -164,6 +164,10 @@ int fvan_create_model(const fvan_model_config* cfg, fvan_model** out) {
   if (!m) return fail(FVAN_ENOMEM, "host allocation failed");
   m->cfg = clamp_mask(*cfg);
   rc = model_allocate(m);
+  // the static KV cache of fvan_sample_noalloc is resolved here, at set-up on
+  // the model's device, so that the sampling call itself never makes the
+  // runtime materialise it
+  if (!rc) rc = static_kv_setup(m->device);
   if (rc) {
     model_free(m);
     delete m;

@@ -69,5 +69,8 @@ void model_free(fvan_model* m);
 void model_free_fwd(fvan_model* m);
 DecodeUnit make_decode_unit(const fvan_model* m, int32_t batch, uint64_t seed, uint64_t stream_id, int8_t* spins,
                             float* log_q, void* kv, int tile0);
+// Resolve (once per device; `dev` must be current) the device address of the
+// static KV cache fvan_sample_noalloc uses.
+int static_kv_setup(int dev);
 hipError_t launch_decode_single(int d_model, int precision, const DecodeUnit& u, int tiles, hipStream_t s);
 }  // namespace fvan
