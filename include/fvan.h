@@ -39,13 +39,14 @@
  *   pos_emb [n_spins, d_pos]   d_pos = d_model - d_token
  *   per layer: ln1.g [d], ln1.b [d], qkv.w [3d, d], qkv.b [3d], ln2.g [d], ln2.b [d],
  *              ffn1.w [4d, d], ffn1.b [4d], ffn2.w [d, 4d], ffn2.b [d]
- *              (qkv rows: Q, then K, then V; head h owns rows h*16 .. h*16+15 of each)
+ *              (qkv rows: Q, then K, then V; head h owns rows h*d_h .. h*d_h+d_h-1 of each,
+ *              d_h = d_model / n_heads)
  *   head.w [vocab, d], head.b [vocab]
  * Count: n_layers (11 d^2 + 12 d) + n_spins d_pos + vocab d_token + vocab (d + 1).
  *
  * Network (per position t, tok_0 = start, tok_t = s_{t-1}):
  *   h = [tok_emb[tok_t]; pos_emb[t]]
- *   per layer: h += concat_heads(softmax_j(q_t.k_j / 4) v_j)  with q,k,v = qkv.w LN1(h) + qkv.b
+ *   per layer: h += concat_heads(softmax_j(q_t.k_j / sqrt(d_h)) v_j)  with q,k,v = qkv.w LN1(h) + qkv.b
  *              h += ffn2.w GELU(ffn1.w LN2(h) + ffn1.b) + ffn2.b
  *   z_t = head.w h + head.b ;  log p_t(s) = z_{t,s} - logsumexp(z_t)
  * LayerNorm: affine, population variance, eps 1e-5.  GELU: x Phi(x) (erf form).
@@ -103,8 +104,9 @@ typedef struct {
   int32_t d_model;     /* d = d_token + d_pos; 32, 64 or 128 */
   int32_t d_token;     /* token-embedding width (2 for single spins) */
   int32_t n_layers;
-  int32_t n_heads;     /* d_model / n_heads must be 16 */
-  int32_t vocab;       /* 2 (single spins); up to 256 for patch tokens, fvan_log_prob_tokens only */
+  int32_t n_heads;     /* d_h = d_model / n_heads must be 16, 32 or 64 (16: MFMA attention in the
+                          teacher-forced passes; 32, 64: FP32 attention kernels) */
+  int32_t vocab;       /* 2 (single spins); up to 256 for patch tokens (the token calls) */
   int32_t window;      /* W of the mask, 0 <= W; values >= n_spins-1 mean full causal */
   int32_t prefix;      /* P of the mask, 0 <= P <= n_spins */
   int32_t max_batch;   /* largest batch any call on this model will pass */
@@ -219,10 +221,47 @@ int fvan_log_prob(fvan_model* model, int32_t batch, const int8_t* spins, float* 
  * tokens (sigma + 1) / 2 it equals fvan_log_prob up to FP32 rounding.  A token
  * >= vocab makes its sample's ln q NaN (no read leaves the parameter vector).
  * EINVAL for NULL pointers, unsynced parameters or batch outside [1, max_batch].
- * A model with vocab > 2 supports only this call among the model entry points
- * (sampling, fvan_log_prob, the backward, the optimiser steps, the training
- * steps and groups return EUNSUPPORTED). */
+ * A model with vocab > 2 takes the token calls (this one, fvan_sample_tokens,
+ * fvan_log_prob_tokens_backward, fvan_train_step_tokens) and the optimiser
+ * steps; the spin calls (fvan_sample, fvan_log_prob, fvan_log_prob_backward,
+ * the spin training steps, groups) return EUNSUPPORTED for it. */
 int fvan_log_prob_tokens(fvan_model* model, int32_t batch, const uint8_t* tokens, float* log_q, void* stream);
+
+/* Ancestral sampling of token sequences (Alg. 2 over 2^D-spin patch tokens,
+ * Methods, model configurations and training settings): at position t the
+ * head gives z_t (vocab outputs, FP32) and p_t = softmax(z_t); with one uniform
+ * u(b, t) per position, drawn exactly as in fvan_sample, the token is the
+ * largest k >= 1 with u < sum_{j >= k} p_t(j), else 0 (the vocabulary walked
+ * from the top; for vocab 2 this is fvan_sample's rule with token (sigma+1)/2),
+ * and it is fed to the token embedding of position t + 1.  Outputs tokens
+ * uint8 [batch, n_spins] and log_q [batch] = sum_t ln p_t(tok_t) (FP32).  Any
+ * vocab in [2, 256].  EINVAL if batch is not in [1, max_batch]. */
+int fvan_sample_tokens(fvan_model* model, int32_t batch, uint64_t seed, uint64_t stream_id, uint8_t* tokens,
+                       float* log_q, void* stream);
+
+/* grads += sum_b grad_log_q[b] * d ln q(tok_b) / d theta for token sequences
+ * (the backward of fvan_log_prob_tokens; the forward is recomputed).
+ * EUNSUPPORTED when vocab > 16 with d_model < 64, or vocab * d_token > 16384. */
+int fvan_log_prob_tokens_backward(fvan_model* model, int32_t batch, const uint8_t* tokens,
+                                  const float* grad_log_q, void* stream);
+
+/* Spins of token sequences (the inverse of the patch map): for every sample b,
+ * token t and bit m < bits, spins[b][sites[t * bits + m]] = bit m of
+ * tokens[b][t] ? +1 : -1.  sites: device int32 [n_tokens, bits], a permutation
+ * of [0, n_spins) (entries outside that range are skipped); spins: device int8
+ * [batch, n_spins].  EINVAL unless n_tokens * bits == n_spins, bits in [1, 8]. */
+int fvan_tokens_to_spins(int32_t n_tokens, int32_t bits, const int32_t* sites, int32_t n_spins, int32_t batch,
+                         const uint8_t* tokens, int8_t* spins, void* stream);
+
+/* One training step of a model over 2^D-spin patch tokens (vocab = 2^bits,
+ * bits = 2^D; the sequence is the model's n_spins tokens): sample tokens
+ * (seed, stream_id = step) -> spins through `sites` (as fvan_tokens_to_spins)
+ * -> energies -> F_q statistics per lattice site (n = n_spins * bits) ->
+ * REINFORCE weights -> token backward -> gradient norm -> Muon update.  stats
+ * as fvan_train_step.  couplings->n_spins must be n_spins * bits. */
+int fvan_train_step_tokens(fvan_model* model, const fvan_couplings* couplings, const int32_t* sites, double beta,
+                           int32_t batch, uint64_t seed, uint64_t step, const fvan_muon* opt, double* stats,
+                           void* stream);
 
 /* grads += sum_b grad_log_q[b] * d ln q(sigma_b) / d theta.  Recomputes the
  * forward pass (attention included) in chunks of samples; nothing from an

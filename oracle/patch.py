@@ -19,8 +19,8 @@ Readings (the paper fixes none of these):
     with bit value (sigma + 1) / 2;
   * categorical draw from one uniform u per (sample, position), the sampler's
     Philox stream: the token is found by walking the vocabulary from the top,
-    tok = the largest k with u >= sum_{j > k} p_j, i.e. u < p_{V-1} gives V-1,
-    else u < p_{V-1} + p_{V-2} gives V-2, and so on.  With V = 2 this is the
+    tok = the largest k >= 1 with u < sum_{j >= k} p_j, else 0, i.e. u < p_{V-1}
+    gives V-1, else u < p_{V-1} + p_{V-2} gives V-2, and so on.  With V = 2 this is the
     binary rule s = +1 iff u < p(+1), so unpatched sampling is the special case.
 """
 from __future__ import annotations
@@ -98,6 +98,24 @@ def log_q_tokens(theta, cfg, tok, chunk: int = 64) -> np.ndarray:
             lp = torch.log_softmax(logits_tokens(th, cfg, tk), dim=-1)
             outs.append(torch.gather(lp, -1, tk.unsqueeze(-1)).squeeze(-1).sum(dim=1))
     return torch.cat(outs).numpy()
+
+
+def grad_surrogate_tokens(theta, cfg, tok, c, chunk: int = 32) -> np.ndarray:
+    """grad_theta sum_b c_b ln q(tok_b), float64 [n_params]: reverse mode through
+    the token logits above (the REINFORCE gradient of a patched model, Eq. 18,
+    is this with c_b the weights of Eq. 19)."""
+    tok = torch.as_tensor(np.asarray(tok, dtype=np.int64))
+    c = torch.as_tensor(np.asarray(c, dtype=np.float64))
+    th = net.as_theta(theta, requires_grad=True)
+    g = torch.zeros_like(th)
+    for b0 in range(0, tok.shape[0], chunk):
+        th.grad = None
+        tk = tok[b0:b0 + chunk]
+        lp = torch.log_softmax(logits_tokens(th, cfg, tk), dim=-1)
+        lq = torch.gather(lp, -1, tk.unsqueeze(-1)).squeeze(-1).sum(dim=1)
+        (c[b0:b0 + chunk] * lq).sum().backward()
+        g += th.grad
+    return g.detach().numpy()
 
 
 def log_q_spins(theta, cfg, spins, L: int, D: int, chunk: int = 64) -> np.ndarray:

@@ -28,7 +28,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", 
 # Every symbol include/fvan.h declares.
 EXPORTS = (
     "fvan_num_params", "fvan_derive_mask", "fvan_create_model", "fvan_destroy_model", "fvan_bind_params",
-    "fvan_sync_params", "fvan_sample", "fvan_sample_noalloc", "fvan_log_prob", "fvan_log_prob_tokens", "fvan_log_prob_backward", "fvan_energy",
+    "fvan_sync_params", "fvan_sample", "fvan_sample_noalloc", "fvan_sample_tokens", "fvan_log_prob_tokens_backward",
+    "fvan_tokens_to_spins", "fvan_train_step_tokens", "fvan_log_prob", "fvan_log_prob_tokens", "fvan_log_prob_backward", "fvan_energy",
     "fvan_free_energy", "fvan_reinforce_weights", "fvan_adam_step", "fvan_train_step",
     "fvan_newton_schulz", "fvan_muon_step", "fvan_train_step_muon",
     "fvan_lmc_refine", "fvan_distill_weights", "fvan_train_step_distill",
@@ -120,6 +121,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "fvan_group_run_graph": [P, P],
         "fvan_model_status": [P, P],
         "fvan_sample_noalloc": [P, I32, U64, U64, P, P, P],
+        "fvan_sample_tokens": [P, I32, U64, U64, P, P, P],
+        "fvan_log_prob_tokens_backward": [P, I32, P, P, P],
+        "fvan_tokens_to_spins": [I32, I32, P, I32, I32, P, P, P],
+        "fvan_train_step_tokens": [P, C.POINTER(CouplingsC), P, D, I32, U64, U64, C.POINTER(MuonC), P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -165,6 +170,41 @@ def _spins_arg(spins, n: int):
     """The C side reads batch x n int8 spins from the pointer: check that much is there."""
     if spins.dtype != torch.int8 or spins.dim() != 2 or spins.shape[1] != n or spins.shape[0] < 1:
         raise ValueError(f"spins must be an int8 [batch, {n}] tensor (got {tuple(spins.shape)}, {spins.dtype})")
+
+
+def _tokens_arg(t, n: int):
+    if t.dtype != torch.uint8 or t.dim() != 2 or not t.is_contiguous() or t.shape[1] != n:
+        raise ValueError(f"tokens must be a contiguous uint8 [batch, {n}] tensor")
+
+
+def patch_sites(L: int, dim: int) -> np.ndarray:
+    """Site of every bit of every patch token of a periodic L^dim lattice cut into
+    2^dim blocks (patches in raster order of their block coordinates, last
+    fastest; the site at offset o in {0,1}^dim of a patch is bit
+    sum_k o_k 2^(dim-1-k) of its token): int32 [(L/2)^dim, 2^dim]."""
+    if L % 2:
+        raise ValueError("patches need an even lattice side")
+    half = L // 2
+    blocks = np.stack(np.unravel_index(np.arange(half ** dim), (half,) * dim), axis=1)      # [T, dim]
+    offs = np.stack(np.unravel_index(np.arange(2 ** dim), (2,) * dim), axis=1)              # [2^dim, dim]
+    coords = 2 * blocks[:, None, :] + offs[None, :, :]                                    # [T, 2^dim, dim]
+    return np.ravel_multi_index(tuple(np.moveaxis(coords, -1, 0)), (L,) * dim).astype(np.int32)
+
+
+def tokens_to_spins(sites: torch.Tensor, tokens: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """int8 +-1 spins [batch, n_tokens * bits] of patch tokens (fvan_tokens_to_spins)."""
+    _require_cuda(sites, tokens)
+    T, bits = sites.shape
+    if sites.dtype != torch.int32 or not sites.is_contiguous():
+        raise ValueError("sites must be a contiguous int32 [n_tokens, bits] tensor")
+    _tokens_arg(tokens, T)
+    n = T * bits
+    if out is None:
+        out = torch.empty(tokens.shape[0], n, dtype=torch.int8, device=tokens.device)
+    _spins_arg(out, n)
+    _check(lib().fvan_tokens_to_spins(T, bits, _ptr(sites), n, tokens.shape[0], _ptr(tokens), _ptr(out),
+                                      _stream(stream)))
+    return out
 
 
 def _vec_arg(t, batch: int, name: str, dtypes=(torch.float32,)):
@@ -417,6 +457,42 @@ class Model:
             log_q = torch.empty(tokens.shape[0], dtype=torch.float32, device=tokens.device)
         _check(lib().fvan_log_prob_tokens(self.handle, tokens.shape[0], _ptr(tokens), _ptr(log_q), _stream(stream)))
         return log_q
+
+    def sample_tokens(self, batch: int, seed: int, stream_id: int, tokens=None, log_q=None, stream=None):
+        """Ancestral sampling of patch-token sequences (uint8 [batch, n_spins]) and their ln q."""
+        dev = self.params.device
+        if tokens is None:
+            tokens = torch.empty(batch, self.cfg.n_spins, dtype=torch.uint8, device=dev)
+        if log_q is None:
+            log_q = torch.empty(batch, dtype=torch.float32, device=dev)
+        _require_cuda(tokens, log_q)
+        _tokens_arg(tokens, self.cfg.n_spins)
+        if tokens.shape[0] < batch:
+            raise ValueError(f"tokens holds {tokens.shape[0]} rows, batch is {batch}")
+        _vec_arg(log_q, batch, "log_q")
+        _check(lib().fvan_sample_tokens(self.handle, batch, seed, stream_id, _ptr(tokens), _ptr(log_q),
+                                        _stream(stream)))
+        return tokens, log_q
+
+    def log_prob_tokens_backward(self, tokens: torch.Tensor, grad_log_q: torch.Tensor, stream=None):
+        _require_cuda(tokens, grad_log_q)
+        _tokens_arg(tokens, self.cfg.n_spins)
+        _vec_arg(grad_log_q, tokens.shape[0], "grad_log_q")
+        _check(lib().fvan_log_prob_tokens_backward(self.handle, tokens.shape[0], _ptr(tokens), _ptr(grad_log_q),
+                                                   _stream(stream)))
+
+    def train_step_tokens(self, coup: "Couplings", sites: torch.Tensor, beta: float, batch: int, seed: int,
+                          step: int, stats=None, stream=None, **hyper):
+        """Training step of a patch-token model (Muon); sites: int32 [n_spins, bits] on the device."""
+        if stats is None:
+            stats = torch.zeros(4, dtype=torch.float64, device=self.params.device)
+        _require_cuda(sites)
+        if sites.dtype != torch.int32 or not sites.is_contiguous() or sites.shape[0] != self.cfg.n_spins:
+            raise ValueError("sites must be a contiguous int32 [n_tokens, bits] tensor")
+        o = muon_struct(**hyper)
+        _check(lib().fvan_train_step_tokens(self.handle, C.byref(coup.c), _ptr(sites), beta, batch, seed, step,
+                                            C.byref(o), _ptr(stats), _stream(stream)))
+        return stats
 
     def log_prob_backward(self, spins: torch.Tensor, grad_log_q: torch.Tensor, stream=None):
         _require_cuda(spins, grad_log_q)

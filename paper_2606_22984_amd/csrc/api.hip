@@ -61,8 +61,9 @@ static int check_config(const fvan_model_config* c) {
   if (c->n_spins < 1) return fail(FVAN_EINVAL, "n_spins must be >= 1");
   if (c->d_model != 32 && c->d_model != 64 && c->d_model != 128)
     return fail(FVAN_EUNSUPPORTED, "d_model must be 32, 64 or 128");
-  if (c->n_heads < 1 || c->d_model != c->n_heads * kHeadDimHost)
-    return fail(FVAN_EUNSUPPORTED, "d_model / n_heads must be 16");
+  if (c->n_heads < 1 || c->d_model % c->n_heads != 0 ||
+      (c->d_model / c->n_heads != 16 && c->d_model / c->n_heads != 32 && c->d_model / c->n_heads != 64))
+    return fail(FVAN_EUNSUPPORTED, "d_model / n_heads must be 16, 32 or 64");
   if (c->d_token < 1 || c->d_token >= c->d_model) return fail(FVAN_EINVAL, "d_token out of range");
   if (c->vocab < 2 || c->vocab > 256) return fail(FVAN_EUNSUPPORTED, "vocab must be in [2, 256]");
   if (c->n_layers < 0 || c->n_layers > 64) return fail(FVAN_EINVAL, "n_layers out of range");
@@ -207,7 +208,22 @@ int fvan_sample(fvan_model* m, int32_t batch, uint64_t seed, uint64_t stream_id,
   if (batch < 1 || batch > m->cfg.max_batch) return fail(FVAN_EINVAL, "batch outside [1, max_batch]");
   DecodeUnit u = make_decode_unit(m, batch, seed, stream_id, spins, log_q, m->kv, 0);
   const int tiles = (batch + decode_tile_samples() - 1) / decode_tile_samples();
-  FVAN_HIP(launch_decode_single(m->cfg.d_model, m->cfg.precision, u, tiles, (hipStream_t)stream));
+  FVAN_HIP(launch_decode_single(decode_shape(m->cfg), u, tiles, (hipStream_t)stream));
+  FVAN_HIP(check_finite(m, log_q, batch, (hipStream_t)stream));
+  return FVAN_OK;
+}
+
+int fvan_sample_tokens(fvan_model* m, int32_t batch, uint64_t seed, uint64_t stream_id, uint8_t* tokens,
+                       float* log_q, void* stream) {
+  if (!m || !tokens || !log_q) return fail(FVAN_EINVAL, "NULL argument");
+  if (!has_sampler(m)) return fail(FVAN_EUNSUPPORTED, kNoSampler);
+  if (!m->params || !m->synced) return fail(FVAN_EINVAL, "parameters not bound/synced");
+  if (batch < 1 || batch > m->cfg.max_batch) return fail(FVAN_EINVAL, "batch outside [1, max_batch]");
+  DecodeShape sh = decode_shape(m->cfg);
+  sh.tokens = true;
+  DecodeUnit u = make_decode_unit(m, batch, seed, stream_id, reinterpret_cast<int8_t*>(tokens), log_q, m->kv, 0);
+  const int tiles = (batch + decode_tile_samples() - 1) / decode_tile_samples();
+  FVAN_HIP(launch_decode_single(sh, u, tiles, (hipStream_t)stream));
   FVAN_HIP(check_finite(m, log_q, batch, (hipStream_t)stream));
   return FVAN_OK;
 }
@@ -242,7 +258,6 @@ int fvan_reinforce_weights(int32_t batch, double beta, int32_t is_int, const voi
 
 int fvan_adam_step(fvan_model* m, const fvan_adam* opt, int64_t step, void* stream) {
   if (!m || !opt) return fail(FVAN_EINVAL, "NULL argument");
-  if (m->cfg.vocab != 2) return fail(FVAN_EUNSUPPORTED, kBinaryOnly);
   if (!has_teacher(m)) return fail(FVAN_EUNSUPPORTED, kNoTeacher);
   if (!m->params || !m->grads) return fail(FVAN_EINVAL, "parameters and gradients must be bound");
   if (step < 1) return fail(FVAN_EINVAL, "step counts from 1");
@@ -310,7 +325,6 @@ int fvan_newton_schulz(int32_t rows, int32_t cols, int32_t steps, float eps, con
 
 int fvan_muon_step(fvan_model* m, const fvan_muon* opt, int64_t step, void* stream) {
   if (!m || !opt) return fail(FVAN_EINVAL, "NULL argument");
-  if (m->cfg.vocab != 2) return fail(FVAN_EUNSUPPORTED, kBinaryOnly);
   if (!has_teacher(m)) return fail(FVAN_EUNSUPPORTED, kNoTeacher);
   if (!m->params || !m->grads) return fail(FVAN_EINVAL, "parameters and gradients must be bound");
   if (step < 1) return fail(FVAN_EINVAL, "step counts from 1");

@@ -21,6 +21,7 @@
 #include "passes.h"
 #include "row_kernels.h"
 #include "attn_mfma.h"
+#include "attn_generic.h"
 
 namespace fvan {
 
@@ -355,13 +356,14 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
   }
 }
 
-// grads: W[m][n] += sum_s part[s][m][n] for n < Nw; bias[m] += sum_s part[s][m][Nw].
+// grads: W[m][n] += sum_s part[s][m][n] for n < Nw; bias[m] += sum_s part[s][m][Nw]
+// (rows m >= m_valid are padding and not written).
 // A block owns 64 consecutive outputs; its four thread groups sum the slices
 // s = grp, grp + 4, ... (eight loads in flight each) and the four partial sums
 // are added in a fixed order: bitwise reproducible.
 constexpr int kRedOut = 64, kRedGroups = 4;
 __global__ __launch_bounds__(kRedOut * kRedGroups) void wgrad_reduce_kernel(const float* __restrict__ part, int S,
-                                                                            int M, int NB, int Nw,
+                                                                            int M, int NB, int Nw, int m_valid,
                                                                             float* __restrict__ gW,
                                                                             float* __restrict__ gb) {
   __shared__ float red[kRedGroups][kRedOut];
@@ -382,7 +384,7 @@ __global__ __launch_bounds__(kRedOut * kRedGroups) void wgrad_reduce_kernel(cons
   }
   red[grp][o] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   __syncthreads();
-  if (grp == 0 && i < total) {
+  if (grp == 0 && i < total && m < m_valid) {
     const float v = ((red[0][o] + red[1][o]) + red[2][o]) + red[3][o];
     if (n < Nw) gW[(size_t)m * Nw + n] += v;
     else gb[m] += v;
@@ -390,7 +392,8 @@ __global__ __launch_bounds__(kRedOut * kRedGroups) void wgrad_reduce_kernel(cons
 }
 
 template <int MODE, int M, int Nw>
-static hipError_t wgrad(fvan_model* m, const void* A, const void* B, int64_t K, float* gW, float* gb, hipStream_t s) {
+static hipError_t wgrad(fvan_model* m, const void* A, const void* B, int64_t K, float* gW, float* gb, hipStream_t s,
+                        int m_valid = M) {
   typedef typename Mode<MODE>::ActT AT;
   constexpr int NB = Nw + 16;
   auto& f = m->fw;
@@ -410,7 +413,7 @@ static hipError_t wgrad(fvan_model* m, const void* A, const void* B, int64_t K, 
                      f.ldT, (const AT*)B, f.ldT, K, kper, M, NB, M / MS, NB / NBS, f.part);
   const int total = M * (Nw + 1);
   hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((total + kRedOut - 1) / kRedOut), dim3(kRedOut * kRedGroups), 0, s,
-                     (const float*)f.part, S, M, NB, Nw, gW, gb);
+                     (const float*)f.part, S, M, NB, Nw, m_valid, gW, gb);
   return hipGetLastError();
 }
 
@@ -521,9 +524,140 @@ __global__ __launch_bounds__(256) void tok_grad_slices_kernel(const float* __res
         red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
 }
 
+// ---------------------------------------------------------------- vocab-way head (patch tokens)
+// One workgroup per sample, positions kHbPos at a time: z = W_h h + b, p =
+// softmax(z) and dz = w_b (onehot(tok) - p), the gradient of w_b ln p_t(tok_t)
+// (a token >= vocab makes its sample's dz NaN); dX = W_h^T dz, and dz written
+// feature-major into dZT [mrows][ldT] (rows v >= vocab zero) for the head's
+// weight-gradient GEMM.
+constexpr int kHbThreads = 256, kHbPos = 16;
+template <int D>
+__global__ __launch_bounds__(kHbThreads) void head_vocab_bwd_kernel(const float* __restrict__ X,
+                                                                    const float* __restrict__ theta, int64_t head_w,
+                                                                    int64_t head_b, int V, int mrows,
+                                                                    const uint8_t* __restrict__ tokens,
+                                                                    const float* __restrict__ w, int N,
+                                                                    float* __restrict__ dX, float* __restrict__ dZT,
+                                                                    int64_t ldT) {
+  constexpr int NW = kHbThreads / 64;
+  __shared__ __align__(16) float xs[kHbPos][D];
+  __shared__ float dzs[kHbPos][kHbThreads + 1];
+  __shared__ float wmax[kHbPos][NW], wsum[kHbPos][NW];
+  const int b = blockIdx.x, v = threadIdx.x, lane = v & 63, wave = v >> 6;
+  const bool live = v < V;
+  const float* wrow = theta + head_w + (int64_t)(live ? v : 0) * D;
+  const float bias = live ? theta[head_b + v] : 0.f;
+  const float wb = w[b];
+  for (int t0 = 0; t0 < N; t0 += kHbPos) {
+    const int np = min(kHbPos, N - t0);
+    const int64_t r0 = (int64_t)b * N + t0;
+    for (int i = v; i < kHbPos * D; i += kHbThreads) {
+      const int p = i / D, k = i % D;
+      xs[p][k] = p < np ? X[(r0 + p) * D + k] : 0.f;
+    }
+    __syncthreads();
+    float z[kHbPos];
+#pragma unroll
+    for (int p = 0; p < kHbPos; ++p) z[p] = -INFINITY;
+    if (live) {
+      float a[kHbPos];
+#pragma unroll
+      for (int p = 0; p < kHbPos; ++p) a[p] = 0.f;
+#pragma unroll 4
+      for (int k = 0; k < D; ++k) {
+        const float wk = wrow[k];
+#pragma unroll
+        for (int p = 0; p < kHbPos; ++p) a[p] += wk * xs[p][k];
+      }
+#pragma unroll
+      for (int p = 0; p < kHbPos; ++p) z[p] = a[p] + bias;
+    }
+    float mxs[kHbPos];
+#pragma unroll
+    for (int p = 0; p < kHbPos; ++p) {
+      float mm = z[p];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) mm = fmaxf(mm, __shfl_xor(mm, o, 64));
+      if (lane == 0) wmax[p][wave] = mm;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < kHbPos; ++p) {
+      float mx = wmax[p][0];
+#pragma unroll
+      for (int q = 1; q < NW; ++q) mx = fmaxf(mx, wmax[p][q]);
+      mxs[p] = mx;
+      z[p] = live ? expf(z[p] - mx) : 0.f;
+      float e = z[p];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+      if (lane == 0) wsum[p][wave] = e;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < kHbPos; ++p) {
+      float tot = 0.f;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) tot += wsum[p][q];
+      const int tk = p < np ? (int)tokens[r0 + p] : 0;
+      float dz = 0.f;
+      if (live) dz = tk < V ? wb * ((v == tk ? 1.f : 0.f) - z[p] / tot) : __builtin_nanf("");
+      dzs[p][v] = dz;
+      if (p < np && v < mrows) dZT[(int64_t)v * ldT + r0 + p] = dz;
+    }
+    __syncthreads();
+    for (int i = v; i < kHbPos * D; i += kHbThreads) {
+      const int p = i / D, k = i % D;
+      if (p < np) {
+        const float* wc = theta + head_w + k;
+        float acc = 0.f;
+        for (int vv = 0; vv < V; ++vv) acc += dzs[p][vv] * wc[(int64_t)vv * D];
+        dX[(r0 + p) * D + k] = acc;
+      }
+    }
+    __syncthreads();                                 // xs, dzs and the partials are rewritten next
+  }
+}
+
+// dT[tok][k] (k < dt) summed over the rows fed token tok (start token 0 at
+// t = 0): one wave per slice of `per` rows, walked in order, accumulating into
+// LDS [V][dt]; part[slice][V * dt] is then summed over the slices in a fixed
+// order (colsum_add).  Tokens >= vocab are clamped (their dX is NaN already).
+__global__ __launch_bounds__(64) void tok_grad_vocab_kernel(const float* __restrict__ dX,
+                                                            const uint8_t* __restrict__ tokens, int64_t rows, int N,
+                                                            int D, int dt, int V, int64_t per,
+                                                            float* __restrict__ part) {
+  extern __shared__ float acc[];                   // [V][dt]
+  for (int i = threadIdx.x; i < V * dt; i += 64) acc[i] = 0.f;
+  __syncthreads();
+  const int64_t r0 = (int64_t)blockIdx.x * per, r1 = std::min<int64_t>(rows, r0 + per);
+  for (int64_t r = r0; r < r1; ++r) {
+    const int tok = r % N == 0 ? 0 : min((int)tokens[r - 1], V - 1);
+    for (int k = threadIdx.x; k < dt; k += 64) acc[tok * dt + k] += dX[r * D + k];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < V * dt; i += 64) part[(size_t)blockIdx.x * V * dt + i] = acc[i];
+}
+
 // ---------------------------------------------------------------- driver
-template <int MODE, int D>
-static hipError_t backward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp, const float* w, hipStream_t s) {
+// Attention backward of one layer for heads wider than 16 (attn_generic.h).
+template <typename KT, typename AT, int DH>
+static hipError_t attn_bwd_gen(fvan_model* m, const KT* QKV, const float* X, const float* XM, const float* LSE,
+                               int nsamp, hipStream_t s) {
+  const fvan_model_config& c = m->cfg;
+  auto& f = m->fw;
+  const int N = c.n_spins, D = c.d_model, H = c.n_heads;
+  const int grid = (N + kGenRows - 1) / kGenRows * H * nsamp;
+  hipLaunchKernelGGL((attn_bwd_dq_gen<KT, AT, DH>), dim3(grid), dim3(kGenThreads), 0, s, QKV, X, XM,
+                     (const float*)f.dXM, LSE, f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window, m->kg.P);
+  hipLaunchKernelGGL((attn_bwd_dkv_gen<KT, AT, DH>), dim3(grid), dim3(kGenThreads), 0, s, QKV, (const float*)f.dXM,
+                     LSE, (const float*)f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window, m->kg.P);
+  return hipGetLastError();
+}
+
+// seq: spins (int8, TOK false) or patch tokens (uint8, TOK true) [nsamp, N].
+template <int MODE, int D, bool TOK>
+static hipError_t backward_chunk_t(fvan_model* m, const void* seq, int nsamp, const float* w, hipStream_t s) {
   typedef typename Mode<MODE>::ActT AT;
   typedef typename Mode<MODE>::KvT KT;
   const fvan_model_config& c = m->cfg;
@@ -532,14 +666,35 @@ static hipError_t backward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp
   const int64_t rows = (int64_t)nsamp * N;
   const int rgrid = (int)((rows + 63) / 64);
   float* G = m->grads;
-  hipError_t err = forward_chunk(m, spins, nsamp, nullptr, true, s);
+  const int8_t* spins = reinterpret_cast<const int8_t*>(seq);
+  const uint8_t* tokens = reinterpret_cast<const uint8_t*>(seq);
+  hipError_t err = TOK ? forward_chunk_tokens(m, tokens, nsamp, nullptr, s) : forward_chunk(m, spins, nsamp, nullptr, true, s);
   if (err != hipSuccess) return err;
 
   // head
-  hipLaunchKernelGGL((head_bwd_kernel<D>), dim3(nsamp), dim3(256), 0, s,
-                     (const float*)(f.X + (size_t)L * f.rows * D), m->params, m->po.head_w, m->po.head_b, spins, w, N,
-                     f.dX, f.colpart);
-  colsum_add(f.colpart, nsamp, 2 * D + 2, f.colpart2, G + m->po.head_w, s);
+  const float* XL = f.X + (size_t)L * f.rows * D;
+  if constexpr (TOK) {
+    const int mrows = c.vocab <= 16 ? 16 : 256;
+    hipLaunchKernelGGL((head_vocab_bwd_kernel<D>), dim3(nsamp), dim3(kHbThreads), 0, s, XL, m->params, m->po.head_w,
+                       m->po.head_b, c.vocab, mrows, tokens, w, N, f.dX, (float*)f.T_a, f.ldT);
+    hipLaunchKernelGGL((transpose_cast_kernel<D, AT>), dim3(rgrid), dim3(256), 0, s, XL, rows, (AT*)nullptr,
+                       (AT*)f.T_c, f.ldT);
+    if (mrows == 16) {
+      if ((err = wgrad<MODE, 16, D>(m, f.T_a, f.T_c, rows, G + m->po.head_w, G + m->po.head_b, s, c.vocab)))
+        return err;
+    } else {
+      if constexpr (4 * D >= 256) {
+        if ((err = wgrad<MODE, 256, D>(m, f.T_a, f.T_c, rows, G + m->po.head_w, G + m->po.head_b, s, c.vocab)))
+          return err;
+      } else {
+        return hipErrorInvalidValue;
+      }
+    }
+  } else {
+    hipLaunchKernelGGL((head_bwd_kernel<D>), dim3(nsamp), dim3(256), 0, s, XL, m->params, m->po.head_w, m->po.head_b,
+                       spins, w, N, f.dX, f.colpart);
+    colsum_add(f.colpart, nsamp, 2 * D + 2, f.colpart2, G + m->po.head_w, s);
+  }
 
   for (int l = L - 1; l >= 0; --l) {
     const float* lp = m->params + m->po.layer0 + (int64_t)l * m->po.layer_stride;
@@ -583,14 +738,21 @@ static hipError_t backward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp
     colsum_add(f.colpart, rgrid, 2 * D, f.colpart2, gl + m->po.ln2_g, s);
     // ---- attention backward (dO = dXM: the heads' output is added to the residual directly);
     // probabilities are recomputed from Q, K and the saved log-sum-exp
-    hipLaunchKernelGGL((attn_bwd_dq_mfma<KT, AT, MODE>), dim3((N + attn_rows(kDqThreads) - 1) / attn_rows(kDqThreads) * H * nsamp),
-                       dim3(kDqThreads), 0, s, QKV, X,
-                       XM, (const float*)f.dXM, LSE, f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window,
-                       m->kg.P);
-    hipLaunchKernelGGL((attn_bwd_dkv_mfma<KT, AT, MODE>), dim3((N + attn_rows(kDkvThreads) - 1) / attn_rows(kDkvThreads) * H * nsamp),
-                       dim3(kDkvThreads), 0, s, QKV,
-                       (const float*)f.dXM, LSE, (const float*)f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H,
-                       c.window, m->kg.P);
+    if (D / H == 16) {
+      hipLaunchKernelGGL((attn_bwd_dq_mfma<KT, AT, MODE>), dim3((N + attn_rows(kDqThreads) - 1) / attn_rows(kDqThreads) * H * nsamp),
+                         dim3(kDqThreads), 0, s, QKV, X,
+                         XM, (const float*)f.dXM, LSE, f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window,
+                         m->kg.P);
+      hipLaunchKernelGGL((attn_bwd_dkv_mfma<KT, AT, MODE>), dim3((N + attn_rows(kDkvThreads) - 1) / attn_rows(kDkvThreads) * H * nsamp),
+                         dim3(kDkvThreads), 0, s, QKV,
+                         (const float*)f.dXM, LSE, (const float*)f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H,
+                         c.window, m->kg.P);
+    } else if (D / H == 32) {
+      if ((err = attn_bwd_gen<KT, AT, 32>(m, QKV, X, XM, LSE, nsamp, s))) return err;
+    } else {
+      if constexpr (D >= 64)
+        if ((err = attn_bwd_gen<KT, AT, 64>(m, QKV, X, XM, LSE, nsamp, s))) return err;
+    }
     // ---- QKV backward
     hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(rgrid), dim3(256), 0, s, X, rows, lp + m->po.ln1_g,
                        lp + m->po.ln1_b, (AT*)nullptr, (AT*)f.T_c, f.ldT);
@@ -606,16 +768,38 @@ static hipError_t backward_chunk_t(fvan_model* m, const int8_t* spins, int nsamp
   const int64_t npos = (int64_t)N * (D - c.d_token);
   hipLaunchKernelGGL(pos_grad_kernel, dim3((int)std::min<int64_t>((npos + 255) / 256, 4096)), dim3(256), 0, s,
                      (const float*)f.dX, nsamp, N, D, c.d_token, G + m->po.pos);
-  hipLaunchKernelGGL(tok_grad_slices_kernel, dim3(kColSlices, c.d_token), dim3(256), 0, s, (const float*)f.dX, spins,
-                     rows, N, D, c.d_token, f.part);
-  hipLaunchKernelGGL(colsum_final_kernel, dim3((2 * c.d_token + 255) / 256), dim3(256), 0, s, (const float*)f.part,
-                     2 * c.d_token, G + m->po.tok);
+  if constexpr (TOK) {
+    const int width = c.vocab * c.d_token;
+    int S = (int)std::max<int64_t>(1, std::min<int64_t>(1024, rows / 64));
+    while ((size_t)S * width > f.part_floats) --S;
+    const int64_t per = (rows + S - 1) / S;
+    S = (int)((rows + per - 1) / per);
+    hipLaunchKernelGGL(tok_grad_vocab_kernel, dim3(S), dim3(64), (size_t)width * sizeof(float), s,
+                       (const float*)f.dX, tokens, rows, N, D, c.d_token, c.vocab, per, f.part);
+    colsum_add(f.part, S, width, f.colpart2, G + m->po.tok, s);
+  } else {
+    hipLaunchKernelGGL(tok_grad_slices_kernel, dim3(kColSlices, c.d_token), dim3(256), 0, s, (const float*)f.dX, spins,
+                       rows, N, D, c.d_token, f.part);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3((2 * c.d_token + 255) / 256), dim3(256), 0, s, (const float*)f.part,
+                       2 * c.d_token, G + m->po.tok);
+  }
   return hipGetLastError();
 }
 
 hipError_t backward_chunk(fvan_model* m, const int8_t* spins, int nsamp, const float* w, hipStream_t s) {
   const int D = m->cfg.d_model;
-#define BWD_CASE(MODE, DD) if (m->cfg.precision == MODE && D == DD) return backward_chunk_t<MODE, DD>(m, spins, nsamp, w, s);
+#define BWD_CASE(MODE, DD) \
+  if (m->cfg.precision == MODE && D == DD) return backward_chunk_t<MODE, DD, false>(m, spins, nsamp, w, s);
+  BWD_CASE(0, 32) BWD_CASE(0, 64) BWD_CASE(0, 128)
+  BWD_CASE(2, 32) BWD_CASE(2, 64) BWD_CASE(2, 128)
+#undef BWD_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t backward_chunk_tokens(fvan_model* m, const uint8_t* tokens, int nsamp, const float* w, hipStream_t s) {
+  const int D = m->cfg.d_model;
+#define BWD_CASE(MODE, DD) \
+  if (m->cfg.precision == MODE && D == DD) return backward_chunk_t<MODE, DD, true>(m, tokens, nsamp, w, s);
   BWD_CASE(0, 32) BWD_CASE(0, 64) BWD_CASE(0, 128)
   BWD_CASE(2, 32) BWD_CASE(2, 64) BWD_CASE(2, 128)
 #undef BWD_CASE

@@ -11,7 +11,6 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 
 constexpr int kWave = 64;
 constexpr float kLnEps = 1e-5f;
-constexpr int kHeadDim = 16;
 
 typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
 

@@ -16,6 +16,7 @@
 #include "passes.h"
 #include "row_kernels.h"
 #include "attn_mfma.h"
+#include "attn_generic.h"
 
 namespace fvan {
 
@@ -202,10 +203,20 @@ hipError_t forward_layer(fvan_model* m, int l, int64_t rows, int nsamp, hipStrea
   e.ln_b = lp + m->po.ln1_b;
   hipError_t err = gemm_rows<MODE, D, 3 * D, EPI_STORE_KV>(nullptr, rows, wl + m->pk.qkv, e, s);
   if (err != hipSuccess) return err;
-  const int H = c.n_heads;
-  hipLaunchKernelGGL((attn_fwd_mfma<KT, MODE>), dim3((c.n_spins + attn_rows(kFwdThreads) - 1) / attn_rows(kFwdThreads) * H * nsamp),
-                     dim3(kFwdThreads), 0, s,
-                     (const KT*)QKV, X, XM, LSE, c.n_spins, D, H, c.window, m->kg.P);
+  const int H = c.n_heads, dh = D / H;
+  const int ggrid = (c.n_spins + kGenRows - 1) / kGenRows * H * nsamp;
+  if (dh == 16) {
+    hipLaunchKernelGGL((attn_fwd_mfma<KT, MODE>), dim3((c.n_spins + attn_rows(kFwdThreads) - 1) / attn_rows(kFwdThreads) * H * nsamp),
+                       dim3(kFwdThreads), 0, s,
+                       (const KT*)QKV, X, XM, LSE, c.n_spins, D, H, c.window, m->kg.P);
+  } else if (dh == 32) {
+    hipLaunchKernelGGL((attn_fwd_gen<KT, 32>), dim3(ggrid), dim3(kGenThreads), 0, s, (const KT*)QKV, X, XM, LSE,
+                       c.n_spins, D, H, c.window, m->kg.P);
+  } else {
+    if constexpr (D >= 64)
+      hipLaunchKernelGGL((attn_fwd_gen<KT, 64>), dim3(ggrid), dim3(kGenThreads), 0, s, (const KT*)QKV, X, XM, LSE,
+                         c.n_spins, D, H, c.window, m->kg.P);
+  }
   hipLaunchKernelGGL((ffn_fused_kernel<MODE, D>), dim3((int)((rows + kFfnRows - 1) / kFfnRows)), dim3(256), 0, s,
                      (const float*)XM, lp + m->po.ln2_g, lp + m->po.ln2_b, rows,
                      reinterpret_cast<const uint4*>(wl + m->pk.ffn1), reinterpret_cast<const uint4*>(wl + m->pk.ffn2),
@@ -244,9 +255,10 @@ static hipError_t forward_chunk_tokens_t(fvan_model* m, const uint8_t* tokens, i
     hipError_t e = forward_layer<MODE, D>(m, l, rows, nsamp, s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((head_vocab_kernel<D>), dim3(nsamp), dim3(kHeadVocabThreads), 0, s,
-                     (const float*)(m->fw.X + (size_t)c.n_layers * m->fw.rows * D), m->params, m->po.head_w,
-                     m->po.head_b, c.vocab, tokens, c.n_spins, logq);
+  if (logq)
+    hipLaunchKernelGGL((head_vocab_kernel<D>), dim3(nsamp), dim3(kHeadVocabThreads), 0, s,
+                       (const float*)(m->fw.X + (size_t)c.n_layers * m->fw.rows * D), m->params, m->po.head_w,
+                       m->po.head_b, c.vocab, tokens, c.n_spins, logq);
   return hipGetLastError();
 }
 

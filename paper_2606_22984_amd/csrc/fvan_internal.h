@@ -73,10 +73,22 @@ struct DecodeUnit {
   int32_t o_ln1_g, o_ln1_b, o_qkv_b, o_ln2_g, o_ln2_b, o_ffn1_b, o_ffn2_b;
   int64_t p_qkv, p_ffn1, p_ffn2, p_layer_stride;   // pack byte offsets
   int32_t d_token;
+  int32_t vocab;       // 2: spins; > 2: patch tokens (uint8 written to `spins`)
 };
 
+// Which decode kernel a model needs.
+struct DecodeShape {
+  int d_model, precision, d_head;
+  bool tokens;         // vocab-way head and token draw
+};
+inline DecodeShape decode_shape(const fvan_model_config& c) {
+  return DecodeShape{c.d_model, c.precision, c.d_model / c.n_heads, c.vocab > 2};
+}
+
 // Messages of the entry points a model's configuration does not provide.
-constexpr const char* kBinaryOnly = "a model over patch tokens (vocab > 2) supports only fvan_log_prob_tokens";
+constexpr const char* kBinaryOnly =
+    "a model over patch tokens (vocab > 2) takes the token calls (fvan_sample_tokens, fvan_log_prob_tokens, "
+    "fvan_log_prob_tokens_backward, fvan_train_step_tokens)";
 constexpr const char* kNoSampler = "the model was created without FVAN_WS_SAMPLER (no KV cache)";
 constexpr const char* kNoTeacher = "the model was created without FVAN_WS_TEACHER (no teacher-forced workspace)";
 constexpr const char* kNoTrain = "a training step needs FVAN_WS_SAMPLER | FVAN_WS_TEACHER";
@@ -92,8 +104,8 @@ int fail(int code, const std::string& msg);
   } while (0)
 
 // ----- launchers (return hipError_t of the launch) -----
-hipError_t launch_decode(int d_model, int precision, const DecodeUnit* units_dev, int n_units,
-                         int total_tiles, int* queue_counter, int grid, hipStream_t s);
+hipError_t launch_decode(const DecodeShape& sh, const DecodeUnit* units_dev, int n_units, int total_tiles,
+                         int* queue_counter, int grid, hipStream_t s);
 int decode_tile_samples();
 
 hipError_t launch_energy(const fvan_couplings& c, int32_t batch, const int8_t* spins, void* energy,
@@ -131,5 +143,13 @@ hipError_t launch_grad_norm(const float* g, int64_t n, double* out, double* scra
 hipError_t launch_mean_energy(int32_t batch, int32_t n, int is_int, const void* energy, double* out,
                               hipStream_t s);
 hipError_t launch_zero_int(int* p, int n, hipStream_t s);
+hipError_t launch_tokens_to_spins(int32_t T, int32_t bits, const int32_t* sites, int32_t n, int32_t batch,
+                                  const uint8_t* tokens, int8_t* spins, hipStream_t s);
+// Bits per patch token of a vocabulary (log2 vocab), 0 when vocab is not a power of two above 2.
+inline int token_bits(int vocab) {
+  for (int b = 2; b <= 8; ++b)
+    if (vocab == (1 << b)) return b;
+  return 0;
+}
 
 }  // namespace fvan

@@ -3,7 +3,6 @@
 
 #include "fvan_internal.h"
 
-constexpr int kHeadDimHost = 16;
 
 struct fvan_model {
   fvan_model_config cfg{};
@@ -27,7 +26,8 @@ struct fvan_model {
   float* adam_m = nullptr;
   float* adam_v = nullptr;
   // train-step buffers
-  int8_t* ts_spins = nullptr;   // [max_batch, N]
+  int8_t* ts_spins = nullptr;   // [max_batch, N] (spins, or the tokens of a patch-token model)
+  int8_t* ts_lattice = nullptr; // patch-token models: [max_batch, N * log2(vocab)] spins of the sampled tokens
   float* ts_logq = nullptr;     // [max_batch]
   void* ts_energy = nullptr;    // [max_batch] int32 or float
   float* ts_w = nullptr;        // [max_batch] REINFORCE weights
@@ -72,5 +72,5 @@ DecodeUnit make_decode_unit(const fvan_model* m, int32_t batch, uint64_t seed, u
 // Resolve (once per device; `dev` must be current) the device address of the
 // static KV cache fvan_sample_noalloc uses.
 int static_kv_setup(int dev);
-hipError_t launch_decode_single(int d_model, int precision, const DecodeUnit& u, int tiles, hipStream_t s);
+hipError_t launch_decode_single(const DecodeShape& sh, const DecodeUnit& u, int tiles, hipStream_t s);
 }  // namespace fvan

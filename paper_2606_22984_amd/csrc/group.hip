@@ -134,6 +134,7 @@ __global__ __launch_bounds__(256) void group_stats_kernel(const GroupStatUnit* _
 
 struct fvan_group {
   int d_model = 0, precision = 0, n_layers = 0;
+  fvan::DecodeShape shape{};
   int n_units = 0, total_tiles = 0, grid = 0, device = 0;
   std::vector<fvan_group_unit> units;
   std::vector<fvan_couplings> coup;
@@ -159,7 +160,7 @@ static std::map<std::tuple<int, int, int, int>, int>& tuned_grids() {
 static hipError_t group_sample(fvan_group* g, int grid, hipStream_t s) {
   hipError_t e = launch_zero_int(g->d_queue, 1, s);
   if (e != hipSuccess) return e;
-  return launch_decode(g->d_model, g->precision, g->d_table, g->n_units, g->total_tiles, g->d_queue, grid, s);
+  return launch_decode(g->shape, g->d_table, g->n_units, g->total_tiles, g->d_queue, grid, s);
 }
 
 static int group_run_impl(fvan_group* g, hipStream_t s) {
@@ -257,6 +258,7 @@ int fvan_group_create(const fvan_group_unit* units, int32_t n_units, int32_t til
   g->d_model = m0->cfg.d_model;
   g->precision = m0->cfg.precision;
   g->n_layers = m0->cfg.n_layers;
+  g->shape = decode_shape(m0->cfg);
   g->n_units = n_units;
   g->device = m0->device;
   g->units.assign(units, units + n_units);

@@ -58,7 +58,8 @@ static int allocate_fwd(fvan_model* m, hipStream_t s) {
       {&f.T_a, 4 * D * ldT * 4, "T_a"},
       {&f.T_b, (4 * D + 16) * ldT * 4, "T_b"},            {&f.T_c, (D + 16) * ldT * 4, "T_c"},
       {(void**)&f.part, f.part_floats * 4, "partials"},   {(void**)&f.colpart, f.colpart_floats * 4, "column partials"},
-      {(void**)&f.colpart2, (size_t)64 * (2 * D + 2) * 4, "column slices"},
+      {(void**)&f.colpart2, (size_t)64 * std::max<size_t>(2 * D + 2, (size_t)c.vocab * c.d_token) * 4,
+       "column slices"},
   };
   for (auto& a : allocs) {
     int rc = dalloc(a.p, std::max<size_t>(a.bytes, 16), a.what);
@@ -109,6 +110,9 @@ int model_allocate(fvan_model* m) {
     if ((rc = dalloc(&m->ts_energy, B * 4, "train-step energies"))) return rc;
     if ((rc = dalloc(&m->ts_w, B * 4, "train-step weights"))) return rc;
     if ((rc = dalloc(&m->ts_dbl, 64 * 8, "FP64 scratch"))) return rc;
+    if (token_bits(c.vocab) &&
+        (rc = dalloc(&m->ts_lattice, B * c.n_spins * token_bits(c.vocab), "train-step lattice spins")))
+      return rc;
   }
   // initialisation on the null stream, waited for here: create is the one call
   // that may block
@@ -130,7 +134,7 @@ static void dfree(void* p) {
 
 void model_free(fvan_model* m) {
   dfree(m->wpack); dfree(m->kv); dfree(m->adam_m); dfree(m->adam_v);
-  dfree(m->ts_spins); dfree(m->ts_logq); dfree(m->ts_energy); dfree(m->ts_w); dfree(m->ts_dbl);
+  dfree(m->ts_spins); dfree(m->ts_lattice); dfree(m->ts_logq); dfree(m->ts_energy); dfree(m->ts_w); dfree(m->ts_dbl);
   dfree(m->nf_flag);
   if (m->nf_host) (void)hipHostFree(m->nf_host);
   if (m->nf_event) (void)hipEventDestroy(m->nf_event);
@@ -205,6 +209,7 @@ DecodeUnit make_decode_unit(const fvan_model* m, int32_t batch, uint64_t seed, u
   u.p_ffn2 = (int64_t)m->pk.ffn2;
   u.p_layer_stride = (int64_t)m->pk.layer_stride;
   u.d_token = c.d_token;
+  u.vocab = c.vocab;
   return u;
 }
 

@@ -74,10 +74,14 @@ template <int MODE> struct Epi<MODE, EPI_F32> {
 hipError_t forward_chunk(fvan_model* m, const int8_t* spins, int nsamp, float* logq, bool for_backward,
                          hipStream_t s);
 // The same forward for a model over patch tokens (vocab >= 2): tokens [nsamp, N]
-// in [0, vocab), a vocab-way head; logq (not NULL): per-sample ln q.
+// in [0, vocab), a vocab-way head; logq: per-sample ln q (NULL: the head is not
+// evaluated, as before a backward pass).
 hipError_t forward_chunk_tokens(fvan_model* m, const uint8_t* tokens, int nsamp, float* logq, hipStream_t s);
 // grads += sum_b w[b] d ln q_b / d theta for one chunk (recomputes the forward).
 hipError_t backward_chunk(fvan_model* m, const int8_t* spins, int nsamp, const float* w, hipStream_t s);
+// The same for a model over patch tokens (uint8 [nsamp, N]); needs vocab <= 16
+// or d_model >= 64 (the head's dz is staged in a [4 d_model]-row buffer).
+hipError_t backward_chunk_tokens(fvan_model* m, const uint8_t* tokens, int nsamp, const float* w, hipStream_t s);
 // Enqueue a check of n floats / doubles: the model's non-finite flag is set if
 // any is NaN or Inf.
 hipError_t check_finite(fvan_model* m, const float* v, int64_t n, hipStream_t s);

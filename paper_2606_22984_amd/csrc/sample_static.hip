@@ -73,7 +73,7 @@ extern "C" int fvan_sample_noalloc(fvan_model* m, int32_t batch, uint64_t seed, 
   if (int rc = scratch_address(dev, &kv)) return rc;
   DecodeUnit u = make_decode_unit(m, batch, seed, stream_id, spins, log_q, kv, 0);
   const int tiles = (batch + decode_tile_samples() - 1) / decode_tile_samples();
-  FVAN_HIP(launch_decode_single(m->cfg.d_model, m->cfg.precision, u, tiles, (hipStream_t)stream));
+  FVAN_HIP(launch_decode_single(decode_shape(m->cfg), u, tiles, (hipStream_t)stream));
   FVAN_HIP(check_finite(m, log_q, batch, (hipStream_t)stream));
   return FVAN_OK;
 }

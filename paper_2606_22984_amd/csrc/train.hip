@@ -84,6 +84,26 @@ int fvan_log_prob_backward(fvan_model* m, int32_t batch, const int8_t* spins, co
   return FVAN_OK;
 }
 
+int fvan_log_prob_tokens_backward(fvan_model* m, int32_t batch, const uint8_t* tokens, const float* grad_log_q,
+                                  void* stream) {
+  if (!m || !tokens || !grad_log_q) return fail(FVAN_EINVAL, "NULL argument");
+  if (!m->params || !m->synced) return fail(FVAN_EINVAL, "parameters not bound/synced");
+  if (!m->grads) return fail(FVAN_EINVAL, "no gradient buffer bound");
+  if (!has_teacher(m)) return fail(FVAN_EUNSUPPORTED, kNoTeacher);
+  if (batch < 1 || batch > m->cfg.max_batch) return fail(FVAN_EINVAL, "batch outside [1, max_batch]");
+  if (m->cfg.vocab > 16 && m->cfg.d_model < 64)
+    return fail(FVAN_EUNSUPPORTED, "the token backward needs vocab <= 16 or d_model >= 64");
+  if (m->cfg.vocab * m->cfg.d_token > 16384) return fail(FVAN_EUNSUPPORTED, "vocab * d_token must be <= 16384");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t N = m->cfg.n_spins;
+  for (int64_t b0 = 0; b0 < batch; b0 += m->fw.chunk) {
+    const int nb = (int)std::min<int64_t>(m->fw.chunk, batch - b0);
+    FVAN_HIP(backward_chunk_tokens(m, tokens + b0 * N, nb, grad_log_q + b0, s));
+  }
+  FVAN_HIP(check_finite(m, m->grads, m->n_params, s));
+  return FVAN_OK;
+}
+
 // Everything of a training step before the update: sample, energies, F_q
 // statistics, REINFORCE weights, backward and the gradient norm.
 static int train_step_gradient(fvan_model* m, const fvan_couplings* c, double beta, int32_t batch, uint64_t seed,
@@ -165,6 +185,35 @@ int fvan_model_status(fvan_model* m, void* stream) {
     return fail(FVAN_ENONFINITE, "a kernel of this model produced a non-finite value");
   }
   return FVAN_OK;
+}
+
+int fvan_train_step_tokens(fvan_model* m, const fvan_couplings* c, const int32_t* sites, double beta, int32_t batch,
+                           uint64_t seed, uint64_t step, const fvan_muon* opt, double* stats, void* stream) {
+  if (!m || !c || !sites || !opt || !stats) return fail(FVAN_EINVAL, "NULL argument");
+  if (const char* why = check_muon(*opt)) return fail(FVAN_EINVAL, why);
+  const int bits = token_bits(m->cfg.vocab);
+  if (!bits) return fail(FVAN_EUNSUPPORTED, "a patch-token training step needs vocab = 2^bits, bits in [2, 8]");
+  const int32_t n = m->cfg.n_spins * bits;
+  if (c->n_spins != n) return fail(FVAN_EINVAL, "couplings must cover n_spins * log2(vocab) lattice sites");
+  if (!(beta > 0.0) || !std::isfinite(beta)) return fail(FVAN_EINVAL, "beta must be finite and > 0");
+  if (step < 1) return fail(FVAN_EINVAL, "step counts from 1");
+  if (!m->params || !m->grads) return fail(FVAN_EINVAL, "parameters and gradients must be bound");
+  if (!has_sampler(m) || !has_teacher(m)) return fail(FVAN_EUNSUPPORTED, kNoTrain);
+  hipStream_t s = (hipStream_t)stream;
+  int rc = previous_step_status(m);
+  if (rc) return rc;
+  uint8_t* tok = reinterpret_cast<uint8_t*>(m->ts_spins);
+  if ((rc = fvan_sample_tokens(m, batch, seed, step, tok, m->ts_logq, stream))) return rc;
+  FVAN_HIP(launch_tokens_to_spins(m->cfg.n_spins, bits, sites, n, batch, tok, m->ts_lattice, s));
+  if ((rc = fvan_energy(c, batch, m->ts_lattice, m->ts_energy, stream))) return rc;
+  const int is_int = c->kind == FVAN_BONDS_PM1;
+  if ((rc = fvan_free_energy(batch, n, beta, is_int, m->ts_energy, m->ts_logq, stats, stream))) return rc;
+  FVAN_HIP(launch_mean_energy(batch, n, is_int, m->ts_energy, stats + 2, s));
+  FVAN_HIP(launch_reinforce(batch, beta, is_int, m->ts_energy, m->ts_logq, m->ts_w, nullptr, s));
+  if ((rc = fvan_log_prob_tokens_backward(m, batch, tok, m->ts_w, stream))) return rc;
+  FVAN_HIP(launch_grad_norm(m->grads, m->n_params, stats + 3, nullptr, s));
+  if ((rc = fvan_muon_step(m, opt, (int64_t)step, stream))) return rc;
+  return finish_step(m, stats, s);
 }
 
 int fvan_train_step_muon(fvan_model* m, const fvan_couplings* c, double beta, int32_t batch, uint64_t seed,

@@ -149,3 +149,27 @@ def test_patch_graph_of_the_inputs_by_brute_force(L, D):
     got = list(zip(pi.tolist(), pj.tolist()))
     assert len(got) == len(set(got)) and set(got) == want
     assert all(a < b for a, b in got)
+
+
+def test_token_gradient_by_central_differences():
+    """The patched model's reverse-mode gradient of sum_b c_b ln q(tok_b) against
+    central differences of the same FP64 sum on coordinates spread over every
+    parameter block (token table, positions, every layer, head)."""
+    cfg = ModelConfig(6, 32, 2, 2, vocab=16).with_mask(2, 1)
+    theta = init_params(cfg, 4, "random")
+    rng = np.random.default_rng(2)
+    tok = rng.integers(0, 16, size=(5, 6))
+    c = rng.standard_normal(5)
+    g = patch.grad_surrogate_tokens(theta, cfg, tok, c)
+
+    def f(th):
+        return float(np.dot(c, patch.log_q_tokens(th, cfg, tok)))
+
+    idx = np.unique(np.concatenate([rng.integers(0, theta.size, 40), [0, 5, 31, theta.size - 1, theta.size - 20]]))
+    h = 1e-6
+    for i in idx:
+        tp, tm = theta.astype(np.float64).copy(), theta.astype(np.float64).copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (f(tp) - f(tm)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
