@@ -56,58 +56,75 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def patched(args, wl, cfg, theta, B):
-    """Teacher-forced ln q over 2^D patch tokens (the paper's EA models) at the 3D
-    workload's model size, in split and FP32 mode, beside the single-spin pass."""
+# The paper's patched 3D EA L=10 model (SI, 3D EA settings): 2x2x2 patches, so
+# 125 positions over a vocabulary of 256; d_token 32 + d_pos 96 = d_model 128,
+# 2 heads, 2 layers, batch 2048; 0.179 s per training step on one H100.
+PATCHED_3D = dict(L=10, D=3, d_model=128, d_token=32, n_heads=2, n_layers=2, batch=2048, paper_step_s=0.179)
+
+
+def patched(args):
+    """Training step of the paper's patched 3D EA L=10 model (sample tokens ->
+    spins -> energies -> F_q -> REINFORCE weights -> token backward -> Muon), in
+    split and FP32 mode, beside the paper's step time for the same workload."""
     import numpy as np
     import torch
 
     import paper_2606_22984_amd as fv
-    from workloads import ModelConfig, init_params
-    from workloads.instances import patch_edges, random_spins
+    from workloads import ModelConfig, ea_instance, init_params, workload
+    from workloads.instances import patch_edges
 
-    T, pi, pj = patch_edges(wl.size, wl.dim)
+    pc = PATCHED_3D
+    wl = workload("ea3d_L10")
+    inst = ea_instance(pc["L"], pc["D"], wl.instance_seed, wl.bonds)
+    T, pi, pj = patch_edges(pc["L"], pc["D"])
     W, P = fv.derive_mask(T, pi, pj)
-    pcfg = ModelConfig(T, cfg.d_model, cfg.n_layers, cfg.n_heads, vocab=2 ** (2 ** wl.dim)).with_mask(W, P)
-    ptheta = init_params(pcfg, wl.param_seed, "default")
-    tok = torch.as_tensor(np.random.default_rng(7).integers(0, pcfg.vocab, size=(B, T)).astype(np.uint8),
-                          device="cuda")
-    spins = torch.as_tensor(random_spins(B, cfg.n_spins, 7), device="cuda")
+    cfg = ModelConfig(T, pc["d_model"], pc["n_layers"], pc["n_heads"], d_token=pc["d_token"],
+                      vocab=2 ** (2 ** pc["D"])).with_mask(W, P)
+    theta = init_params(cfg, wl.param_seed, "default")
+    coup = fv.couplings(inst)
+    sites = torch.as_tensor(fv.patch_sites(pc["L"], pc["D"]), device="cuda")
+    B, beta, seed = pc["batch"], 1.0, 12345
     stream = torch.cuda.current_stream()
-
-    def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(args.steps):
-            fn()
-        b.record(stream)
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / args.steps
-
     out = {}
     for name, prec in (("bf16split", fv.FVAN_BF16_SPLIT), ("fp32", fv.FVAN_FP32)):
-        mp = fv.Model(pcfg, B, prec, ptheta)
+        m = fv.Model(cfg, B, prec, theta)
+        stats = torch.zeros(4, dtype=torch.float64, device="cuda")
+        for k in range(1, args.warmup + 1):
+            m.train_step_tokens(coup, sites, beta, B, seed, k, stats, lr=warmup_lr(k), adam_lr=warmup_lr(k))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.warmup + 1, args.warmup + args.steps + 1):
+            m.train_step_tokens(coup, sites, beta, B, seed, k, stats, lr=warmup_lr(k), adam_lr=warmup_lr(k))
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        # sampling alone, timed on the stream it runs on
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tok = torch.empty(B, T, dtype=torch.uint8, device="cuda")
         lq = torch.empty(B, dtype=torch.float32, device="cuda")
-        ms_p = timed(lambda: mp.log_prob_tokens(tok, lq))
-        del mp
-        ms_s = None
-        if name == "bf16split":
-            ms_ = fv.Model(cfg, B, prec, theta)
-            ms_s = timed(lambda: ms_.log_prob(spins, lq))
-            del ms_
-        out[name] = {"patched_ms": round(ms_p, 3), "patched_sequences_per_s": round(B / (ms_p * 1e-3), 1),
-                     "single_spin_ms": None if ms_s is None else round(ms_s, 3)}
-        print(f"[bench] patched ln q, {name}: {ms_p:.2f} ms per batch", file=sys.stderr, flush=True)
+        m.sample_tokens(B, seed, 1, tok, lq)
+        a.record(stream)
+        m.sample_tokens(B, seed, 2, tok, lq)
+        b.record(stream)
+        torch.cuda.synchronize()
+        st = stats.cpu().numpy()
+        m.status()
+        m.close()
+        out[name] = {"ms_per_step": round(ms, 3), "samples_per_s": round(B / (ms * 1e-3), 1),
+                     "sample_ms": round(a.elapsed_time(b), 3), "F_per_site": float(st[0])}
+        progress(f"patched 3D step, {name}: {ms:.2f} ms per step")
     s = out["bf16split"]
-    return {"metric": "teacher-forced ln q of one batch over patch tokens", "value": s["patched_ms"], "unit": "ms",
-            "higher_is_better": False, "n_gpus": 1, "steps": args.steps, "dtype": "bf16-split-mfma+fp16-kv",
-            "data": "synthetic: seeded random tokens and random-init parameters",
-            "config": {"workload": f"3D EA L={wl.size} in 2x2x2 patches: {T} positions, vocabulary {pcfg.vocab}, "
-                                   f"d_model={cfg.d_model}, {cfg.n_layers} layers, {cfg.n_heads} heads, batch {B}, "
-                                   f"mask W={W} P={P}"},
-            "precisions": out, "speedup_vs_single_spin_pass": round(s["single_spin_ms"] / s["patched_ms"], 2)}
+    return {"metric": "training-step time, patched 3D EA L=10 (the paper's model and batch)",
+            "value": s["ms_per_step"], "unit": "ms", "higher_is_better": False, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "dtype": "bf16-split-mfma+fp16-kv",
+            "data": "synthetic: seeded Gaussian 3D EA instance and seeded random-init parameters",
+            "config": {"workload": f"3D EA L={pc['L']} PBC, Gaussian J, 2x2x2 patches: {T} positions, vocabulary "
+                                   f"{cfg.vocab}, d_model={cfg.d_model} (d_token {cfg.d_token}), "
+                                   f"{cfg.n_layers} layers, {cfg.n_heads} heads, batch {B}, mask W={W} P={P}, "
+                                   "REINFORCE + Muon"},
+            "paper_step_ms": 1e3 * pc["paper_step_s"],
+            "paper_hardware": "one NVIDIA H100 80GB, PyTorch 2.8 + FlashAttention-2, FP16 attention",
+            "speedup_vs_paper": round(1e3 * pc["paper_step_s"] / s["ms_per_step"], 2),
+            "precisions": out}
 
 
 def main():
@@ -130,8 +147,8 @@ def main():
                     help="time the overlap histogram of the 3D EA batch (16384 sampled configurations of 1000 "
                          "spins, all pairs) instead")
     ap.add_argument("--patched", action="store_true",
-                    help="time the teacher-forced ln q of the 3D EA model over 2x2x2 patch tokens (125 positions, "
-                         "vocabulary 256, batch 16384) instead, beside the single-spin pass over 1000 positions")
+                    help="time the training step of the paper's patched 3D EA L=10 model instead (2x2x2 patches: "
+                         "125 positions, vocabulary 256, d_model 128, 2 heads, 2 layers, batch 2048)")
     ap.add_argument("--lmc-sweeps", type=int, default=10)
     ap.add_argument("--w", type=float, default=0.1)
     ap.add_argument("--profile-decode", action="store_true",
@@ -199,7 +216,7 @@ def main():
         print(json.dumps(distill(args, cfg, theta, inst, coup, B, beta, seed, N)))
         return
     if args.patched:
-        print(json.dumps(patched(args, wl, cfg, theta, B)))
+        print(json.dumps(patched(args)))
         return
 
     def run(prec, steps, warmup):
