@@ -355,7 +355,8 @@ def batched(args):
     t0 = time.perf_counter()
     g = fv.Group(units)
     torch.cuda.synchronize()
-    progress(f"batched: group created and autotuned in {time.perf_counter() - t0:.1f} s")
+    shape = g.launch_shape()
+    progress(f"batched: group created in {time.perf_counter() - t0:.1f} s, launch shape {shape}")
     g.run_graph()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -368,8 +369,14 @@ def batched(args):
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / reps
     total = sum(u["batch"] for u in units)
+    kv = sum(kv_bytes_per_sample(u["model"].cfg.n_spins, u["model"].cfg.n_layers, u["model"].cfg.d_model,
+                                 u["model"].cfg.window, u["model"].cfg.prefix, 2) * u["batch"] for u in units)
+    achieved = kv / (ms * 1e-3) / 1e9
     return {"metric": "batched sampling + energy + F_q (spin samples/s)", "value": round(total / (ms * 1e-3), 1),
             "unit": "samples/s", "ms_per_launch": round(ms, 2), "units": len(units), "samples_per_launch": total,
+            "launch_shape": shape,
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": kv},
             "dtype": "bf16-split-mfma+fp16-kv",
             "config": {"workload": "64 2D EA instances (L=16/24/32 round-robin, +/-J) x 8 betas in [0.2, 3.0], "
                                    "d_model=64, 4 layers, 4 heads, 1024 samples per unit, one graph replay"}}

@@ -406,11 +406,27 @@ typedef struct {
   double* stats;                    /* device [2] as fvan_free_energy */
 } fvan_group_unit;
 
-/* Build the device unit table.  tile_samples: samples per work item; 0 or the
- * decode kernel's tile of 32 samples (anything else is EUNSUPPORTED).  EINVAL
- * when the models disagree in shape. */
+/* Build the device unit table and choose the launch shape (spec:
+ * batched launches with tile shapes from an autotuner).  tile_samples: samples
+ * per work item and decode workgroup, 16 or 32, or 0 to let the autotuner
+ * choose it.  The autotuner searches the tile and the persistent grid size
+ * (1, 2 and 4 workgroups per compute unit, and the grid whose samples in
+ * flight keep their K/V caches within the 256 MB MALL), timing each candidate
+ * on the same prefix of the work queue, and keeps the fastest per sample.  The
+ * choice is persisted per launch shape (model shape, precision, compute units,
+ * the units' sizes, masks and batches) in the JSON file named by
+ * $FVAN_TUNE_FILE (default $HOME/.cache/fvan_tuning.json); a later group of the
+ * same shape, in any process, takes the stored choice without timing.
+ * Creation synchronises the device.  EINVAL when the models disagree in shape;
+ * EUNSUPPORTED for a tile of 16 the model's decode kernel does not have. */
 int fvan_group_create(const fvan_group_unit* units, int32_t n_units, int32_t tile_samples,
                       fvan_group** out);
+/* The launch shape a group runs with: tile (samples per workgroup), grid
+ * (persistent workgroups), from_store = 1 when it came from the persisted
+ * store (no timing), and ms = the timed prefix of that shape.  Any output
+ * pointer may be NULL (host pointers). */
+int fvan_group_launch_shape(const fvan_group* group, int32_t* host_tile, int32_t* host_grid,
+                            int32_t* host_from_store, double* host_ms);
 int fvan_group_destroy(fvan_group* group);
 /* Sampling of every unit in one persistent launch (work queue over
  * (unit, sample tile)), followed by the energies and free-energy statistics. */

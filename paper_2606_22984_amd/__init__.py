@@ -29,7 +29,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", 
 EXPORTS = (
     "fvan_num_params", "fvan_derive_mask", "fvan_create_model", "fvan_destroy_model", "fvan_bind_params",
     "fvan_sync_params", "fvan_sample", "fvan_sample_noalloc", "fvan_sample_tokens", "fvan_log_prob_tokens_backward",
-    "fvan_tokens_to_spins", "fvan_train_step_tokens", "fvan_log_prob", "fvan_log_prob_tokens", "fvan_log_prob_backward", "fvan_energy",
+    "fvan_tokens_to_spins", "fvan_train_step_tokens", "fvan_group_launch_shape", "fvan_log_prob", "fvan_log_prob_tokens", "fvan_log_prob_backward", "fvan_energy",
     "fvan_free_energy", "fvan_reinforce_weights", "fvan_adam_step", "fvan_train_step",
     "fvan_newton_schulz", "fvan_muon_step", "fvan_train_step_muon",
     "fvan_lmc_refine", "fvan_distill_weights", "fvan_train_step_distill",
@@ -125,6 +125,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "fvan_log_prob_tokens_backward": [P, I32, P, P, P],
         "fvan_tokens_to_spins": [I32, I32, P, I32, I32, P, P, P],
         "fvan_train_step_tokens": [P, C.POINTER(CouplingsC), P, D, I32, U64, U64, C.POINTER(MuonC), P, P],
+        "fvan_group_launch_shape": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_double)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -654,6 +656,12 @@ class Group:
         h = C.c_void_p()
         _check(lib().fvan_group_create(arr, len(units), tile_samples, C.byref(h)))
         self.handle = h
+
+    def launch_shape(self) -> dict:
+        """The autotuned launch shape: tile, grid, whether it came from the persisted store, timed ms."""
+        t, g, f, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+        _check(lib().fvan_group_launch_shape(self.handle, C.byref(t), C.byref(g), C.byref(f), C.byref(ms)))
+        return {"tile": t.value, "grid": g.value, "from_store": bool(f.value), "prefix_ms": ms.value}
 
     def run(self, stream=None):
         _check(lib().fvan_group_run(self.handle, _stream(stream)))

@@ -206,9 +206,10 @@ int fvan_sample(fvan_model* m, int32_t batch, uint64_t seed, uint64_t stream_id,
   if (!has_sampler(m)) return fail(FVAN_EUNSUPPORTED, kNoSampler);
   if (!m->params || !m->synced) return fail(FVAN_EINVAL, "parameters not bound/synced");
   if (batch < 1 || batch > m->cfg.max_batch) return fail(FVAN_EINVAL, "batch outside [1, max_batch]");
-  DecodeUnit u = make_decode_unit(m, batch, seed, stream_id, spins, log_q, m->kv, 0);
-  const int tiles = (batch + decode_tile_samples() - 1) / decode_tile_samples();
-  FVAN_HIP(launch_decode_single(decode_shape(m->cfg), u, tiles, (hipStream_t)stream));
+  DecodeShape sh = decode_shape(m->cfg);
+  sh.tile = sample_tile(m, sh, batch);
+  DecodeUnit u = make_decode_unit(m, batch, seed, stream_id, spins, log_q, m->kv, 0, sh.tile);
+  FVAN_HIP(launch_decode_single(sh, u, u.n_tiles, (hipStream_t)stream));
   FVAN_HIP(check_finite(m, log_q, batch, (hipStream_t)stream));
   return FVAN_OK;
 }
@@ -221,9 +222,10 @@ int fvan_sample_tokens(fvan_model* m, int32_t batch, uint64_t seed, uint64_t str
   if (batch < 1 || batch > m->cfg.max_batch) return fail(FVAN_EINVAL, "batch outside [1, max_batch]");
   DecodeShape sh = decode_shape(m->cfg);
   sh.tokens = true;
-  DecodeUnit u = make_decode_unit(m, batch, seed, stream_id, reinterpret_cast<int8_t*>(tokens), log_q, m->kv, 0);
-  const int tiles = (batch + decode_tile_samples() - 1) / decode_tile_samples();
-  FVAN_HIP(launch_decode_single(sh, u, tiles, (hipStream_t)stream));
+  sh.tile = sample_tile(m, sh, batch);
+  DecodeUnit u = make_decode_unit(m, batch, seed, stream_id, reinterpret_cast<int8_t*>(tokens), log_q, m->kv, 0,
+                                  sh.tile);
+  FVAN_HIP(launch_decode_single(sh, u, u.n_tiles, (hipStream_t)stream));
   FVAN_HIP(check_finite(m, log_q, batch, (hipStream_t)stream));
   return FVAN_OK;
 }

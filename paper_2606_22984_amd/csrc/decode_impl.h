@@ -1,6 +1,6 @@
 // KV-cached ancestral sampling (Alg. 2 of the paper) for gfx950.
 //
-// One workgroup (8 waves) owns a tile of kM = 32 samples and runs every step
+// One workgroup (8 waves) owns a tile of KM = 32 (or 16) samples and runs every step
 // t = 0..N-1 and every layer without leaving the kernel: samples are
 // independent, so no grid-wide synchronisation is ever needed.  Per layer step:
 //   LN1 (16 lanes per sample, shuffle reductions)
@@ -31,27 +31,28 @@
 
 namespace fvan {
 
-constexpr int kM = 32;                 // samples per workgroup (two 16-row MFMA tiles)
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 constexpr int kMaxVocab = 256;
 
-template <int D, int MODE, bool TOK>
+// KM: samples per workgroup, 32 (two 16-row MFMA tiles: every weight fragment
+// feeds both) or 16 (one tile; twice the workgroups for a batch).
+template <int D, int MODE, bool TOK, int KM>
 struct DecodeSmem {
   typedef typename Mode<MODE>::ActT A;
   static constexpr int PAD = 16 / (int)sizeof(A);
   static constexpr int LDA = D + PAD;
   static constexpr int LDH = 4 * D + PAD;
   static constexpr int LDZ = kMaxVocab + 1;
-  __align__(16) float h[kM][D];
-  A a[kM][LDA];
+  __align__(16) float h[KM][D];
+  A a[KM][LDA];
   union {
-    float q[kM][D];
-    A hid[kM][LDH];
-    float z[TOK ? kM : 1][TOK ? LDZ : 1];   // logits of the vocab-way head
+    float q[KM][D];
+    A hid[KM][LDH];
+    float z[TOK ? KM : 1][TOK ? LDZ : 1];   // logits of the vocab-way head
   } u;
-  int tok[kM];
-  int8_t sbuf[kM][64];
+  int tok[KM];
+  int8_t sbuf[KM][64];
 };
 
 // Maximum over the 16 lanes of a row, the same in every lane of it.
@@ -65,13 +66,14 @@ __device__ __forceinline__ float row_max16(float v) {
 
 __device__ __forceinline__ float reduce16(float v) { return row_sum16(v); }
 
-// LayerNorm of the kM residual rows into the MFMA operand buffer.
-template <int D, int MODE, bool TOK>
-__device__ __forceinline__ void ln_rows(DecodeSmem<D, MODE, TOK>& sm, const float* __restrict__ g,
+// LayerNorm of the KM residual rows into the MFMA operand buffer (16 lanes per row).
+template <int D, int MODE, bool TOK, int KM>
+__device__ __forceinline__ void ln_rows(DecodeSmem<D, MODE, TOK, KM>& sm, const float* __restrict__ g,
                                         const float* __restrict__ b) {
   typedef typename Mode<MODE>::ActT T;
   constexpr int PER = D / 16;
   const int m = threadIdx.x >> 4, part = threadIdx.x & 15;
+  if (m >= KM) return;
   float x[PER];
   float s = 0.f;
 #pragma unroll
@@ -94,10 +96,11 @@ __device__ __forceinline__ void ln_rows(DecodeSmem<D, MODE, TOK>& sm, const floa
   }
 }
 
-// acc0, acc1 (16 x 16 tile nt of rows 0..15 and 16..31) = A[32 x K] (LDS, row
-// stride lda elements) . pack tile nt; each weight fragment is loaded once.
+// acc0, acc1 (16 x 16 tile nt of rows 0..15 and 16..31) = A[16 NRT x K] (LDS, row
+// stride lda elements) . pack tile nt; each weight fragment is loaded once and
+// feeds the NRT (1 or 2) row tiles; acc1 is left zero when NRT = 1.
 // lo_u4: distance (in 16-byte units) from a split pack's hi part to its lo part.
-template <int MODE, int K>
+template <int MODE, int K, int NRT>
 __device__ __forceinline__ void mfma_rowtiles(const typename Mode<MODE>::ActT* A, int lda,
                                               const uint4* __restrict__ pack, size_t lo_u4, int nt, int lane,
                                               floatx4& acc0, floatx4& acc1) {
@@ -122,15 +125,21 @@ __device__ __forceinline__ void mfma_rowtiles(const typename Mode<MODE>::ActT* A
       bl[u] = Mode<MODE>::SPLIT ? bp[(c0 + u) * 64 + lo_u4] : bh[u];
     }
 #pragma unroll
-    for (int u = 0; u < G; ++u)
-      Frag<MODE>::step2v(arow + (c0 + u) * KC, arow1 + (c0 + u) * KC, bh[u], bl[u], acc0, acc1);
+    for (int u = 0; u < G; ++u) {
+      if constexpr (NRT == 2)
+        Frag<MODE>::step2v(arow + (c0 + u) * KC, arow1 + (c0 + u) * KC, bh[u], bl[u], acc0, acc1);
+      else
+        Frag<MODE>::step1v(arow + (c0 + u) * KC, bh[u], bl[u], acc0);
+    }
   }
 }
 
-template <int D, int MODE, int DH, bool TOK>
-__device__ void decode_tile(DecodeSmem<D, MODE, TOK>& sm, const DecodeUnit& U, int local_tile) {
+template <int D, int MODE, int DH, bool TOK, int KM>
+__device__ void decode_tile(DecodeSmem<D, MODE, TOK, KM>& sm, const DecodeUnit& U, int local_tile) {
   typedef typename Mode<MODE>::KvT T;
-  typedef DecodeSmem<D, MODE, TOK> Sm;
+  typedef DecodeSmem<D, MODE, TOK, KM> Sm;
+  constexpr int NRT = KM / 16;          // 16-row MFMA tiles
+  static_assert(KM == 16 || KM == 32, "16 or 32 samples per workgroup");
   constexpr int VEC = Chunk<T>::N;
   constexpr int LPR = D / VEC;          // lanes per K/V row
   constexpr int RPL = 64 / LPR;         // rows per wave load
@@ -142,8 +151,8 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK>& sm, const DecodeUnit& U, i
   constexpr float kScaleLog2 = (DH == 16 ? 0.25f : DH == 32 ? 0.17677669529663688f : 0.125f) * 1.4426950408889634f;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int b0 = local_tile * kM;
-  const int nb = min(kM, U.B - b0);
+  const int b0 = local_tile * KM;
+  const int nb = min(KM, U.B - b0);
   const int N = U.N, P = U.P, R = U.R, S = U.S, nl = U.n_layers, dt = U.d_token;
   const float* __restrict__ theta = U.theta;
   const char* wbase = reinterpret_cast<const char*>(U.wpack);
@@ -154,12 +163,12 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK>& sm, const DecodeUnit& U, i
   const int hm = tid >> 4, hpart = tid & 15;
   float lq = 0.f;
   float ur[4] = {0.f, 0.f, 0.f, 0.f};
-  if (tid < kM) sm.tok[tid] = 0;   // start token
+  if (tid < KM) sm.tok[tid] = 0;   // start token
   __syncthreads();
 
   for (int t = 0; t < N; ++t) {
     // ---- concatenated embedding [tok_emb[tok]; pos_emb[t]] ----
-    for (int i = tid; i < kM * D; i += kThreads) {
+    for (int i = tid; i < KM * D; i += kThreads) {
       const int m = i / D, k = i % D;
       sm.h[m][k] = k < dt ? theta[sm.tok[m] * dt + k] : theta[U.pos_off + (size_t)t * (D - dt) + (k - dt)];
     }
@@ -170,7 +179,7 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK>& sm, const DecodeUnit& U, i
     for (int l = 0; l < nl; ++l) {
       const float* lp = theta + U.layer0 + (size_t)l * U.layer_stride;
       const char* wl = wbase + (size_t)l * U.p_layer_stride;
-      ln_rows<D, MODE>(sm, lp + U.o_ln1_g, lp + U.o_ln1_b);
+      ln_rows<D, MODE, TOK, KM>(sm, lp + U.o_ln1_g, lp + U.o_ln1_b);
       __syncthreads();
 
       // ---- QKV projection; k_t, v_t appended to the cache ----
@@ -178,11 +187,11 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK>& sm, const DecodeUnit& U, i
         const uint4* pk = reinterpret_cast<const uint4*>(wl + U.p_qkv);
         for (int nt = wave; nt < 3 * D / 16; nt += kWaves) {
           floatx4 acc[2];
-          mfma_rowtiles<MODE, D>(&sm.a[0][0], Sm::LDA, pk, (size_t)3 * D * D / 8, nt, lane, acc[0], acc[1]);
+          mfma_rowtiles<MODE, D, NRT>(&sm.a[0][0], Sm::LDA, pk, (size_t)3 * D * D / 8, nt, lane, acc[0], acc[1]);
           const int n = nt * 16 + (lane & 15);
           const float bias = lp[U.o_qkv_b + n];
 #pragma unroll
-          for (int ri = 0; ri < 8; ++ri) {
+          for (int ri = 0; ri < 4 * NRT; ++ri) {
             const int row = 16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3);
             const float val = acc[ri >> 2][ri & 3] + bias;
             if (n < D) {
@@ -303,17 +312,17 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK>& sm, const DecodeUnit& U, i
       __syncthreads();
 
       // ---- feed-forward block ----
-      ln_rows<D, MODE>(sm, lp + U.o_ln2_g, lp + U.o_ln2_b);
+      ln_rows<D, MODE, TOK, KM>(sm, lp + U.o_ln2_g, lp + U.o_ln2_b);
       __syncthreads();
       {
         const uint4* p1 = reinterpret_cast<const uint4*>(wl + U.p_ffn1);
         for (int nt = wave; nt < 4 * D / 16; nt += kWaves) {
           floatx4 acc[2];
-          mfma_rowtiles<MODE, D>(&sm.a[0][0], Sm::LDA, p1, (size_t)4 * D * D / 8, nt, lane, acc[0], acc[1]);
+          mfma_rowtiles<MODE, D, NRT>(&sm.a[0][0], Sm::LDA, p1, (size_t)4 * D * D / 8, nt, lane, acc[0], acc[1]);
           const int n = nt * 16 + (lane & 15);
           const float bias = lp[U.o_ffn1_b + n];
 #pragma unroll
-          for (int ri = 0; ri < 8; ++ri)
+          for (int ri = 0; ri < 4 * NRT; ++ri)
             sm.u.hid[16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3)][n] =
                 from_f<typename Mode<MODE>::ActT>(gelu(acc[ri >> 2][ri & 3] + bias));
         }
@@ -323,11 +332,11 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK>& sm, const DecodeUnit& U, i
         const uint4* p2 = reinterpret_cast<const uint4*>(wl + U.p_ffn2);
         for (int nt = wave; nt < D / 16; nt += kWaves) {
           floatx4 acc[2];
-          mfma_rowtiles<MODE, 4 * D>(&sm.u.hid[0][0], Sm::LDH, p2, (size_t)4 * D * D / 8, nt, lane, acc[0], acc[1]);
+          mfma_rowtiles<MODE, 4 * D, NRT>(&sm.u.hid[0][0], Sm::LDH, p2, (size_t)4 * D * D / 8, nt, lane, acc[0], acc[1]);
           const int n = nt * 16 + (lane & 15);
           const float bias = lp[U.o_ffn2_b + n];
 #pragma unroll
-          for (int ri = 0; ri < 8; ++ri) sm.h[16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3)][n] += acc[ri >> 2][ri & 3] + bias;
+          for (int ri = 0; ri < 4 * NRT; ++ri) sm.h[16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3)][n] += acc[ri >> 2][ri & 3] + bias;
         }
       }
       __syncthreads();
@@ -338,7 +347,7 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK>& sm, const DecodeUnit& U, i
       // logits z[m][v] = W_h[v] . h[m] + b[v]: thread (v, half) for samples 16 half .. 16 half + 15
       {
         const int v = tid & (kMaxVocab - 1), half = tid / kMaxVocab;
-        if (v < U.vocab) {
+        if (v < U.vocab && 16 * half < KM) {
           const float* wr = theta + U.head_w + (size_t)v * D;
           float acc[16];
 #pragma unroll
@@ -361,7 +370,7 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK>& sm, const DecodeUnit& U, i
       // softmax and draw: 16 lanes per sample, lane hpart holds logits 16 hpart .. 16 hpart + 15.
       // The token is the largest k >= 1 with u < sum_{j >= k} p_j (else 0), decided as
       // u * total < sum_{j >= k} e_j with e_j = exp(z_j - max), total = sum_j e_j.
-      {
+      if (hm < KM) {
         const int V = U.vocab, v0 = 16 * hpart;
         float zl[16];
         float mx = -INFINITY;
@@ -410,7 +419,7 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK>& sm, const DecodeUnit& U, i
         }
       }
     } else {
-      {
+      if (hm < KM) {
         const float* hw = theta + U.head_w;
         float z0 = 0.f, z1 = 0.f;
 #pragma unroll
@@ -442,7 +451,7 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK>& sm, const DecodeUnit& U, i
     __syncthreads();
     if ((t & 63) == 63 || t == N - 1) {
       const int base = t & ~63;
-      for (int i = tid; i < kM * 64; i += kThreads) {
+      for (int i = tid; i < KM * 64; i += kThreads) {
         const int m = i >> 6, j = i & 63;
         if (m < nb && base + j <= t) U.spins[(size_t)(b0 + m) * N + base + j] = sm.sbuf[m][j];
       }
@@ -452,10 +461,10 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK>& sm, const DecodeUnit& U, i
   __syncthreads();
 }
 
-template <int D, int MODE, int DH, bool TOK>
+template <int D, int MODE, int DH, bool TOK, int KM>
 __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeUnit u0, const DecodeUnit* __restrict__ table,
                                                           int n_units, int total_tiles, int* queue) {
-  __shared__ DecodeSmem<D, MODE, TOK> sm;
+  __shared__ DecodeSmem<D, MODE, TOK, KM> sm;
   __shared__ int s_tile;
   bool first = true;
   for (;;) {
@@ -475,31 +484,38 @@ __global__ __launch_bounds__(kThreads) void decode_kernel(DecodeUnit u0, const D
         if (table[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
       }
       const DecodeUnit U = table[lo];
-      decode_tile<D, MODE, DH, TOK>(sm, U, tile - U.tile0);
+      decode_tile<D, MODE, DH, TOK, KM>(sm, U, tile - U.tile0);
     } else {
-      decode_tile<D, MODE, DH, TOK>(sm, u0, tile);
+      decode_tile<D, MODE, DH, TOK, KM>(sm, u0, tile);
     }
   }
 }
 
-template <int D, int MODE, int DH, bool TOK>
+template <int D, int MODE, int DH, bool TOK, int KM>
 hipError_t launch_d(const DecodeUnit& u0, const DecodeUnit* table, int n_units, int total_tiles, int* queue, int grid,
                     hipStream_t s) {
-  hipLaunchKernelGGL((decode_kernel<D, MODE, DH, TOK>), dim3(grid), dim3(kThreads), 0, s, u0, table, n_units,
+  hipLaunchKernelGGL((decode_kernel<D, MODE, DH, TOK, KM>), dim3(grid), dim3(kThreads), 0, s, u0, table, n_units,
                      total_tiles, queue);
   return hipGetLastError();
 }
 
-// The instantiations decode_ext.hip holds (X(D, MODE, DH, TOK)).
-#define FVAN_DECODE_EXT_LIST(X)                                                                        \
-  X(32, 0, 32, false) X(32, 2, 32, false) X(64, 0, 32, false) X(64, 2, 32, false) X(64, 0, 64, false)   \
-  X(64, 2, 64, false) X(128, 0, 32, false) X(128, 2, 32, false) X(128, 0, 64, false)                    \
-  X(128, 2, 64, false) X(32, 0, 16, true) X(32, 2, 16, true) X(32, 0, 32, true) X(32, 2, 32, true)      \
-  X(64, 0, 16, true) X(64, 2, 16, true) X(64, 0, 32, true) X(64, 2, 32, true) X(64, 0, 64, true)        \
-  X(64, 2, 64, true) X(128, 0, 16, true) X(128, 2, 16, true) X(128, 0, 32, true) X(128, 2, 32, true)    \
-  X(128, 0, 64, true) X(128, 2, 64, true)
-#define FVAN_DECODE_INST(D, MODE, DH, TOK) \
-  template hipError_t launch_d<D, MODE, DH, TOK>(const DecodeUnit&, const DecodeUnit*, int, int, int*, int, hipStream_t);
-#define FVAN_DECODE_EXTERN(D, MODE, DH, TOK) extern FVAN_DECODE_INST(D, MODE, DH, TOK)
+// The instantiations decode_ext.hip holds (X(D, MODE, DH, TOK, KM)): other head
+// widths and token models with 32-sample tiles, and 16-sample tiles of the
+// single-spin 16-wide-head kernels (batched launches) and of the patched 3D
+// model's kernels.
+#define FVAN_DECODE_EXT_LIST(X)                                                                                \
+  X(32, 0, 32, false, 32) X(32, 2, 32, false, 32) X(64, 0, 32, false, 32) X(64, 2, 32, false, 32)             \
+  X(64, 0, 64, false, 32) X(64, 2, 64, false, 32) X(128, 0, 32, false, 32) X(128, 2, 32, false, 32)           \
+  X(128, 0, 64, false, 32) X(128, 2, 64, false, 32) X(32, 0, 16, true, 32) X(32, 2, 16, true, 32)             \
+  X(32, 0, 32, true, 32) X(32, 2, 32, true, 32) X(64, 0, 16, true, 32) X(64, 2, 16, true, 32)                 \
+  X(64, 0, 32, true, 32) X(64, 2, 32, true, 32) X(64, 0, 64, true, 32) X(64, 2, 64, true, 32)                 \
+  X(128, 0, 16, true, 32) X(128, 2, 16, true, 32) X(128, 0, 32, true, 32) X(128, 2, 32, true, 32)             \
+  X(128, 0, 64, true, 32) X(128, 2, 64, true, 32)                                                             \
+  X(32, 0, 16, false, 16) X(32, 2, 16, false, 16) X(64, 0, 16, false, 16) X(64, 2, 16, false, 16)             \
+  X(128, 0, 16, false, 16) X(128, 2, 16, false, 16) X(128, 0, 64, true, 16) X(128, 2, 64, true, 16)
+#define FVAN_DECODE_INST(D, MODE, DH, TOK, KM)                                                         \
+  template hipError_t launch_d<D, MODE, DH, TOK, KM>(const DecodeUnit&, const DecodeUnit*, int, int, int*, int, \
+                                                      hipStream_t);
+#define FVAN_DECODE_EXTERN(D, MODE, DH, TOK, KM) extern FVAN_DECODE_INST(D, MODE, DH, TOK, KM)
 
 }  // namespace fvan

@@ -117,6 +117,14 @@ template <> struct Frag<0> {
                                                floatx4& acc0, floatx4& acc1) {
     step2v(a0, a1, *b, *b, acc0, acc1);
   }
+  // one 16-row A tile against a B fragment already in registers
+  static __device__ __forceinline__ void step1v(const float* a0, const uint4 bv, const uint4, floatx4& acc0) {
+    const float4 x = *reinterpret_cast<const float4*>(a0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, __uint_as_float(bv.x), acc0, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, __uint_as_float(bv.y), acc0, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, __uint_as_float(bv.z), acc0, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, __uint_as_float(bv.w), acc0, 0, 0, 0);
+  }
   // the same with the B fragment already in registers
   static __device__ __forceinline__ void step2v(const float* a0, const float* a1, const uint4 bv, const uint4,
                                                 floatx4& acc0, floatx4& acc1) {
@@ -156,6 +164,13 @@ template <> struct Frag<2> {
   static __device__ __forceinline__ void step2(const float* a0, const float* a1, const uint4* b, const uint4* blo,
                                                floatx4& acc0, floatx4& acc1) {
     step2v(a0, a1, *b, *blo, acc0, acc1);
+  }
+  static __device__ __forceinline__ void step1v(const float* a0, const uint4 bh, const uint4 bl, floatx4& acc0) {
+    uint4 xh, xl;
+    split_a(a0, xh, xl);
+    acc0 = mfma_bf16(xl, bh, acc0);
+    acc0 = mfma_bf16(xh, bl, acc0);
+    acc0 = mfma_bf16(xh, bh, acc0);
   }
   static __device__ __forceinline__ void step2v(const float* a0, const float* a1, const uint4 bh, const uint4 bl,
                                                 floatx4& acc0, floatx4& acc1) {

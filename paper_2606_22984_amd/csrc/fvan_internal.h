@@ -80,10 +80,13 @@ struct DecodeUnit {
 struct DecodeShape {
   int d_model, precision, d_head;
   bool tokens;         // vocab-way head and token draw
+  int tile;            // samples per workgroup: 32, or 16 where decode_has_tile16
 };
-inline DecodeShape decode_shape(const fvan_model_config& c) {
-  return DecodeShape{c.d_model, c.precision, c.d_model / c.n_heads, c.vocab > 2};
+inline DecodeShape decode_shape(const fvan_model_config& c, int tile = 32) {
+  return DecodeShape{c.d_model, c.precision, c.d_model / c.n_heads, c.vocab > 2, tile};
 }
+// Whether the decode kernel of this shape exists with 16-sample tiles.
+bool decode_has_tile16(const DecodeShape& sh);
 
 // Messages of the entry points a model's configuration does not provide.
 constexpr const char* kBinaryOnly =

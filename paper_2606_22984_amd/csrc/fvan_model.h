@@ -67,8 +67,11 @@ inline bool has_sampler(const fvan_model* m) { return (m->cfg.workspaces & FVAN_
 inline bool has_teacher(const fvan_model* m) { return (m->cfg.workspaces & FVAN_WS_TEACHER) != 0; }
 void model_free(fvan_model* m);
 void model_free_fwd(fvan_model* m);
+// tile: samples per decode workgroup (16 or 32; DecodeShape::tile of the launch).
 DecodeUnit make_decode_unit(const fvan_model* m, int32_t batch, uint64_t seed, uint64_t stream_id, int8_t* spins,
-                            float* log_q, void* kv, int tile0);
+                            float* log_q, void* kv, int tile0, int tile);
+int device_cus(int dev);
+int sample_tile(const fvan_model* m, DecodeShape sh, int32_t batch);
 // Resolve (once per device; `dev` must be current) the device address of the
 // static KV cache fvan_sample_noalloc uses.
 int static_kv_setup(int dev);

@@ -10,16 +10,23 @@
 // once into a HIP graph and replayed; the queue counter is reset by a kernel,
 // not a memset node, so replays stay correct.
 //
-// The persistent grid size is chosen by a small autotuner that times the
-// sampling launch for a few grid sizes and keeps the fastest; results are
-// cached per (d_model, n_layers, precision, work items) for the process.
+// The launch shape is chosen by an autotuner: samples per workgroup (16 or 32)
+// and the persistent grid size, including a grid sized so that the K/V caches
+// of the samples in flight fit the 256 MB MALL (the last-level cache in front of
+// HBM) rather than streaming from HBM.  Each candidate is timed on the same
+// prefix of the work queue (the longest units); the fastest is kept and
+// persisted per shape (tune_cache.h), so later groups of that shape, in this
+// or another process, reuse it without timing.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
-#include <tuple>
+#include <string>
 #include <vector>
 
 #include "device_common.h"
 #include "fvan_model.h"
+#include "tune_cache.h"
 
 namespace fvan {
 
@@ -136,6 +143,11 @@ struct fvan_group {
   int d_model = 0, precision = 0, n_layers = 0;
   fvan::DecodeShape shape{};
   int n_units = 0, total_tiles = 0, grid = 0, device = 0;
+  std::vector<fvan::DecodeUnit> host_table;   // tile0 / n_tiles for shape.tile
+  std::string tune_key;
+  bool tuned_from_cache = false;
+  double tuned_ms = 0.0;                      // timed prefix of the chosen shape
+  size_t kv_sample_max = 0;                   // largest per-sample K/V cache of the units
   std::vector<fvan_group_unit> units;
   std::vector<fvan_couplings> coup;
   fvan::DecodeUnit* d_table = nullptr;
@@ -152,15 +164,30 @@ struct fvan_group {
 
 namespace fvan {
 
-static std::map<std::tuple<int, int, int, int>, int>& tuned_grids() {
-  static std::map<std::tuple<int, int, int, int>, int> m;
-  return m;
+constexpr size_t kMallBytes = size_t(256) << 20;   // MI355X Infinity Cache (MALL)
+
+static hipError_t group_sample_n(fvan_group* g, int grid, int n_tiles, hipStream_t s) {
+  hipError_t e = launch_zero_int(g->d_queue, 1, s);
+  if (e != hipSuccess) return e;
+  return launch_decode(g->shape, g->d_table, g->n_units, n_tiles, g->d_queue, grid, s);
 }
 
 static hipError_t group_sample(fvan_group* g, int grid, hipStream_t s) {
-  hipError_t e = launch_zero_int(g->d_queue, 1, s);
-  if (e != hipSuccess) return e;
-  return launch_decode(g->shape, g->d_table, g->n_units, g->total_tiles, g->d_queue, grid, s);
+  return group_sample_n(g, grid, g->total_tiles, s);
+}
+
+// Re-tile the unit table for `tile` samples per workgroup and upload it (synchronous).
+static hipError_t group_set_tile(fvan_group* g, int tile) {
+  int t0 = 0;
+  for (auto& d : g->host_table) {
+    d.tile0 = t0;
+    d.n_tiles = (d.B + tile - 1) / tile;
+    t0 += d.n_tiles;
+  }
+  g->shape.tile = tile;
+  g->total_tiles = t0;
+  return hipMemcpy(g->d_table, g->host_table.data(), g->host_table.size() * sizeof(DecodeUnit),
+                   hipMemcpyHostToDevice);
 }
 
 static int group_run_impl(fvan_group* g, hipStream_t s) {
@@ -178,47 +205,105 @@ static int group_run_impl(fvan_group* g, hipStream_t s) {
   return FVAN_OK;
 }
 
-// Time the sampling launch at a few persistent grid sizes; keep the fastest.
-static int autotune_grid(fvan_group* g) {
-  int cus = 256;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, g->device) == hipSuccess && prop.multiProcessorCount > 0)
-    cus = prop.multiProcessorCount;
-  const auto key = std::make_tuple(g->d_model, g->n_layers, g->precision, g->total_tiles);
-  auto it = tuned_grids().find(key);
-  if (it != tuned_grids().end()) {
-    g->grid = it->second;
-    return FVAN_OK;
+// Key of a group's launch shape: model shape, precision, compute units and a
+// hash of the units' (N, W, P, batch) in table order.
+static std::string group_tune_key(const fvan_group* g, int cus) {
+  uint64_t h = 1469598103934665603ull;   // FNV-1a
+  auto mix = [&](int64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (uint64_t)((v >> (8 * i)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  for (const auto& d : g->host_table) {
+    mix(d.N); mix(d.W); mix(d.P); mix(d.B);
   }
-  std::vector<int> cand;
-  for (int k : {1, 2, 3, 4}) cand.push_back(std::min(g->total_tiles, k * cus));
-  std::sort(cand.begin(), cand.end());
-  cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "group_d%d_l%d_h%d_p%d_cu%d_u%d_%016llx", g->d_model, g->n_layers,
+                g->shape.d_head, g->precision, cus, g->n_units, (unsigned long long)h);
+  return buf;
+}
+
+// Choose (tile, grid): a persisted entry for this shape if there is one, else
+// time every candidate on the same prefix of the work queue and persist the
+// fastest.  fixed_tile (16 or 32) restricts the search to that tile.
+static int autotune(fvan_group* g, int fixed_tile) {
+  const int cus = device_cus(g->device);
+  g->tune_key = group_tune_key(g, cus);
+  std::vector<int> tiles;
+  if (fixed_tile) {
+    tiles.push_back(fixed_tile);
+  } else {
+    DecodeShape sh16 = g->shape;
+    sh16.tile = 16;
+    if (decode_has_tile16(sh16)) tiles.push_back(16);
+    tiles.push_back(32);
+  }
+  const std::string path = tune_file_path();
+  {
+    std::lock_guard<std::mutex> lock(tune_mutex());
+    const auto stored = tune_read(path);
+    auto it = stored.find(g->tune_key);
+    if (it != stored.end() && it->second.grid > 0 &&
+        std::find(tiles.begin(), tiles.end(), it->second.tile) != tiles.end()) {
+      FVAN_HIP(group_set_tile(g, it->second.tile));
+      g->grid = std::min(it->second.grid, g->total_tiles);
+      g->tuned_ms = it->second.ms;
+      g->tuned_from_cache = true;
+      return FVAN_OK;
+    }
+  }
   hipStream_t s;
   FVAN_HIP(hipStreamCreate(&s));
   hipEvent_t a, b;
   FVAN_HIP(hipEventCreate(&a));
   FVAN_HIP(hipEventCreate(&b));
+  // the prefix every candidate runs: the first ~12 tiles of 32 samples per compute unit
+  const int64_t prefix_samples = std::min<int64_t>(g->total_samples, (int64_t)cus * 32 * 12);
   float best = 1e30f;
-  int best_grid = cand.back();
-  for (int grid : cand) {
-    FVAN_HIP(group_sample(g, grid, s));     // warm
-    FVAN_HIP(hipEventRecord(a, s));
-    FVAN_HIP(group_sample(g, grid, s));
-    FVAN_HIP(hipEventRecord(b, s));
-    FVAN_HIP(hipEventSynchronize(b));
-    float ms = 0.f;
-    FVAN_HIP(hipEventElapsedTime(&ms, a, b));
-    if (ms < best) {
-      best = ms;
-      best_grid = grid;
+  int best_tile = tiles.back(), best_grid = 0;
+  for (int tile : tiles) {
+    FVAN_HIP(group_set_tile(g, tile));
+    const int n_pre = (int)std::min<int64_t>(g->total_tiles, (prefix_samples + tile - 1) / tile);
+    std::vector<int> cand;
+    for (int k : {1, 2, 4}) cand.push_back(std::min(n_pre, k * cus));
+    const int64_t mall = (int64_t)(kMallBytes / std::max<size_t>(1, (size_t)tile * g->kv_sample_max));
+    if (mall >= cus / 4 && mall < n_pre) cand.push_back((int)mall);
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    FVAN_HIP(group_sample_n(g, cand.front(), n_pre, s));   // loads this tile's kernel
+    for (int grid : cand) {
+      FVAN_HIP(hipEventRecord(a, s));
+      FVAN_HIP(group_sample_n(g, grid, n_pre, s));
+      FVAN_HIP(hipEventRecord(b, s));
+      FVAN_HIP(hipEventSynchronize(b));
+      float ms = 0.f;
+      FVAN_HIP(hipEventElapsedTime(&ms, a, b));
+      // per sample, so tiles of 16 and 32 compare on the same prefix
+      const float per = ms / (float)std::min<int64_t>(g->total_samples, (int64_t)n_pre * tile);
+      if (std::getenv("FVAN_TUNE_LOG"))
+        std::fprintf(stderr, "[fvan tune] %s tile %d grid %d: %.3f ms for %d work items (%.3f us per sample)\n",
+                     g->tune_key.c_str(), tile, grid, ms, n_pre, 1e3 * per);
+      if (per < best) {
+        best = per;
+        best_tile = tile;
+        best_grid = grid;
+      }
     }
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   (void)hipStreamDestroy(s);
-  g->grid = best_grid;
-  tuned_grids()[key] = best_grid;
+  FVAN_HIP(group_set_tile(g, best_tile));
+  g->grid = std::min(best_grid, g->total_tiles);
+  g->tuned_ms = (double)best * (double)prefix_samples;
+  g->tuned_from_cache = false;
+  {
+    std::lock_guard<std::mutex> lock(tune_mutex());
+    auto stored = tune_read(path);
+    stored[g->tune_key] = TuneEntry{best_tile, best_grid, g->tuned_ms};
+    (void)tune_write(path, stored);          // best effort: an unwritable store only costs re-tuning
+  }
   return FVAN_OK;
 }
 
@@ -242,8 +327,8 @@ extern "C" {
 int fvan_group_create(const fvan_group_unit* units, int32_t n_units, int32_t tile_samples, fvan_group** out) {
   if (!units || !out || n_units < 1) return fail(FVAN_EINVAL, "units and out must be non-NULL, n_units >= 1");
   *out = nullptr;
-  if (tile_samples != 0 && tile_samples != decode_tile_samples())
-    return fail(FVAN_EUNSUPPORTED, "tile_samples must be 0 or " + std::to_string(decode_tile_samples()));
+  if (tile_samples != 0 && tile_samples != 16 && tile_samples != 32)
+    return fail(FVAN_EUNSUPPORTED, "tile_samples must be 0 (autotuned), 16 or 32");
   const fvan_model* m0 = units[0].model;
   if (!m0) return fail(FVAN_EINVAL, "unit 0 has no model");
   for (int i = 0; i < n_units; ++i)
@@ -294,9 +379,10 @@ int fvan_group_create(const fvan_group_unit* units, int32_t n_units, int32_t til
       delete g;
       return fail(FVAN_EINVAL, "unit " + std::to_string(i) + ": batch, beta or couplings out of range");
     }
-    DecodeUnit d = make_decode_unit(m, u.batch, u.seed, u.stream_id, u.spins, u.log_q, m->kv, tiles);
+    DecodeUnit d = make_decode_unit(m, u.batch, u.seed, u.stream_id, u.spins, u.log_q, m->kv, tiles, 32);
     tiles += d.n_tiles;
     table.push_back(d);
+    g->kv_sample_max = std::max(g->kv_sample_max, m->kv_bytes / (size_t)m->cfg.max_batch);
     g->coup.push_back(*u.couplings);
     if (u.couplings->kind == FVAN_BONDS_DENSE || u.couplings->n_spins > 4096) g->ell_energy = false;
     en[k] = GroupEnergyUnit{m->cfg.n_spins, u.couplings->kind, u.couplings->degree, u.batch, u.couplings->nbr,
@@ -326,13 +412,32 @@ int fvan_group_create(const fvan_group_unit* units, int32_t n_units, int32_t til
     delete g;
     return fail(FVAN_ENOMEM, std::string("group tables: ") + hipGetErrorString(e));
   }
-  int rc = autotune_grid(g);
+  g->host_table = table;
+  if (tile_samples == 16) {
+    DecodeShape sh16 = g->shape;
+    sh16.tile = 16;
+    if (!decode_has_tile16(sh16)) {
+      group_free(g);
+      delete g;
+      return fail(FVAN_EUNSUPPORTED, "no 16-sample decode tile for this model shape");
+    }
+  }
+  int rc = autotune(g, tile_samples);
   if (rc) {
     group_free(g);
     delete g;
     return rc;
   }
   *out = g;
+  return FVAN_OK;
+}
+
+int fvan_group_launch_shape(const fvan_group* g, int32_t* tile, int32_t* grid, int32_t* from_store, double* ms) {
+  if (!g) return fail(FVAN_EINVAL, "group is NULL");
+  if (tile) *tile = g->shape.tile;
+  if (grid) *grid = g->grid;
+  if (from_store) *from_store = g->tuned_from_cache ? 1 : 0;
+  if (ms) *ms = g->tuned_ms;
   return FVAN_OK;
 }
 

@@ -1,6 +1,8 @@
 // Model workspaces (allocated and initialised at create time) and the
 // per-call decode descriptor.
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "device_common.h"
 #include "fvan_model.h"
@@ -170,8 +172,32 @@ static hipError_t check_finite_t(fvan_model* m, const T* v, int64_t n, hipStream
 hipError_t check_finite(fvan_model* m, const float* v, int64_t n, hipStream_t s) { return check_finite_t(m, v, n, s); }
 hipError_t check_finite(fvan_model* m, const double* v, int64_t n, hipStream_t s) { return check_finite_t(m, v, n, s); }
 
+int device_cus(int dev) {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) {
+    (void)hipGetLastError();
+    n = 256;
+  }
+  cache[dev] = n;
+  return n;
+}
+
+// Samples per decode workgroup for a sampling call of `batch` samples: 16 when
+// 32-sample tiles would leave compute units idle and the kernel exists with
+// 16-sample tiles (the per-sample arithmetic is the same for both), else 32.
+int sample_tile(const fvan_model* m, DecodeShape sh, int32_t batch) {
+  sh.tile = 16;
+  if (!decode_has_tile16(sh)) return 32;
+  return (batch + 31) / 32 < device_cus(m->device) ? 16 : 32;
+}
+
 DecodeUnit make_decode_unit(const fvan_model* m, int32_t batch, uint64_t seed, uint64_t stream_id, int8_t* spins,
-                            float* log_q, void* kv, int tile0) {
+                            float* log_q, void* kv, int tile0, int tile) {
   const fvan_model_config& c = m->cfg;
   DecodeUnit u{};
   u.theta = m->params;
@@ -187,7 +213,7 @@ DecodeUnit make_decode_unit(const fvan_model* m, int32_t batch, uint64_t seed, u
   u.B = batch;
   u.n_layers = c.n_layers;
   u.tile0 = tile0;
-  u.n_tiles = (batch + decode_tile_samples() - 1) / decode_tile_samples();
+  u.n_tiles = (batch + tile - 1) / tile;
   u.pos_off = (int32_t)m->po.pos;
   u.layer0 = m->po.layer0;
   u.layer_stride = m->po.layer_stride;

@@ -71,9 +71,10 @@ extern "C" int fvan_sample_noalloc(fvan_model* m, int32_t batch, uint64_t seed, 
   if (dev != m->device) return fail(FVAN_EINVAL, "the current device is not the model's device");
   void* kv = nullptr;
   if (int rc = scratch_address(dev, &kv)) return rc;
-  DecodeUnit u = make_decode_unit(m, batch, seed, stream_id, spins, log_q, kv, 0);
-  const int tiles = (batch + decode_tile_samples() - 1) / decode_tile_samples();
-  FVAN_HIP(launch_decode_single(decode_shape(m->cfg), u, tiles, (hipStream_t)stream));
+  DecodeShape sh = decode_shape(m->cfg);
+  sh.tile = sample_tile(m, sh, batch);
+  DecodeUnit u = make_decode_unit(m, batch, seed, stream_id, spins, log_q, kv, 0, sh.tile);
+  FVAN_HIP(launch_decode_single(sh, u, u.n_tiles, (hipStream_t)stream));
   FVAN_HIP(check_finite(m, log_q, batch, (hipStream_t)stream));
   return FVAN_OK;
 }

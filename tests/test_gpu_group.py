@@ -28,10 +28,17 @@ def _units(prec, sizes=(4, 6, 8), betas=(0.5, 1.5), batch=40, d=64):
     return units
 
 
+@pytest.mark.parametrize("tile", [0, 16, 32])
 @pytest.mark.parametrize("prec", [FP32, SPLIT])
-def test_group_equals_single_model_runs(prec):
+def test_group_equals_single_model_runs(prec, tile):
+    """Every tile shape (0: the autotuner's choice) gives each unit exactly the
+    samples of its model sampled alone (the per-sample arithmetic does not depend
+    on the tile)."""
     units = _units(prec)
-    g = fv.Group(units)
+    g = fv.Group(units, tile_samples=tile)
+    say(f"group launch shape {g.launch_shape()}")
+    if tile:
+        assert g.launch_shape()["tile"] == tile
     g.run()
     torch.cuda.synchronize()
     for u, out in zip(units, g.outputs):
@@ -81,17 +88,58 @@ def test_group_rejects_mismatched_models():
         fv.Group(b)
 
 
-def test_group_tile_size_is_the_decode_tile():
-    """tile_samples: 0 (default) and 32 build the same group; any other size is
-    refused with a message naming the supported one."""
+def test_group_tile_sizes():
+    """tile_samples 0 (autotuned), 16 and 32 are accepted; any other size is
+    refused with a message naming the supported ones."""
     a = _units(FP32, sizes=(4,), betas=(1.0,))
-    fv.Group(a, tile_samples=32)
-    with pytest.raises(fv.FvanError, match="32"):
-        fv.Group(a, tile_samples=16)
+    for t in (0, 16, 32):
+        fv.Group(a, tile_samples=t).close()
+    with pytest.raises(fv.FvanError, match="16 or 32"):
+        fv.Group(a, tile_samples=8)
 
 
+_REUSE_SCRIPT = """
+import json, sys, torch
+sys.path.insert(0, {root!r})
+import paper_2606_22984_amd as fv
+from tests.gpu_util import lattice_cfg
+from workloads import ea_instance, init_params
+units = []
+for k, L in enumerate((6, 8)):
+    cfg = lattice_cfg(L, 2, 64, 2, 4)
+    m = fv.Model(cfg, 200, fv.FVAN_BF16_SPLIT, init_params(cfg, k), workspaces=fv.WS_SAMPLER)
+    units.append(dict(model=m, couplings=fv.couplings(ea_instance(L, 2, k, "pm1")), beta=1.0, batch=200, seed=1,
+                      stream_id=k))
+g = fv.Group(units)
+print(json.dumps(g.launch_shape()))
+"""
+
+
+def test_group_launch_shape_is_persisted_and_reused(tmp_path):
+    """A second process building a group of the same shape takes the first one's
+    tuned launch shape from the store, without timing."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, FVAN_TUNE_FILE=str(tmp_path / "tune.json"))
+    outs = []
+    for _ in range(2):
+        r = subprocess.run([sys.executable, "-c", _REUSE_SCRIPT.format(root=root)], env=env, capture_output=True,
+                           text=True, timeout=240)
+        assert r.returncode == 0, r.stderr[-2000:]
+        outs.append(json.loads(r.stdout.strip().splitlines()[-1]))
+    say(f"first process {outs[0]}, second {outs[1]}")
+    assert not outs[0]["from_store"] and outs[1]["from_store"]
+    assert (outs[0]["tile"], outs[0]["grid"]) == (outs[1]["tile"], outs[1]["grid"])
+    store = (tmp_path / "tune.json").read_text()
+    assert '"tile": %d, "grid": %d' % (outs[0]["tile"], outs[0]["grid"]) in store
+
+
+@pytest.mark.parametrize("tile", [16, 32])
 @pytest.mark.parametrize("prec", [FP32, SPLIT])
-def test_group_matches_oracle_at_batched_workload_shape(prec):
+def test_group_matches_oracle_at_batched_workload_shape(prec, tile):
     """The batched workload's unit shape (2D EA, d_model 64, 4 layers, 4 heads,
     1024 samples per unit) at L = 16, 24 and 32 in one group, each unit checked
     against the FP64 oracle directly: the teacher-forced decision check and the
@@ -107,10 +155,10 @@ def test_group_matches_oracle_at_batched_workload_shape(prec):
         m = fv.Model(cfg, B, prec, theta, workspaces=fv.WS_SAMPLER)
         units.append(dict(model=m, couplings=fv.couplings(inst), beta=0.2 + 1.4 * k, batch=B, seed=17,
                           stream_id=300 + k, inst=inst, theta=theta, cfg=cfg))
-    g = fv.Group(units)
+    g = fv.Group(units, tile_samples=tile)
     g.run_graph()
     torch.cuda.synchronize()
-    rows = [0, 31, 32, 500, B - 1]
+    rows = [0, 15, 16, 31, 32, 500, B - 1]
     for u, out in zip(units, g.outputs):
         cfg = u["cfg"]
         say(f"group unit L={int(round(cfg.n_spins ** 0.5))} prec {prec}: oracle on rows {rows}")
