@@ -127,6 +127,74 @@ def patched(args):
             "precisions": out}
 
 
+def single_workload(name, steps, warmup, optimizer="muon"):
+    """Another single-model workload at its own sizes: the full training step
+    (split and FP32) and sampling alone, with the decode's HBM roofline
+    fraction (the K/V bytes it must read, per launch duration)."""
+    import numpy as np
+    import torch
+
+    import paper_2606_22984_amd as fv
+    from workloads import ea_instance, init_params, sk_instance, workload
+
+    wl = workload(name)
+    if wl.kind == "sk":
+        inst = sk_instance(wl.size, wl.instance_seed)
+        cfg = wl.model.full_causal()
+    else:
+        inst = ea_instance(wl.size, wl.dim, wl.instance_seed, wl.bonds)
+        W, P = fv.derive_mask(inst.n, inst.edges_i, inst.edges_j)
+        cfg = wl.model.with_mask(W, P)
+    theta = init_params(cfg, wl.param_seed, "default")
+    coup = fv.couplings(inst)
+    B, beta, seed = wl.batch, float(wl.betas[0]), 777
+    stream = torch.cuda.current_stream()
+    out = {}
+    for pname, prec in (("bf16split", fv.FVAN_BF16_SPLIT), ("fp32", fv.FVAN_FP32)):
+        m = fv.Model(cfg, B, prec, theta)
+        stats = torch.zeros(4, dtype=torch.float64, device="cuda")
+
+        def step(k):
+            if optimizer == "muon":
+                m.train_step_muon(coup, beta, B, seed, k, stats, lr=warmup_lr(k), adam_lr=warmup_lr(k))
+            else:
+                m.train_step(coup, beta, B, seed, k, lr=warmup_lr(k), stats=stats)
+
+        for k in range(1, warmup + 1):
+            step(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(warmup + 1, warmup + steps + 1):
+            step(k)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        spins = torch.empty(B, cfg.n_spins, dtype=torch.int8, device="cuda")
+        lq = torch.empty(B, dtype=torch.float32, device="cuda")
+        m.sample(B, seed, 1, spins, lq)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for k in range(steps):
+            m.sample(B, seed, 2 + k, spins, lq)
+        b.record(stream)
+        torch.cuda.synchronize()
+        dec = a.elapsed_time(b) / steps
+        m.status()
+        m.close()
+        kv = kv_bytes_per_sample(cfg.n_spins, cfg.n_layers, cfg.d_model, cfg.window, cfg.prefix,
+                                 4 if prec == fv.FVAN_FP32 else 2) * B
+        out[pname] = {"train_step_ms": round(ms, 3), "train_samples_per_s": round(B / (ms * 1e-3), 1),
+                      "decode_ms": round(dec, 3), "sample_only_samples_per_s": round(B / (dec * 1e-3), 1),
+                      "decode_hbm_frac": round(kv / (dec * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                      "F_per_site": float(stats[0].item())}
+        progress(f"{name} {pname}: {ms:.1f} ms per step, decode {dec:.2f} ms")
+    sp, fp = out["bf16split"], out["fp32"]
+    return {"workload": f"{name}: N={cfg.n_spins}, d_model={cfg.d_model}, {cfg.n_layers} layers, {cfg.n_heads} heads, "
+                        f"batch {B}, mask W={cfg.window} P={cfg.prefix}",
+            "precisions": out,
+            "speedup_vs_fp32": {"train_step": round(fp["train_step_ms"] / sp["train_step_ms"], 3),
+                                "sampling": round(fp["decode_ms"] / sp["decode_ms"], 3)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +203,9 @@ def main():
     ap.add_argument("--compare-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (2D EA L=16, SK N=512, the batched launch, the patched 3D step) "
+                         "that the default line carries as extra keys")
     ap.add_argument("--optimizer", choices=("muon", "adam"), default="muon",
                     help="parameter update of the training step (muon: the paper's default)")
     ap.add_argument("--batched", action="store_true",
@@ -291,6 +362,18 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": DECODE_TRAFFIC_BYTES,
             "kernel": "decode_kernel<128,2>", "algorithmic_bytes_per_launch": bytes_launch}
 
+    extra = None
+    if not args.no_extra:
+        extra = {}
+        for name in ("ea2d_L16", "sk512"):
+            extra[name] = single_workload(name, 3, 1, args.optimizer)
+        progress("batched workload")
+        bargs = argparse.Namespace(steps=2)
+        extra["ea2d_batched"] = batched(bargs)
+        progress("patched 3D step")
+        pargs = argparse.Namespace(steps=5, warmup=2)
+        extra["ea3d_L10_patched"] = patched(pargs)
+
     cpu = None
     if not args.no_cpu_baseline:
         progress("timing the FP64 oracle on the host")
@@ -322,6 +405,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if extra is not None:
+        out["other_workloads"] = extra
     if "fp32" in others:
         out["speedup_vs_fp32"] = {
             "train_step": round(head["samples_per_s"] / others["fp32"]["samples_per_s"], 3),
