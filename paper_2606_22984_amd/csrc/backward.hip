@@ -704,38 +704,17 @@ static hipError_t backward_chunk_t(fvan_model* m, const void* seq, int nsamp, co
     const float* XM = f.XM + (size_t)l * f.rows * D;
     const KT* QKV = reinterpret_cast<const KT*>(f.QKV) + (size_t)l * f.rows * 3 * D;
     const float* LSE = f.LSE + (size_t)l * f.rows * H;
-    // ---- FFN: recompute LN2 and the pre-activation, then differentiate
-    // (LN2 output feature-major for dW1; the FFN1 GEMM recomputes LN2 itself)
-    hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(rgrid), dim3(256), 0, s, XM, rows, lp + m->po.ln2_g,
-                       lp + m->po.ln2_b, (AT*)nullptr, (AT*)f.T_c, f.ldT);
-    EpiArgs e1{};
-    e1.bias = lp + m->po.ffn1_b;
-    e1.hpre_out = f.HPRE;
-    e1.outT = f.T_b;
-    e1.ldT = f.ldT;
-    e1.ln_x = XM;
-    e1.ln_g = lp + m->po.ln2_g;
-    e1.ln_b = lp + m->po.ln2_b;
-    if ((err = gemm_rows<MODE, D, 4 * D, EPI_GELU>(nullptr, rows, wl + m->pk.ffn1, e1, s))) return err;
-    // activations are FP32 in both modes: the row-major dY operand is dX itself
-    static_assert(sizeof(AT) == 4, "FP32 activations");
-    const AT* dY = (const AT*)f.dX;
-    hipLaunchKernelGGL((transpose_cast_kernel<D, AT>), dim3(rgrid), dim3(256), 0, s, (const float*)f.dX, rows,
-                       (AT*)nullptr, (AT*)f.T_a, f.ldT);
-    if ((err = wgrad<MODE, D, 4 * D>(m, f.T_a, f.T_b, rows, gl + m->po.ffn2_w, gl + m->po.ffn2_b, s))) return err;
-    EpiArgs e2{};
-    e2.hpre_in = f.HPRE;
-    e2.out = f.dH;
-    e2.outT = f.T_a;
-    e2.ldT = f.ldT;
-    if ((err = gemm_rows<MODE, D, 4 * D, EPI_DGELU>(dY, rows, wl + m->pk.ffn2T, e2, s))) return err;
+    // ---- FFN: one fused kernel recomputes LN2, the pre-activation and GELU,
+    // differentiates through W2, GELU' and W1 and the LayerNorm, and leaves the
+    // feature-major operands of the two weight gradients
+    hipLaunchKernelGGL((ffn_bwd_fused_kernel<MODE, D>), dim3((int)((rows + kFfnBwdRows - 1) / kFfnBwdRows)),
+                       dim3(512), 0, s, XM, (const float*)f.dX, lp + m->po.ln2_g, lp + m->po.ln2_b, rows,
+                       reinterpret_cast<const uint4*>(wl + m->pk.ffn1), reinterpret_cast<const uint4*>(wl + m->pk.ffn2T),
+                       reinterpret_cast<const uint4*>(wl + m->pk.ffn1T), lp + m->po.ffn1_b, (AT*)f.T_b, (AT*)f.T_a,
+                       (AT*)f.T_c, (AT*)f.T_d, f.ldT, f.dXM, f.colpart);
+    if ((err = wgrad<MODE, D, 4 * D>(m, f.T_d, f.T_b, rows, gl + m->po.ffn2_w, gl + m->po.ffn2_b, s))) return err;
     if ((err = wgrad<MODE, 4 * D, D>(m, f.T_a, f.T_c, rows, gl + m->po.ffn1_w, gl + m->po.ffn1_b, s))) return err;
-    EpiArgs e3{};
-    e3.out = f.TMP;
-    if ((err = gemm_rows<MODE, 4 * D, D, EPI_F32>((const AT*)f.dH, rows, wl + m->pk.ffn1T, e3, s))) return err;
-    hipLaunchKernelGGL((ln_bwd_kernel<D>), dim3(rgrid), dim3(256), 0, s, (const float*)f.TMP, XM, lp + m->po.ln2_g,
-                       (const float*)f.dX, rows, f.dXM, f.colpart);
-    colsum_add(f.colpart, rgrid, 2 * D, f.colpart2, gl + m->po.ln2_g, s);
+    colsum_add(f.colpart, (int)((rows + kFfnBwdRows - 1) / kFfnBwdRows), 2 * D, f.colpart2, gl + m->po.ln2_g, s);
     // ---- attention backward (dO = dXM: the heads' output is added to the residual directly);
     // probabilities are recomputed from Q, K and the saved log-sum-exp
     if (D / H == 16) {

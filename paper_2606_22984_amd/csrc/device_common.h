@@ -273,6 +273,13 @@ __device__ __forceinline__ float gelu_grad(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * __expf(-0.5f * x * x);
 }
 
+// GELU(x) and its derivative from one evaluation of erf.
+__device__ __forceinline__ void gelu_and_grad(float x, float& g, float& gp) {
+  const float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
+  g = x * cdf;
+  gp = cdf + x * 0.39894228040143268f * __expf(-0.5f * x * x);
+}
+
 // log(1 + exp(x)) without overflow.
 __device__ __forceinline__ float softplus(float x) { return fmaxf(x, 0.0f) + log1pf(__expf(-fabsf(x))); }
 

@@ -41,6 +41,7 @@ struct fvan_model {
     float* DELTA = nullptr;        // [rows][H] dO . O per head (backward)
     float* TMP = nullptr;          // [rows][D] LayerNorm-output gradients (backward)
     void* T_c = nullptr;           // [(D+16)][ldT] feature-major LN outputs (+ ones row) for weight gradients
+    void* T_d = nullptr;           // [D][ldT] feature-major gradient at a block's output (left operand of dW2)
     int64_t ldT = 0;               // row stride of the feature-major buffers (rows rounded up to 64)
     void* QKV = nullptr;           // [n_layers][rows][3D] (K/V element type)
     float* HPRE = nullptr;         // [rows][4D] FFN pre-activation (backward)

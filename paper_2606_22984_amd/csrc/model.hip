@@ -59,6 +59,7 @@ static int allocate_fwd(fvan_model* m, hipStream_t s) {
       {&f.dQKV, R * 3 * D * 4, "dQKV"},                   {&f.dH, R * 4 * D * 4, "dH"},
       {&f.T_a, 4 * D * ldT * 4, "T_a"},
       {&f.T_b, (4 * D + 16) * ldT * 4, "T_b"},            {&f.T_c, (D + 16) * ldT * 4, "T_c"},
+      {&f.T_d, D * ldT * 4, "T_d"},
       {(void**)&f.part, f.part_floats * 4, "partials"},   {(void**)&f.colpart, f.colpart_floats * 4, "column partials"},
       {(void**)&f.colpart2, (size_t)64 * std::max<size_t>(2 * D + 2, (size_t)c.vocab * c.d_token) * 4,
        "column slices"},
@@ -149,7 +150,7 @@ void model_free_fwd(fvan_model* m) {
   auto& f = m->fw;
   dfree(f.X); dfree(f.XM); dfree(f.LSE); dfree(f.DELTA); dfree(f.TMP);
   dfree(f.QKV); dfree(f.HPRE); dfree(f.logp); dfree(f.dX); dfree(f.dXM); dfree(f.dQKV); dfree(f.dH);
-  dfree(f.T_a); dfree(f.T_b); dfree(f.T_c); dfree(f.part); dfree(f.colpart); dfree(f.colpart2);
+  dfree(f.T_a); dfree(f.T_b); dfree(f.T_c); dfree(f.T_d); dfree(f.part); dfree(f.colpart); dfree(f.colpart2);
   m->fw = fvan_model::Fwd();
 }
 

@@ -415,6 +415,270 @@ __global__ __launch_bounds__(256) void ffn_fused_kernel(const float* __restrict_
   }
 }
 
+// Fused feed-forward backward of one layer, with the block's forward recomputed
+// in place (x = the post-attention residual XM, dY = the gradient arriving at
+// the block's output):
+//   a = LN2(x), h = W1 a + b1, g = GELU(h)             (recompute)
+//   dG = W2^T dY, dH = dG * GELU'(h), dA = W1^T dH      (back through W2, GELU, W1)
+//   out = dY + LN2'(dA)                                 (LayerNorm backward and the residual)
+// plus the feature-major operands of the weight gradients, Gt = g^T and
+// dHt = dH^T [4D x ldT], At = a^T and dYt = dY^T [D x ldT], and per-workgroup
+// partial sums of the LN2 gain and shift gradients (part[block][2D]).
+// 128 rows per workgroup, one 16-row MFMA tile per wave (8 waves).  The hidden
+// layer is walked 32 units at a time: the chunk's weight fragments (rows of W1
+// and W2^T, columns of W1^T) are staged in LDS once for all eight waves, the
+// next chunk's are fetched into registers meanwhile, and each wave's h, g and
+// dH go through a wave-private LDS tile; they reach HBM only as the two
+// feature-major weight-gradient operands.  (One wave loading every weight for
+// its own 16 rows made the kernel bound by L2 reads of the weights.)
+// p1: W1 [4D x D] pack; p2t: W2^T [4D x D] pack; p1t: W1^T [D x 4D] pack.
+constexpr int kFfnBwdRows = 128;
+
+template <int MODE, int D>
+__global__ __launch_bounds__(512) void ffn_bwd_fused_kernel(
+    const float* __restrict__ X, const float* __restrict__ dY, const float* __restrict__ ln_g,
+    const float* __restrict__ ln_b, int64_t rows, const uint4* __restrict__ p1, const uint4* __restrict__ p2t,
+    const uint4* __restrict__ p1t, const float* __restrict__ b1, typename Mode<MODE>::ActT* __restrict__ Gt,
+    typename Mode<MODE>::ActT* __restrict__ dHt, typename Mode<MODE>::ActT* __restrict__ At,
+    typename Mode<MODE>::ActT* __restrict__ dYt, int64_t ldT, float* __restrict__ out, float* __restrict__ part) {
+  typedef typename Mode<MODE>::ActT AT;
+  static_assert(sizeof(AT) == 4, "FP32 activations");
+  constexpr int NW = 8;                      // waves
+  constexpr int KC = Mode<MODE>::KC;
+  constexpr int LK = KC / 4;
+  constexpr int NPL = Mode<MODE>::SPLIT ? 2 : 1;   // weight planes (hi, lo)
+  constexpr int NC1 = D / KC;                // K chunks of the D-wide products
+  constexpr int HC = 32;                     // hidden units per chunk
+  constexpr int NH = 4 * D / HC;
+  constexpr int NT1 = HC / 16;               // h / dG tiles per chunk
+  constexpr int NT2 = D / 16;                // output tiles of dA
+  constexpr int NC2 = 4 * D / KC;            // K chunks of the dA product
+  constexpr int NC2H = HC / KC;              // ... per hidden chunk
+  constexpr size_t LO = (size_t)4 * D * D / 8;
+  constexpr int S1 = NT1 * NC1 * 64;         // fragments of a W1 (or W2^T) chunk, per plane
+  constexpr int S3 = NT2 * NC2H * 64;        // fragments of a W1^T chunk, per plane
+  constexpr int SW = 2 * S1 + S3;
+  constexpr int NPRE = (NPL * SW + 64 * NW - 1) / (64 * NW);   // staged fragments per thread
+  constexpr int LDH = HC + 4;
+  __shared__ __align__(16) uint4 Ws[NPL][SW];      // [W1 chunk | W2^T chunk | W1^T chunk]
+  __shared__ __align__(16) float Hg[NW][16][LDH];
+  __shared__ __align__(16) float Hd[NW][16][LDH];
+  __shared__ float red[NW][2 * D];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
+  const int64_t rbase = (int64_t)blockIdx.x * kFfnBwdRows + wave * 16;
+  const bool full = rbase + 16 <= rows;
+  // staged fragment idx (plane pl, slot j) -> its place in the packs
+  auto src = [&](int hc, int idx) -> const uint4* {
+    const int pl = idx / SW, j = idx % SW;
+    const size_t lo = pl ? LO : 0;
+    if (j < S1) return p1 + (size_t)hc * S1 + j + lo;
+    if (j < 2 * S1) return p2t + (size_t)hc * S1 + (j - S1) + lo;
+    const int k = j - 2 * S1, t2 = k / (NC2H * 64), rest = k % (NC2H * 64);
+    return p1t + ((size_t)t2 * NC2 + (size_t)hc * NC2H) * 64 + rest + lo;
+  };
+  // the next chunk's fragments, held in registers (p0..p5) between the fetch and the commit
+  static_assert(NPRE <= 6, "at most six staged fragments per thread");
+  uint4 p0{}, p1r{}, p2r{}, p3{}, p4{}, p5{};
+#define FVAN_FB_FETCH(hc)                                                            \
+  do {                                                                               \
+    const int i0 = tid;                                                              \
+    if (NPRE > 0 && i0 < NPL * SW) p0 = *src(hc, i0);                                \
+    if (NPRE > 1 && i0 + 512 < NPL * SW) p1r = *src(hc, i0 + 512);                   \
+    if (NPRE > 2 && i0 + 1024 < NPL * SW) p2r = *src(hc, i0 + 1024);                 \
+    if (NPRE > 3 && i0 + 1536 < NPL * SW) p3 = *src(hc, i0 + 1536);                  \
+    if (NPRE > 4 && i0 + 2048 < NPL * SW) p4 = *src(hc, i0 + 2048);                  \
+    if (NPRE > 5 && i0 + 2560 < NPL * SW) p5 = *src(hc, i0 + 2560);                  \
+  } while (0)
+#define FVAN_FB_COMMIT()                                                             \
+  do {                                                                               \
+    uint4* w = &Ws[0][0];                                                            \
+    if (NPRE > 0 && tid < NPL * SW) w[tid] = p0;                                     \
+    if (NPRE > 1 && tid + 512 < NPL * SW) w[tid + 512] = p1r;                        \
+    if (NPRE > 2 && tid + 1024 < NPL * SW) w[tid + 1024] = p2r;                      \
+    if (NPRE > 3 && tid + 1536 < NPL * SW) w[tid + 1536] = p3;                       \
+    if (NPRE > 4 && tid + 2048 < NPL * SW) w[tid + 2048] = p4;                       \
+    if (NPRE > 5 && tid + 2560 < NPL * SW) w[tid + 2560] = p5;                       \
+  } while (0)
+  static_assert(64 * NW == 512, "staging strides assume 512 threads");
+  FVAN_FB_FETCH(0);
+  // A fragments of the wave's rows (clamped; every output below is guarded)
+  const int64_t ra = std::min<int64_t>(rbase + c, rows - 1);
+  FragA<MODE> fa[NC1], fy[NC1];
+  load_ln_frags<MODE, D>(X, ra, ln_g, ln_b, g, fa);
+#pragma unroll
+  for (int cc = 0; cc < NC1; ++cc) {
+    alignas(16) AT af[LK];
+#pragma unroll
+    for (int i = 0; i < LK; i += 4)
+      *reinterpret_cast<float4*>(&af[i]) = *reinterpret_cast<const float4*>(dY + ra * D + cc * KC + g * LK + i);
+    fy[cc].load(af);
+  }
+  FVAN_FB_COMMIT();
+  __syncthreads();
+  if (NH > 1) FVAN_FB_FETCH(1);
+  floatx4 acc[NT2];
+#pragma unroll
+  for (int t = 0; t < NT2; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float (*HG)[LDH] = Hg[wave];
+  float (*HD)[LDH] = Hd[wave];
+  const uint4* W1s = &Ws[0][0];
+  const uint4* W2s = &Ws[0][S1];
+  const uint4* W3s = &Ws[0][2 * S1];
+  constexpr int PLO = NPL > 1 ? SW : 0;      // hi-to-lo distance in the stage
+  for (int hc = 0; hc < NH; ++hc) {
+#pragma unroll
+    for (int t = 0; t < NT1; ++t) {
+      floatx4 ah = {0.f, 0.f, 0.f, 0.f}, ag = ah;
+#pragma unroll
+      for (int cc = 0; cc < NC1; ++cc) {
+        const int f = (t * NC1 + cc) * 64 + lane;
+        ah = fa[cc].mma(W1s + f, W1s + f + PLO, ah);
+        ag = fy[cc].mma(W2s + f, W2s + f + PLO, ag);
+      }
+      const float bias = b1[hc * HC + t * 16 + c];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float gv, gp;
+        gelu_and_grad(ah[i] + bias, gv, gp);
+        HG[4 * g + i][16 * t + c] = gv;
+        HD[4 * g + i][16 * t + c] = ag[i] * gp;
+      }
+    }
+    wave_lds_sync();
+    // dA += dH_chunk W1^T_chunk
+#pragma unroll
+    for (int cc = 0; cc < NC2H; ++cc) {
+      FragA<MODE> hd;
+      hd.load(&HD[c][cc * KC + g * LK]);
+#pragma unroll
+      for (int t = 0; t < NT2; ++t) {
+        const int f = (t * NC2H + cc) * 64 + lane;
+        acc[t] = hd.mma(W3s + f, W3s + f + PLO, acc[t]);
+      }
+    }
+    // feature-major g and dH: lane -> (hidden unit lane % 32, rows 8 (lane / 32) .. +7)
+    {
+      const int u = lane & 31, q0 = (lane >> 5) * 8;
+      const int64_t n = (int64_t)hc * HC + u;
+      AT* gp = Gt + n * ldT + rbase + q0;
+      AT* dp = dHt + n * ldT + rbase + q0;
+      if (full) {
+#pragma unroll
+        for (int q = 0; q < 8; q += 4) {
+          *reinterpret_cast<float4*>(gp + q) =
+              make_float4(HG[q0 + q][u], HG[q0 + q + 1][u], HG[q0 + q + 2][u], HG[q0 + q + 3][u]);
+          *reinterpret_cast<float4*>(dp + q) =
+              make_float4(HD[q0 + q][u], HD[q0 + q + 1][u], HD[q0 + q + 2][u], HD[q0 + q + 3][u]);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (rbase + q0 + q < rows) {
+            gp[q] = HG[q0 + q][u];
+            dp[q] = HD[q0 + q][u];
+          }
+      }
+    }
+    __syncthreads();                         // every wave is done with this chunk's weights and tiles
+    if (hc + 1 < NH) {
+      FVAN_FB_COMMIT();
+      __syncthreads();
+      if (hc + 2 < NH) FVAN_FB_FETCH(hc + 2);
+    }
+  }
+  // LN2 backward on the wave's rows: lane (g, c) holds dA of rows 4g+i, columns 16t+c
+  float xh[NT2][4], dyv[NT2][4];
+  bool live[4];
+  float rstd[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t r = rbase + 4 * g + i;
+    live[i] = r < rows;
+    const int64_t rr = std::min<int64_t>(r, rows - 1);
+    float s = 0.f;
+#pragma unroll
+    for (int t = 0; t < NT2; ++t) {
+      xh[t][i] = X[rr * D + 16 * t + c];
+      dyv[t][i] = dY[rr * D + 16 * t + c];
+      s += xh[t][i];
+    }
+    const float mean = row_sum16(s) * (1.0f / D);
+    float q = 0.f;
+#pragma unroll
+    for (int t = 0; t < NT2; ++t) {
+      xh[t][i] -= mean;
+      q += xh[t][i] * xh[t][i];
+    }
+    rstd[i] = rsqrtf(row_sum16(q) * (1.0f / D) + kLnEps);
+#pragma unroll
+    for (int t = 0; t < NT2; ++t) xh[t][i] *= rstd[i];
+  }
+  float s1[4] = {0.f, 0.f, 0.f, 0.f}, s2[4] = {0.f, 0.f, 0.f, 0.f};
+  float pg[NT2], pb[NT2];
+#pragma unroll
+  for (int t = 0; t < NT2; ++t) {
+    const int k = 16 * t + c;
+    const float gk = ln_g[k], bk = ln_b[k];
+    pg[t] = 0.f;
+    pb[t] = 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float a = live[i] ? acc[t][i] : 0.f;
+      pg[t] += a * xh[t][i];
+      pb[t] += a;
+      acc[t][i] = a * gk;                    // now dy = dA * gain
+      s1[i] += acc[t][i];
+      s2[i] += acc[t][i] * xh[t][i];
+    }
+    // feature-major LN2 output and dY (four consecutive rows per lane)
+    AT* ap = At + (int64_t)k * ldT + rbase + 4 * g;
+    AT* yp = dYt + (int64_t)k * ldT + rbase + 4 * g;
+    if (full) {
+      *reinterpret_cast<float4*>(ap) = make_float4(xh[t][0] * gk + bk, xh[t][1] * gk + bk, xh[t][2] * gk + bk,
+                                                   xh[t][3] * gk + bk);
+      *reinterpret_cast<float4*>(yp) = make_float4(dyv[t][0], dyv[t][1], dyv[t][2], dyv[t][3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (live[i]) {
+          ap[i] = xh[t][i] * gk + bk;
+          yp[i] = dyv[t][i];
+        }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    s1[i] = row_sum16(s1[i]) * (1.0f / D);
+    s2[i] = row_sum16(s2[i]) * (1.0f / D);
+  }
+#pragma unroll
+  for (int t = 0; t < NT2; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = rbase + 4 * g + i;
+      if (live[i]) out[r * D + 16 * t + c] = dyv[t][i] + rstd[i] * (acc[t][i] - s1[i] - xh[t][i] * s2[i]);
+    }
+  // the workgroup's partial sums of the gain and shift gradients
+#pragma unroll
+  for (int t = 0; t < NT2; ++t) {
+    pg[t] = sum_xor32(sum_xor16(pg[t]));
+    pb[t] = sum_xor32(sum_xor16(pb[t]));
+    if (g == 0) {
+      red[wave][16 * t + c] = pg[t];
+      red[wave][D + 16 * t + c] = pb[t];
+    }
+  }
+  __syncthreads();
+  for (int k = tid; k < 2 * D; k += 64 * NW) {
+    float sum = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) sum += red[w][k];
+    part[(size_t)blockIdx.x * 2 * D + k] = sum;
+  }
+#undef FVAN_FB_FETCH
+#undef FVAN_FB_COMMIT
+}
+
 template <int MODE, int K, int NOUT, int EPI>
 inline hipError_t gemm_rows(const typename Mode<MODE>::ActT* A, int64_t rows, const void* pack, const EpiArgs& e,
                             hipStream_t s) {
