@@ -217,7 +217,7 @@ hipError_t forward_layer(fvan_model* m, int l, int64_t rows, int nsamp, hipStrea
       hipLaunchKernelGGL((attn_fwd_gen<KT, 64>), dim3(ggrid), dim3(kGenThreads), 0, s, (const KT*)QKV, X, XM, LSE,
                          c.n_spins, D, H, c.window, m->kg.P);
   }
-  hipLaunchKernelGGL((ffn_fused_kernel<MODE, D>), dim3((int)((rows + kFfnRows - 1) / kFfnRows)), dim3(256), 0, s,
+  hipLaunchKernelGGL((ffn_fused_kernel<MODE, D>), dim3((int)((rows + kFfnRows - 1) / kFfnRows)), dim3(512), 0, s,
                      (const float*)XM, lp + m->po.ln2_g, lp + m->po.ln2_b, rows,
                      reinterpret_cast<const uint4*>(wl + m->pk.ffn1), reinterpret_cast<const uint4*>(wl + m->pk.ffn2),
                      lp + m->po.ffn1_b, lp + m->po.ffn2_b, (const float*)XM, Xn);

@@ -323,11 +323,15 @@ __global__ __launch_bounds__(256) void gemm_rows_staged_kernel(const typename Mo
 }
 
 // Fused feed-forward block of the teacher-forced forward pass:
-//   out[r] = resid[r] + W2 GELU(W1 a[r] + b1) + b2,   W1 [4D x D], W2 [D x 4D].
-// 128 rows per workgroup, one wave per 32 rows (two 16-row MFMA tiles, so every
-// weight fragment a wave loads feeds both).  A wave's hidden activations go
-// through a wave-private LDS tile, 64 hidden units at a time, straight into the
-// W2 product, so the 4D-wide hidden layer never reaches HBM.
+//   out[r] = resid[r] + W2 GELU(W1 a[r] + b1) + b2,   W1 [4D x D], W2 [D x 4D],
+// a[r] = LayerNorm(X rows; ln_g, ln_b) computed in the kernel.
+// 128 rows per workgroup, one 16-row MFMA tile per wave (8 waves).  The hidden
+// layer is walked 32 units at a time: the chunk's fragments of W1 (its rows)
+// and W2 (its columns) are staged in LDS once for all eight waves, the next
+// chunk's fetched into registers meanwhile, and each wave's hidden activations
+// go through a wave-private LDS tile straight into the W2 product, so the
+// 4D-wide hidden layer never reaches HBM.  (Each wave loading every weight for
+// its own rows made the kernel bound by L2 reads of the weights.)
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -335,83 +339,114 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 constexpr int kFfnRows = 128;                // rows per fused-FFN workgroup
 
-// The input rows are LayerNorm(X rows; ln_g, ln_b), computed in the kernel.
 template <int MODE, int D>
-__global__ __launch_bounds__(256) void ffn_fused_kernel(const float* __restrict__ X, const float* __restrict__ ln_g,
+__global__ __launch_bounds__(512, 4) void ffn_fused_kernel(const float* __restrict__ X, const float* __restrict__ ln_g,
                                                         const float* __restrict__ ln_b, int64_t rows,
                                                         const uint4* __restrict__ p1, const uint4* __restrict__ p2,
                                                         const float* __restrict__ b1, const float* __restrict__ b2,
                                                         const float* __restrict__ resid, float* __restrict__ out) {
   typedef typename Mode<MODE>::ActT AT;
+  constexpr int NW = 8;                      // waves
   constexpr int KC = Mode<MODE>::KC;
-  constexpr int LK = KC / 4;                 // A elements per lane per chunk
+  constexpr int LK = KC / 4;
+  constexpr int NPL = Mode<MODE>::SPLIT ? 2 : 1;   // weight planes (hi, lo)
   constexpr int NC1 = D / KC;                // K chunks of the W1 product
-  constexpr int HC = 64;                     // hidden units per chunk
-  constexpr int NH = 4 * D / HC;             // hidden chunks
-  constexpr int NT1 = HC / 16;               // W1 output tiles per hidden chunk
+  constexpr int HC = 32;                     // hidden units per chunk
+  constexpr int NH = 4 * D / HC;
+  constexpr int NT1 = HC / 16;               // W1 output tiles per chunk
   constexpr int NT2 = D / 16;                // W2 output tiles
   constexpr int NC2 = 4 * D / KC;            // K chunks of the W2 product
   constexpr int NC2H = HC / KC;              // ... per hidden chunk
   constexpr size_t LO = (size_t)4 * D * D / 8;   // hi-to-lo distance of a split pack (both matrices 4D^2)
-  constexpr int LDH = HC + 16 / (int)sizeof(AT);
-  __shared__ __align__(16) AT Hs[4][32][LDH];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
-  const int64_t rbase = (int64_t)blockIdx.x * kFfnRows + wave * 32;
-  if (rbase >= rows) return;                 // no block-wide barrier below
-  FragA<MODE> fa[2][NC1];                    // both row tiles' A fragments, converted once
+  constexpr int S1 = NT1 * NC1 * 64;         // fragments of a W1 chunk, per plane
+  constexpr int S2 = NT2 * NC2H * 64;        // fragments of a W2 chunk, per plane
+  constexpr int SW = S1 + S2;
+  constexpr int NPRE = (NPL * SW + 64 * NW - 1) / (64 * NW);
+  static_assert(NPRE <= 4, "at most four staged fragments per thread");
+  static_assert(64 * NW == 512, "staging strides assume 512 threads");
+  constexpr int LDH = HC + 4;
+  __shared__ __align__(16) uint4 Ws[NPL][SW];      // [W1 chunk | W2 chunk]
+  __shared__ __align__(16) AT Hs[NW][16][LDH];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
+  const int64_t rbase = (int64_t)blockIdx.x * kFfnRows + wave * 16;
+  auto src = [&](int hc, int idx) -> const uint4* {
+    const int pl = idx / SW, j = idx % SW;
+    const size_t lo = pl ? LO : 0;
+    if (j < S1) return p1 + (size_t)hc * S1 + j + lo;
+    const int k = j - S1, t2 = k / (NC2H * 64), rest = k % (NC2H * 64);
+    return p2 + ((size_t)t2 * NC2 + (size_t)hc * NC2H) * 64 + rest + lo;
+  };
+  uint4 q0{}, q1{}, q2{}, q3{};
+#define FVAN_FF_FETCH(hc)                                                            \
+  do {                                                                               \
+    if (NPRE > 0 && tid < NPL * SW) q0 = *src(hc, tid);                              \
+    if (NPRE > 1 && tid + 512 < NPL * SW) q1 = *src(hc, tid + 512);                  \
+    if (NPRE > 2 && tid + 1024 < NPL * SW) q2 = *src(hc, tid + 1024);                \
+    if (NPRE > 3 && tid + 1536 < NPL * SW) q3 = *src(hc, tid + 1536);                \
+  } while (0)
+#define FVAN_FF_COMMIT()                                                             \
+  do {                                                                               \
+    uint4* w = &Ws[0][0];                                                            \
+    if (NPRE > 0 && tid < NPL * SW) w[tid] = q0;                                     \
+    if (NPRE > 1 && tid + 512 < NPL * SW) w[tid + 512] = q1;                         \
+    if (NPRE > 2 && tid + 1024 < NPL * SW) w[tid + 1024] = q2;                       \
+    if (NPRE > 3 && tid + 1536 < NPL * SW) w[tid + 1536] = q3;                       \
+  } while (0)
+  FVAN_FF_FETCH(0);
+  FragA<MODE> fa[NC1];                       // the wave's A fragments, converted once (rows clamped)
+  load_ln_frags<MODE, D>(X, std::min<int64_t>(rbase + c, rows - 1), ln_g, ln_b, g, fa);
+  floatx4 acc2[NT2];
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
-    load_ln_frags<MODE, D>(X, std::min<int64_t>(rbase + 16 * rt + c, rows - 1), ln_g, ln_b, g, fa[rt]);
-  floatx4 acc2[2][NT2];
-#pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-    for (int t = 0; t < NT2; ++t) acc2[rt][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < NT2; ++t) acc2[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  FVAN_FF_COMMIT();
+  __syncthreads();
+  if (NH > 1) FVAN_FF_FETCH(1);
   AT (*H)[LDH] = Hs[wave];
+  const uint4* W1s = &Ws[0][0];
+  const uint4* W2s = &Ws[0][S1];
+  constexpr int PLO = NPL > 1 ? SW : 0;      // hi-to-lo distance in the stage
   for (int hc = 0; hc < NH; ++hc) {
 #pragma unroll
     for (int t = 0; t < NT1; ++t) {
-      const int nt = hc * NT1 + t;
-      floatx4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0;
-      const uint4* bp = p1 + (size_t)nt * NC1 * 64 + lane;
+      floatx4 a0 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int cc = 0; cc < NC1; ++cc) {
-        a0 = fa[0][cc].mma(bp + cc * 64, bp + cc * 64 + LO, a0);
-        a1 = fa[1][cc].mma(bp + cc * 64, bp + cc * 64 + LO, a1);
+        const int f = (t * NC1 + cc) * 64 + lane;
+        a0 = fa[cc].mma(W1s + f, W1s + f + PLO, a0);
       }
-      const float bias = b1[nt * 16 + c];
+      const float bias = b1[hc * HC + t * 16 + c];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        H[4 * g + i][t * 16 + c] = from_f<AT>(gelu(a0[i] + bias));
-        H[16 + 4 * g + i][t * 16 + c] = from_f<AT>(gelu(a1[i] + bias));
-      }
+      for (int i = 0; i < 4; ++i) H[4 * g + i][t * 16 + c] = from_f<AT>(gelu(a0[i] + bias));
     }
     wave_lds_sync();
 #pragma unroll
     for (int cc = 0; cc < NC2H; ++cc) {
-      FragA<MODE> h0, h1;
+      FragA<MODE> h0;
       h0.load(&H[c][cc * KC + g * LK]);
-      h1.load(&H[16 + c][cc * KC + g * LK]);
 #pragma unroll
       for (int t = 0; t < NT2; ++t) {
-        const uint4* bp = p2 + ((size_t)t * NC2 + hc * NC2H + cc) * 64 + lane;
-        acc2[0][t] = h0.mma(bp, bp + LO, acc2[0][t]);
-        acc2[1][t] = h1.mma(bp, bp + LO, acc2[1][t]);
+        const int f = (t * NC2H + cc) * 64 + lane;
+        acc2[t] = h0.mma(W2s + f, W2s + f + PLO, acc2[t]);
       }
     }
-    wave_lds_sync();                         // the next chunk overwrites H
+    __syncthreads();                         // every wave is done with this chunk's weights and tiles
+    if (hc + 1 < NH) {
+      FVAN_FF_COMMIT();
+      __syncthreads();
+      if (hc + 2 < NH) FVAN_FF_FETCH(hc + 2);
+    }
   }
+#undef FVAN_FF_FETCH
+#undef FVAN_FF_COMMIT
 #pragma unroll
   for (int t = 0; t < NT2; ++t) {
     const int n = t * 16 + c;
     const float bias = b2[n];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t r = rbase + 16 * rt + 4 * g + i;
-        if (r < rows) out[r * D + n] = resid[r * D + n] + acc2[rt][t][i] + bias;
-      }
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = rbase + 4 * g + i;
+      if (r < rows) out[r * D + n] = resid[r * D + n] + acc2[t][i] + bias;
+    }
   }
 }
 
