@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 --pmc runs, each scaled by the same counter's reading for a 1 GiB copy);
 # the record with the commands is profiles/decode_ea3d_L10_hbm_counters.md.
 # Set to None whenever decode_kernel changes until the counters are taken again.
-DECODE_TRAFFIC_BYTES = 12353908217037
+DECODE_TRAFFIC_BYTES = 12353910745088
 # learning rate: the paper's eta = 1e-3 reached by a linear warm-up over 300 steps
 # (Methods, model configurations and training settings); the timed steps sit at
 # the start of the warm-up
@@ -360,7 +360,7 @@ def main():
     achieved = bytes_launch / (head["decode_ms"] * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": DECODE_TRAFFIC_BYTES,
-            "kernel": "decode_kernel<128,2>", "algorithmic_bytes_per_launch": bytes_launch}
+            "kernel": "decode_kernel<128,2,16,false,32>", "algorithmic_bytes_per_launch": bytes_launch}
 
     extra = None
     if not args.no_extra:
