@@ -52,7 +52,13 @@ PackOffsets pack_offsets(const fvan_model_config& c) {
   p.ffn1T = p.qkvT + 3 * d * d * e;
   p.ffn2T = p.ffn1T + 4 * d * d * e;
   p.layer_stride = p.ffn2T + 4 * d * d * e;
-  p.total = p.layer_stride * c.n_layers;
+  p.head = p.headT = p.total = p.layer_stride * c.n_layers;
+  p.vp = 0;
+  if (c.vocab > 2) {
+    p.vp = (c.vocab + 31) / 32 * 32;
+    p.headT = p.head + (size_t)p.vp * d * e;
+    p.total = p.headT + d * (size_t)p.vp * e;
+  }
   return p;
 }
 

@@ -481,15 +481,29 @@ __global__ __launch_bounds__(256) void ln_bwd_kernel(const float* __restrict__ d
 }
 
 // ---------------------------------------------------------------- embedding
-// dP[t][k] += sum_b dX0[b*N + t][dt + k]: one thread per (t, k), samples summed in order.
-__global__ void pos_grad_kernel(const float* __restrict__ dX, int nsamp, int N, int D, int dt,
-                                float* __restrict__ gpos) {
+// dP[t][k] += sum_b dX0[b*N + t][dt + k], in two fixed-order steps: workgroup
+// column y sums the samples of its slice for every (t, k) into part[y][t][k],
+// then pos_grad_final adds the slices in order.
+constexpr int kPosSlices = 32;
+__global__ void pos_grad_slices_kernel(const float* __restrict__ dX, int nsamp, int N, int D, int dt,
+                                       float* __restrict__ part) {
   const int dp = D - dt;
   const int64_t total = (int64_t)N * dp;
+  const int per = (nsamp + gridDim.y - 1) / gridDim.y;
+  const int b0 = blockIdx.y * per, b1 = min(nsamp, b0 + per);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int t = (int)(i / dp), k = (int)(i % dp);
     float s = 0.f;
-    for (int b = 0; b < nsamp; ++b) s += dX[((int64_t)b * N + t) * D + dt + k];
+    for (int b = b0; b < b1; ++b) s += dX[((int64_t)b * N + t) * D + dt + k];
+    part[(size_t)blockIdx.y * total + i] = s;
+  }
+}
+
+__global__ void pos_grad_final_kernel(const float* __restrict__ part, int slices, int64_t total,
+                                      float* __restrict__ gpos) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int y = 0; y < slices; ++y) s += part[(size_t)y * total + i];
     gpos[i] += s;
   }
 }
@@ -525,98 +539,130 @@ __global__ __launch_bounds__(256) void tok_grad_slices_kernel(const float* __res
 }
 
 // ---------------------------------------------------------------- vocab-way head (patch tokens)
-// One workgroup per sample, positions kHbPos at a time: z = W_h h + b, p =
-// softmax(z) and dz = w_b (onehot(tok) - p), the gradient of w_b ln p_t(tok_t)
-// (a token >= vocab makes its sample's dz NaN); dX = W_h^T dz, and dz written
-// feature-major into dZT [mrows][ldT] (rows v >= vocab zero) for the head's
-// weight-gradient GEMM.
-constexpr int kHbThreads = 256, kHbPos = 16;
-template <int D>
-__global__ __launch_bounds__(kHbThreads) void head_vocab_bwd_kernel(const float* __restrict__ X,
-                                                                    const float* __restrict__ theta, int64_t head_w,
-                                                                    int64_t head_b, int V, int mrows,
-                                                                    const uint8_t* __restrict__ tokens,
-                                                                    const float* __restrict__ w, int N,
-                                                                    float* __restrict__ dX, float* __restrict__ dZT,
-                                                                    int64_t ldT) {
-  constexpr int NW = kHbThreads / 64;
-  __shared__ __align__(16) float xs[kHbPos][D];
-  __shared__ float dzs[kHbPos][kHbThreads + 1];
-  __shared__ float wmax[kHbPos][NW], wsum[kHbPos][NW];
-  const int b = blockIdx.x, v = threadIdx.x, lane = v & 63, wave = v >> 6;
-  const bool live = v < V;
-  const float* wrow = theta + head_w + (int64_t)(live ? v : 0) * D;
-  const float bias = live ? theta[head_b + v] : 0.f;
-  const float wb = w[b];
-  for (int t0 = 0; t0 < N; t0 += kHbPos) {
-    const int np = min(kHbPos, N - t0);
-    const int64_t r0 = (int64_t)b * N + t0;
-    for (int i = v; i < kHbPos * D; i += kHbThreads) {
-      const int p = i / D, k = i % D;
-      xs[p][k] = p < np ? X[(r0 + p) * D + k] : 0.f;
+// 64 rows (positions) per workgroup, one 16-row MFMA tile per wave:
+//   z = W_h h + b_h (MFMA against the padded head pack [vp x D]); p = softmax(z)
+//   per row (the row's vp logits sit in 16 lanes x vp/16 tiles); dz = w_b
+//   (onehot(tok) - p), the gradient of w_b ln p_t(tok_t) (a token >= vocab makes
+//   its row's dz NaN); dz written feature-major into dZT [mrows][ldT] (rows >=
+//   vocab zero) for the head's weight-gradient GEMM, and through a wave-private
+//   LDS tile into dX = W_h^T dz (MFMA against the transposed pack [D x vp]).
+constexpr int kHbRows = 64;
+template <int MODE, int D, int VP>
+__global__ __launch_bounds__(256) void head_vocab_bwd_kernel(const float* __restrict__ X, const uint4* __restrict__ ph,
+                                                             const uint4* __restrict__ phT,
+                                                             const float* __restrict__ hb, int V, int mrows,
+                                                             const uint8_t* __restrict__ tokens,
+                                                             const float* __restrict__ w, int N, int64_t rows,
+                                                             float* __restrict__ dX, float* __restrict__ dZT,
+                                                             int64_t ldT) {
+  typedef typename Mode<MODE>::ActT AT;
+  constexpr int KC = Mode<MODE>::KC;
+  constexpr int LK = KC / 4;
+  constexpr int NC = D / KC;                 // K chunks of z = h W_h^T
+  constexpr int NZ = VP / 16;                // logit tiles
+  constexpr int NC2 = VP / KC;               // K chunks of dX = dz W_h
+  constexpr int NX = D / 16;                 // dX tiles
+  constexpr size_t LO1 = (size_t)VP * D / 8, LO2 = LO1;
+  constexpr int LDZ = VP + 4;
+  __shared__ __align__(16) float Zs[4][16][LDZ];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+  const int64_t rbase = (int64_t)blockIdx.x * kHbRows + wave * 16;
+  if (rbase >= rows) return;                 // no block-wide barrier below
+  FragA<MODE> fa[NC];
+  {
+    const int64_t ra = std::min<int64_t>(rbase + c, rows - 1);
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+      alignas(16) AT af[LK];
+#pragma unroll
+      for (int i = 0; i < LK; i += 4)
+        *reinterpret_cast<float4*>(&af[i]) = *reinterpret_cast<const float4*>(X + ra * D + cc * KC + g * LK + i);
+      fa[cc].load(af);
     }
-    __syncthreads();
-    float z[kHbPos];
-#pragma unroll
-    for (int p = 0; p < kHbPos; ++p) z[p] = -INFINITY;
-    if (live) {
-      float a[kHbPos];
-#pragma unroll
-      for (int p = 0; p < kHbPos; ++p) a[p] = 0.f;
-#pragma unroll 4
-      for (int k = 0; k < D; ++k) {
-        const float wk = wrow[k];
-#pragma unroll
-        for (int p = 0; p < kHbPos; ++p) a[p] += wk * xs[p][k];
-      }
-#pragma unroll
-      for (int p = 0; p < kHbPos; ++p) z[p] = a[p] + bias;
-    }
-    float mxs[kHbPos];
-#pragma unroll
-    for (int p = 0; p < kHbPos; ++p) {
-      float mm = z[p];
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) mm = fmaxf(mm, __shfl_xor(mm, o, 64));
-      if (lane == 0) wmax[p][wave] = mm;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < kHbPos; ++p) {
-      float mx = wmax[p][0];
-#pragma unroll
-      for (int q = 1; q < NW; ++q) mx = fmaxf(mx, wmax[p][q]);
-      mxs[p] = mx;
-      z[p] = live ? expf(z[p] - mx) : 0.f;
-      float e = z[p];
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
-      if (lane == 0) wsum[p][wave] = e;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < kHbPos; ++p) {
-      float tot = 0.f;
-#pragma unroll
-      for (int q = 0; q < NW; ++q) tot += wsum[p][q];
-      const int tk = p < np ? (int)tokens[r0 + p] : 0;
-      float dz = 0.f;
-      if (live) dz = tk < V ? wb * ((v == tk ? 1.f : 0.f) - z[p] / tot) : __builtin_nanf("");
-      dzs[p][v] = dz;
-      if (p < np && v < mrows) dZT[(int64_t)v * ldT + r0 + p] = dz;
-    }
-    __syncthreads();
-    for (int i = v; i < kHbPos * D; i += kHbThreads) {
-      const int p = i / D, k = i % D;
-      if (p < np) {
-        const float* wc = theta + head_w + k;
-        float acc = 0.f;
-        for (int vv = 0; vv < V; ++vv) acc += dzs[p][vv] * wc[(int64_t)vv * D];
-        dX[(r0 + p) * D + k] = acc;
-      }
-    }
-    __syncthreads();                                 // xs, dzs and the partials are rewritten next
   }
+  floatx4 z[NZ];
+#pragma unroll
+  for (int t = 0; t < NZ; ++t) {
+    z[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const uint4* bp = ph + (size_t)t * NC * 64 + lane;
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) z[t] = fa[cc].mma(bp + cc * 64, bp + cc * 64 + LO1, z[t]);
+  }
+  // softmax of each row: lane (g, c) holds logits of rows 4g+i at columns 16t+c
+  float mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+  for (int t = 0; t < NZ; ++t) {
+    const int col = 16 * t + c;
+    const float bias = col < V ? hb[col] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      z[t][i] = col < V ? z[t][i] + bias : -INFINITY;
+      mx[i] = fmaxf(mx[i], z[t][i]);
+    }
+  }
+  float sum[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) mx[i] = row_max16(mx[i]);
+#pragma unroll
+  for (int t = 0; t < NZ; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      z[t][i] = 16 * t + c < V ? expf(z[t][i] - mx[i]) : 0.f;
+      sum[i] += z[t][i];
+    }
+  int tok[4];
+  float wb[4];
+  bool live[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    sum[i] = row_sum16(sum[i]);
+    const int64_t r = rbase + 4 * g + i;
+    live[i] = r < rows;
+    const int64_t rr = live[i] ? r : rows - 1;
+    tok[i] = tokens[rr];
+    wb[i] = live[i] ? w[rr / N] : 0.f;
+  }
+  float (*Z)[LDZ] = Zs[wave];
+#pragma unroll
+  for (int t = 0; t < NZ; ++t) {
+    const int col = 16 * t + c;
+    float dz[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      dz[i] = col < V ? wb[i] * ((col == tok[i] ? 1.f : 0.f) - z[t][i] / sum[i]) : 0.f;
+      if (live[i] && tok[i] >= V) dz[i] = __builtin_nanf("");
+      Z[4 * g + i][col] = dz[i];
+    }
+    if (col < mrows) {
+      float* dst = dZT + (int64_t)col * ldT + rbase + 4 * g;
+      if (live[3]) {
+        *reinterpret_cast<float4*>(dst) = make_float4(dz[0], dz[1], dz[2], dz[3]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (live[i]) dst[i] = dz[i];
+      }
+    }
+  }
+  wave_lds_sync();
+  floatx4 ax[NX];
+#pragma unroll
+  for (int t = 0; t < NX; ++t) ax[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int cc = 0; cc < NC2; ++cc) {
+    FragA<MODE> dzf;
+    dzf.load(&Z[c][cc * KC + g * LK]);
+#pragma unroll
+    for (int t = 0; t < NX; ++t) {
+      const uint4* bp = phT + ((size_t)t * NC2 + cc) * 64 + lane;
+      ax[t] = dzf.mma(bp, bp + LO2, ax[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NX; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (live[i]) dX[(rbase + 4 * g + i) * D + 16 * t + c] = ax[t][i];
 }
 
 // dT[tok][k] (k < dt) summed over the rows fed token tok (start token 0 at
@@ -675,8 +721,21 @@ static hipError_t backward_chunk_t(fvan_model* m, const void* seq, int nsamp, co
   const float* XL = f.X + (size_t)L * f.rows * D;
   if constexpr (TOK) {
     const int mrows = c.vocab <= 16 ? 16 : 256;
-    hipLaunchKernelGGL((head_vocab_bwd_kernel<D>), dim3(nsamp), dim3(kHbThreads), 0, s, XL, m->params, m->po.head_w,
-                       m->po.head_b, c.vocab, mrows, tokens, w, N, f.dX, (float*)f.T_a, f.ldT);
+    const char* wp = reinterpret_cast<const char*>(m->wpack);
+    const uint4* ph = reinterpret_cast<const uint4*>(wp + m->pk.head);
+    const uint4* phT = reinterpret_cast<const uint4*>(wp + m->pk.headT);
+    const dim3 hgrid((unsigned)((rows + kHbRows - 1) / kHbRows));
+    const float* hb = m->params + m->po.head_b;
+    switch (m->pk.vp) {
+#define HB_CASE(VPV)                                                                                             \
+  case VPV:                                                                                                      \
+    hipLaunchKernelGGL((head_vocab_bwd_kernel<MODE, D, VPV>), hgrid, dim3(256), 0, s, XL, ph, phT, hb, c.vocab, \
+                       mrows, tokens, w, N, rows, f.dX, (float*)f.T_a, f.ldT);                                   \
+    break;
+      HB_CASE(32) HB_CASE(64) HB_CASE(96) HB_CASE(128) HB_CASE(160) HB_CASE(192) HB_CASE(224) HB_CASE(256)
+#undef HB_CASE
+      default: return hipErrorInvalidValue;
+    }
     hipLaunchKernelGGL((transpose_cast_kernel<D, AT>), dim3(rgrid), dim3(256), 0, s, XL, rows, (AT*)nullptr,
                        (AT*)f.T_c, f.ldT);
     if (mrows == 16) {
@@ -745,8 +804,12 @@ static hipError_t backward_chunk_t(fvan_model* m, const void* seq, int nsamp, co
   }
   // embeddings
   const int64_t npos = (int64_t)N * (D - c.d_token);
-  hipLaunchKernelGGL(pos_grad_kernel, dim3((int)std::min<int64_t>((npos + 255) / 256, 4096)), dim3(256), 0, s,
-                     (const float*)f.dX, nsamp, N, D, c.d_token, G + m->po.pos);
+  int slices = std::min(kPosSlices, nsamp);
+  while (slices > 1 && (size_t)slices * npos > f.part_floats) --slices;
+  hipLaunchKernelGGL(pos_grad_slices_kernel, dim3((unsigned)std::min<int64_t>((npos + 255) / 256, 4096), slices),
+                     dim3(256), 0, s, (const float*)f.dX, nsamp, N, D, c.d_token, f.part);
+  hipLaunchKernelGGL(pos_grad_final_kernel, dim3((unsigned)std::min<int64_t>((npos + 255) / 256, 4096)), dim3(256), 0,
+                     s, (const float*)f.part, slices, npos, G + m->po.pos);
   if constexpr (TOK) {
     const int width = c.vocab * c.d_token;
     int S = (int)std::max<int64_t>(1, std::min<int64_t>(1024, rows / 64));

@@ -55,14 +55,6 @@ struct DecodeSmem {
   int8_t sbuf[KM][64];
 };
 
-// Maximum over the 16 lanes of a row, the same in every lane of it.
-__device__ __forceinline__ float row_max16(float v) {
-  v = fmaxf(v, dpp<0x128>(v));               // row_ror:8
-  v = fmaxf(v, dpp<0x124>(v));               // row_ror:4
-  v = fmaxf(v, dpp<0x4E>(v));
-  v = fmaxf(v, dpp<0xB1>(v));
-  return v;
-}
 
 __device__ __forceinline__ float reduce16(float v) { return row_sum16(v); }
 

@@ -267,6 +267,15 @@ __device__ __forceinline__ float row_sum16(float v) {
   return v;
 }
 
+// Maximum over the 16 lanes of a row, the same in every lane of it.
+__device__ __forceinline__ float row_max16(float v) {
+  v = fmaxf(v, dpp<0x128>(v));               // row_ror:8
+  v = fmaxf(v, dpp<0x124>(v));               // row_ror:4
+  v = fmaxf(v, dpp<0x4E>(v));
+  v = fmaxf(v, dpp<0xB1>(v));
+  return v;
+}
+
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float x) {
   // d/dx [x Phi(x)] = Phi(x) + x phi(x)

@@ -29,7 +29,12 @@ ParamOffsets param_offsets(const fvan_model_config& c);
 // elements c*KC + (l/16)*KC/4 .. +KC/4.  Split packs store all hi fragments,
 // then all lo fragments.
 struct PackOffsets {
-  size_t qkv, ffn1, ffn2, qkvT, ffn1T, ffn2T, layer_stride, total;
+  size_t qkv, ffn1, ffn2, qkvT, ffn1T, ffn2T, layer_stride;
+  // models over patch tokens (vocab > 2): the head W_h [vocab x d] padded to vp
+  // rows (vp = vocab rounded up to 32, zero rows), and its transpose [d x vp]
+  size_t head, headT;
+  int vp;
+  size_t total;
 };
 PackOffsets pack_offsets(const fvan_model_config& c);
 

@@ -12,8 +12,10 @@ namespace fvan {
 // dst = pack of the [rows x K] matrix M, M[r][k] = src[r*K + k] (or src[k*rows + r]
 // when transposed, i.e. M = W^T of a row-major W [K x rows]).  Split mode
 // writes the bf16 hi parts at dst[0, rows*K) and the lo parts right after.
+// valid: entries of M with row (or, transposed, k) index >= valid are zero
+// (padding of the vocab-way head).
 template <int MODE>
-__global__ void pack_kernel(const float* __restrict__ src, int rows, int K, int transposed,
+__global__ void pack_kernel(const float* __restrict__ src, int rows, int K, int transposed, int valid,
                             typename Mode<MODE>::WT* __restrict__ dst) {
   typedef typename Mode<MODE>::WT WT;
   constexpr int KC = Mode<MODE>::KC;
@@ -29,7 +31,8 @@ __global__ void pack_kernel(const float* __restrict__ src, int rows, int K, int 
     const int n = (int)(rest / nchunk);
     const int r = 16 * n + (l & 15);
     const int k = c * KC + (l >> 4) * VEC + e;
-    const float v = transposed ? src[(size_t)k * rows + r] : src[(size_t)r * K + k];
+    const float v = transposed ? (k < valid ? src[(size_t)k * rows + r] : 0.f)
+                               : (r < valid ? src[(size_t)r * K + k] : 0.f);
     const WT hi = from_f<WT>(v);
     dst[p] = hi;
     if (Mode<MODE>::SPLIT) dst[p + total] = from_f<WT>(v - to_f(hi));
@@ -53,8 +56,17 @@ static hipError_t pack_all(const fvan_model_config& c, const float* theta, void*
       const int64_t total = (int64_t)j.rows * j.K;
       const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
       hipLaunchKernelGGL((pack_kernel<MODE>), dim3(grid), dim3(256), 0, s, j.src, j.rows, j.K, j.tr,
-                         reinterpret_cast<WT*>(w + j.off));
+                         j.tr ? j.K : j.rows, reinterpret_cast<WT*>(w + j.off));
     }
+  }
+  if (pk.vp) {   // the vocab-way head: W_h [vp x D] (rows >= vocab zero) and W_h^T [D x vp]
+    char* w = reinterpret_cast<char*>(wpack);
+    const int64_t total = (int64_t)pk.vp * D;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL((pack_kernel<MODE>), dim3(grid), dim3(256), 0, s, theta + po.head_w, pk.vp, D, 0, c.vocab,
+                       reinterpret_cast<WT*>(w + pk.head));
+    hipLaunchKernelGGL((pack_kernel<MODE>), dim3(grid), dim3(256), 0, s, theta + po.head_w, D, pk.vp, 1, c.vocab,
+                       reinterpret_cast<WT*>(w + pk.headT));
   }
   return hipGetLastError();
 }
