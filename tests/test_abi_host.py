@@ -60,8 +60,8 @@ def test_mask_derivation_sk_and_errors():
 def test_invalid_configs_are_rejected_on_the_host():
     base = dict(n_spins=16, d_model=32, d_token=2, n_layers=2, n_heads=2, vocab=2, window=15, prefix=0,
                 max_batch=8, precision=0)
-    bad = [dict(d_model=48), dict(n_heads=4), dict(vocab=1), dict(vocab=257), dict(window=-1), dict(prefix=17),
-           dict(max_batch=0), dict(precision=7), dict(precision=1), dict(workspaces=4)]
+    bad = [dict(d_model=48), dict(n_heads=4), dict(n_heads=3), dict(vocab=1), dict(vocab=257), dict(window=-1),
+           dict(prefix=17), dict(max_batch=0), dict(precision=7), dict(precision=1), dict(workspaces=4)]
     for b in bad:
         c = fv.ModelConfigC(**{**base, **b})
         h = C.c_void_p()
@@ -157,3 +157,27 @@ def test_refinement_graph_needs_a_proper_colouring():
         with pytest.raises(ValueError, match="colouring"):
             fv.lmc_graph(ea_instance(L, dim, 1, "pm1"), 1, device="cpu")
     fv.lmc_graph(ea_instance(5, 2, 1, "pm1", pbc=False), 1, device="cpu")   # open boundaries: bipartite
+
+
+def test_token_entry_points_reject_bad_arguments_on_the_host():
+    lib, p = fv.lib(), C.c_void_p(8)
+    assert lib.fvan_sample_tokens(None, 1, 0, 0, p, p, None) == -1
+    assert lib.fvan_log_prob_tokens_backward(None, 1, p, p, None) == -1
+    # tokens -> spins: n_tokens * bits must be n_spins, bits in [1, 8]
+    assert lib.fvan_tokens_to_spins(16, 4, p, 63, 1, p, p, None) == -1
+    assert lib.fvan_tokens_to_spins(16, 9, p, 144, 1, p, p, None) == -1
+    assert lib.fvan_tokens_to_spins(16, 4, None, 64, 1, p, p, None) == -1
+    assert lib.fvan_tokens_to_spins(16, 4, p, 64, 0, p, p, None) == -1
+    o = fv.muon_struct()
+    assert lib.fvan_train_step_tokens(None, None, p, 1.0, 1, 0, 1, C.byref(o), p, None) == -1
+    assert lib.fvan_sample_noalloc(None, 1, 0, 0, p, p, None) == -1
+    assert lib.fvan_group_launch_shape(None, None, None, None, None) == -1
+
+
+def test_binding_patch_geometry_equals_the_oracles():
+    """The binding's site map of patch tokens (its own code) against the oracle's."""
+    from oracle import patch
+    for L, D in ((2, 1), (6, 1), (4, 2), (8, 2), (4, 3), (10, 3)):
+        assert np.array_equal(fv.patch_sites(L, D), patch.patch_sites(L, D)), (L, D)
+    with pytest.raises(ValueError):
+        fv.patch_sites(5, 2)
