@@ -791,16 +791,13 @@ static hipError_t backward_chunk_t(fvan_model* m, const void* seq, int nsamp, co
       if constexpr (D >= 64)
         if ((err = attn_bwd_gen<KT, AT, 64>(m, QKV, X, XM, LSE, nsamp, s))) return err;
     }
-    // ---- QKV backward
-    hipLaunchKernelGGL((ln_kernel<D, AT, AT>), dim3(rgrid), dim3(256), 0, s, X, rows, lp + m->po.ln1_g,
-                       lp + m->po.ln1_b, (AT*)nullptr, (AT*)f.T_c, f.ldT);
+    // ---- QKV backward: dA1 = dQKV W_qkv and the LN1 backward in one kernel, which
+    // also leaves LN1(x) feature-major for the W_qkv gradient
+    hipLaunchKernelGGL((gemm_ln_bwd_kernel<MODE, D, 3 * D>), dim3((int)((rows + kGlbRows - 1) / kGlbRows)), dim3(512),
+                       0, s, (const float*)f.dQKV, rows, reinterpret_cast<const uint4*>(wl + m->pk.qkvT), X,
+                       lp + m->po.ln1_g, lp + m->po.ln1_b, (const float*)f.dXM, f.dX, (float*)f.T_c, f.ldT, f.colpart);
     if ((err = wgrad<MODE, 3 * D, D>(m, f.T_a, f.T_c, rows, gl + m->po.qkv_w, gl + m->po.qkv_b, s))) return err;
-    EpiArgs e4{};
-    e4.out = f.TMP;
-    if ((err = gemm_rows<MODE, 3 * D, D, EPI_F32>((const AT*)f.dQKV, rows, wl + m->pk.qkvT, e4, s))) return err;
-    hipLaunchKernelGGL((ln_bwd_kernel<D>), dim3(rgrid), dim3(256), 0, s, (const float*)f.TMP, X, lp + m->po.ln1_g,
-                       (const float*)f.dXM, rows, f.dX, f.colpart);
-    colsum_add(f.colpart, rgrid, 2 * D, f.colpart2, gl + m->po.ln1_g, s);
+    colsum_add(f.colpart, (int)((rows + kGlbRows - 1) / kGlbRows), 2 * D, f.colpart2, gl + m->po.ln1_g, s);
   }
   // embeddings
   const int64_t npos = (int64_t)N * (D - c.d_token);

@@ -450,6 +450,104 @@ __global__ __launch_bounds__(512, 4) void ffn_fused_kernel(const float* __restri
   }
 }
 
+// LayerNorm backward of the 16 rows a wave holds as MFMA accumulators (lane
+// (g, c): rows rbase+4g+i, columns 16t+c of dA, the gradient at the LayerNorm's
+// output; y = LN(x) with gain ln_g, shift ln_b):
+//   out[r] = resid[r] + LN'(dA[r])       (row-major, rows < rows)
+//   At[k][r] = y[r][k]                   (feature-major, for a weight gradient)
+//   Rt[k][r] = resid[r][k]               (feature-major, if Rt is set)
+// and the wave's column sums of dA * xhat (the gain gradient) and of dA (the
+// shift gradient) into red[0 .. D) and red[D .. 2D) (lanes with g = 0 write).
+template <int D>
+__device__ __forceinline__ void ln_bwd_rows(floatx4 (&acc)[D / 16], const float* __restrict__ X,
+                                            const float* __restrict__ resid, const float* __restrict__ ln_g,
+                                            const float* __restrict__ ln_b, int64_t rbase, int64_t rows, int g,
+                                            int c, float* __restrict__ out, float* __restrict__ At,
+                                            float* __restrict__ Rt, int64_t ldT, float* __restrict__ red) {
+  constexpr int NT2 = D / 16;
+  const bool full = rbase + 16 <= rows;
+  float xh[NT2][4], dyv[NT2][4];
+  bool live[4];
+  float rstd[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t r = rbase + 4 * g + i;
+    live[i] = r < rows;
+    const int64_t rr = std::min<int64_t>(r, rows - 1);
+    float s = 0.f;
+#pragma unroll
+    for (int t = 0; t < NT2; ++t) {
+      xh[t][i] = X[rr * D + 16 * t + c];
+      dyv[t][i] = resid[rr * D + 16 * t + c];
+      s += xh[t][i];
+    }
+    const float mean = row_sum16(s) * (1.0f / D);
+    float q = 0.f;
+#pragma unroll
+    for (int t = 0; t < NT2; ++t) {
+      xh[t][i] -= mean;
+      q += xh[t][i] * xh[t][i];
+    }
+    rstd[i] = rsqrtf(row_sum16(q) * (1.0f / D) + kLnEps);
+#pragma unroll
+    for (int t = 0; t < NT2; ++t) xh[t][i] *= rstd[i];
+  }
+  float s1[4] = {0.f, 0.f, 0.f, 0.f}, s2[4] = {0.f, 0.f, 0.f, 0.f};
+  float pg[NT2], pb[NT2];
+#pragma unroll
+  for (int t = 0; t < NT2; ++t) {
+    const int k = 16 * t + c;
+    const float gk = ln_g[k], bk = ln_b[k];
+    pg[t] = 0.f;
+    pb[t] = 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float a = live[i] ? acc[t][i] : 0.f;
+      pg[t] += a * xh[t][i];
+      pb[t] += a;
+      acc[t][i] = a * gk;                    // now dy = dA * gain
+      s1[i] += acc[t][i];
+      s2[i] += acc[t][i] * xh[t][i];
+    }
+    // feature-major LN output (and resid): four consecutive rows per lane
+    float* ap = At + (int64_t)k * ldT + rbase + 4 * g;
+    float* yp = Rt ? Rt + (int64_t)k * ldT + rbase + 4 * g : nullptr;
+    if (full) {
+      *reinterpret_cast<float4*>(ap) = make_float4(xh[t][0] * gk + bk, xh[t][1] * gk + bk, xh[t][2] * gk + bk,
+                                                   xh[t][3] * gk + bk);
+      if (yp) *reinterpret_cast<float4*>(yp) = make_float4(dyv[t][0], dyv[t][1], dyv[t][2], dyv[t][3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (live[i]) {
+          ap[i] = xh[t][i] * gk + bk;
+          if (yp) yp[i] = dyv[t][i];
+        }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    s1[i] = row_sum16(s1[i]) * (1.0f / D);
+    s2[i] = row_sum16(s2[i]) * (1.0f / D);
+  }
+#pragma unroll
+  for (int t = 0; t < NT2; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = rbase + 4 * g + i;
+      if (live[i]) out[r * D + 16 * t + c] = dyv[t][i] + rstd[i] * (acc[t][i] - s1[i] - xh[t][i] * s2[i]);
+    }
+#pragma unroll
+  for (int t = 0; t < NT2; ++t) {
+    pg[t] = sum_xor32(sum_xor16(pg[t]));
+    pb[t] = sum_xor32(sum_xor16(pb[t]));
+    if (g == 0) {
+      red[16 * t + c] = pg[t];
+      red[D + 16 * t + c] = pb[t];
+    }
+  }
+}
+
 // Fused feed-forward backward of one layer, with the block's forward recomputed
 // in place (x = the post-attention residual XM, dY = the gradient arriving at
 // the block's output):
@@ -621,88 +719,8 @@ __global__ __launch_bounds__(512) void ffn_bwd_fused_kernel(
       if (hc + 2 < NH) FVAN_FB_FETCH(hc + 2);
     }
   }
-  // LN2 backward on the wave's rows: lane (g, c) holds dA of rows 4g+i, columns 16t+c
-  float xh[NT2][4], dyv[NT2][4];
-  bool live[4];
-  float rstd[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t r = rbase + 4 * g + i;
-    live[i] = r < rows;
-    const int64_t rr = std::min<int64_t>(r, rows - 1);
-    float s = 0.f;
-#pragma unroll
-    for (int t = 0; t < NT2; ++t) {
-      xh[t][i] = X[rr * D + 16 * t + c];
-      dyv[t][i] = dY[rr * D + 16 * t + c];
-      s += xh[t][i];
-    }
-    const float mean = row_sum16(s) * (1.0f / D);
-    float q = 0.f;
-#pragma unroll
-    for (int t = 0; t < NT2; ++t) {
-      xh[t][i] -= mean;
-      q += xh[t][i] * xh[t][i];
-    }
-    rstd[i] = rsqrtf(row_sum16(q) * (1.0f / D) + kLnEps);
-#pragma unroll
-    for (int t = 0; t < NT2; ++t) xh[t][i] *= rstd[i];
-  }
-  float s1[4] = {0.f, 0.f, 0.f, 0.f}, s2[4] = {0.f, 0.f, 0.f, 0.f};
-  float pg[NT2], pb[NT2];
-#pragma unroll
-  for (int t = 0; t < NT2; ++t) {
-    const int k = 16 * t + c;
-    const float gk = ln_g[k], bk = ln_b[k];
-    pg[t] = 0.f;
-    pb[t] = 0.f;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float a = live[i] ? acc[t][i] : 0.f;
-      pg[t] += a * xh[t][i];
-      pb[t] += a;
-      acc[t][i] = a * gk;                    // now dy = dA * gain
-      s1[i] += acc[t][i];
-      s2[i] += acc[t][i] * xh[t][i];
-    }
-    // feature-major LN2 output and dY (four consecutive rows per lane)
-    AT* ap = At + (int64_t)k * ldT + rbase + 4 * g;
-    AT* yp = dYt + (int64_t)k * ldT + rbase + 4 * g;
-    if (full) {
-      *reinterpret_cast<float4*>(ap) = make_float4(xh[t][0] * gk + bk, xh[t][1] * gk + bk, xh[t][2] * gk + bk,
-                                                   xh[t][3] * gk + bk);
-      *reinterpret_cast<float4*>(yp) = make_float4(dyv[t][0], dyv[t][1], dyv[t][2], dyv[t][3]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (live[i]) {
-          ap[i] = xh[t][i] * gk + bk;
-          yp[i] = dyv[t][i];
-        }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    s1[i] = row_sum16(s1[i]) * (1.0f / D);
-    s2[i] = row_sum16(s2[i]) * (1.0f / D);
-  }
-#pragma unroll
-  for (int t = 0; t < NT2; ++t)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t r = rbase + 4 * g + i;
-      if (live[i]) out[r * D + 16 * t + c] = dyv[t][i] + rstd[i] * (acc[t][i] - s1[i] - xh[t][i] * s2[i]);
-    }
-  // the workgroup's partial sums of the gain and shift gradients
-#pragma unroll
-  for (int t = 0; t < NT2; ++t) {
-    pg[t] = sum_xor32(sum_xor16(pg[t]));
-    pb[t] = sum_xor32(sum_xor16(pb[t]));
-    if (g == 0) {
-      red[wave][16 * t + c] = pg[t];
-      red[wave][D + 16 * t + c] = pb[t];
-    }
-  }
+  // LN2 backward on the wave's rows (the workgroup's partial sums below)
+  ln_bwd_rows<D>(acc, X, dY, ln_g, ln_b, rbase, rows, g, c, out, At, dYt, ldT, red[wave]);
   __syncthreads();
   for (int k = tid; k < 2 * D; k += 64 * NW) {
     float sum = 0.f;
@@ -712,6 +730,115 @@ __global__ __launch_bounds__(512) void ffn_bwd_fused_kernel(
   }
 #undef FVAN_FB_FETCH
 #undef FVAN_FB_COMMIT
+}
+
+// Input gradient of the LayerNorm-fed QKV projection, in one kernel:
+//   dA = dQKV W_qkv                  (row GEMM, K = 3D, against the pack of W_qkv^T [D x 3D])
+//   out = resid + LN1'(dA)           (LayerNorm backward; resid = the gradient at the residual)
+//   At = LN1(x)^T                    (feature-major operand of the W_qkv gradient)
+// plus per-workgroup partial sums of the LN1 gain and shift gradients.  128 rows
+// per workgroup (8 waves x 16 rows); the weight fragments are staged in LDS for
+// all waves, CG K-chunks at a time, the next group fetched into registers
+// meanwhile.
+constexpr int kGlbRows = 128;
+
+template <int MODE, int D, int K>
+__global__ __launch_bounds__(512) void gemm_ln_bwd_kernel(const float* __restrict__ A, int64_t rows,
+                                                          const uint4* __restrict__ pack, const float* __restrict__ X,
+                                                          const float* __restrict__ ln_g,
+                                                          const float* __restrict__ ln_b,
+                                                          const float* __restrict__ resid, float* __restrict__ out,
+                                                          float* __restrict__ At, int64_t ldT,
+                                                          float* __restrict__ part) {
+  typedef typename Mode<MODE>::ActT AT;
+  static_assert(sizeof(AT) == 4, "FP32 activations");
+  constexpr int NW = 8;
+  constexpr int KC = Mode<MODE>::KC;
+  constexpr int LK = KC / 4;
+  constexpr int NPL = Mode<MODE>::SPLIT ? 2 : 1;
+  constexpr int NT = D / 16;
+  constexpr int NC = K / KC;
+  constexpr int CG = Mode<MODE>::SPLIT ? 3 : 6;   // K chunks per stage
+  static_assert(NC % CG == 0, "whole stages");
+  constexpr int NG = NC / CG;
+  constexpr size_t LO = (size_t)D * K / 8;
+  constexpr int SW = NT * CG * 64;           // fragments per plane and stage
+  constexpr int NPRE = (NPL * SW + 64 * NW - 1) / (64 * NW);
+  static_assert(NPRE <= 6, "at most six staged fragments per thread");
+  __shared__ __align__(16) uint4 Ws[NPL][SW];
+  __shared__ float red[NW][2 * D];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
+  const int64_t rbase = (int64_t)blockIdx.x * kGlbRows + wave * 16;
+  const int64_t ra = std::min<int64_t>(rbase + c, rows - 1);
+  // staged fragment idx (plane, tile t, chunk cc of the group, lane) -> its place in the pack
+  auto src = [&](int grp, int idx) -> const uint4* {
+    const int pl = idx / SW, rem = idx % SW, t = rem / (CG * 64), r2 = rem % (CG * 64);
+    return pack + ((size_t)t * NC + (size_t)grp * CG) * 64 + r2 + (pl ? LO : 0);
+  };
+  uint4 q0{}, q1{}, q2{}, q3{}, q4{}, q5{};
+#define FVAN_GL_FETCH(grp)                                                           \
+  do {                                                                               \
+    if (NPRE > 0 && tid < NPL * SW) q0 = *src(grp, tid);                             \
+    if (NPRE > 1 && tid + 512 < NPL * SW) q1 = *src(grp, tid + 512);                 \
+    if (NPRE > 2 && tid + 1024 < NPL * SW) q2 = *src(grp, tid + 1024);               \
+    if (NPRE > 3 && tid + 1536 < NPL * SW) q3 = *src(grp, tid + 1536);               \
+    if (NPRE > 4 && tid + 2048 < NPL * SW) q4 = *src(grp, tid + 2048);               \
+    if (NPRE > 5 && tid + 2560 < NPL * SW) q5 = *src(grp, tid + 2560);               \
+  } while (0)
+#define FVAN_GL_COMMIT()                                                             \
+  do {                                                                               \
+    uint4* w = &Ws[0][0];                                                            \
+    if (NPRE > 0 && tid < NPL * SW) w[tid] = q0;                                     \
+    if (NPRE > 1 && tid + 512 < NPL * SW) w[tid + 512] = q1;                         \
+    if (NPRE > 2 && tid + 1024 < NPL * SW) w[tid + 1024] = q2;                       \
+    if (NPRE > 3 && tid + 1536 < NPL * SW) w[tid + 1536] = q3;                       \
+    if (NPRE > 4 && tid + 2048 < NPL * SW) w[tid + 2048] = q4;                       \
+    if (NPRE > 5 && tid + 2560 < NPL * SW) w[tid + 2560] = q5;                       \
+  } while (0)
+  static_assert(64 * NW == 512, "staging strides assume 512 threads");
+  FVAN_GL_FETCH(0);
+  FVAN_GL_COMMIT();
+  __syncthreads();
+  if (NG > 1) FVAN_GL_FETCH(1);
+  floatx4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  constexpr int PLO = NPL > 1 ? SW : 0;
+  const uint4* ws = &Ws[0][0];
+  for (int grp = 0; grp < NG; ++grp) {
+#pragma unroll
+    for (int cc = 0; cc < CG; ++cc) {
+      FragA<MODE> fa;
+      {
+        alignas(16) AT af[LK];
+        const float* ap = A + ra * K + (grp * CG + cc) * KC + g * LK;
+#pragma unroll
+        for (int i = 0; i < LK; i += 4) *reinterpret_cast<float4*>(&af[i]) = *reinterpret_cast<const float4*>(ap + i);
+        fa.load(af);
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int f = (t * CG + cc) * 64 + lane;
+        acc[t] = fa.mma(ws + f, ws + f + PLO, acc[t]);
+      }
+    }
+    __syncthreads();                         // every wave is done with this group's weights
+    if (grp + 1 < NG) {
+      FVAN_GL_COMMIT();
+      __syncthreads();
+      if (grp + 2 < NG) FVAN_GL_FETCH(grp + 2);
+    }
+  }
+#undef FVAN_GL_FETCH
+#undef FVAN_GL_COMMIT
+  ln_bwd_rows<D>(acc, X, resid, ln_g, ln_b, rbase, rows, g, c, out, At, nullptr, ldT, red[wave]);
+  __syncthreads();
+  for (int k = tid; k < 2 * D; k += 64 * NW) {
+    float sum = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) sum += red[w][k];
+    part[(size_t)blockIdx.x * 2 * D + k] = sum;
+  }
 }
 
 template <int MODE, int K, int NOUT, int EPI>
