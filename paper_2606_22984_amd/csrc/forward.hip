@@ -16,6 +16,7 @@
 #include "passes.h"
 #include "row_kernels.h"
 #include "attn_mfma.h"
+#include "attn_f16.h"
 #include "attn_generic.h"
 
 namespace fvan {
@@ -206,9 +207,13 @@ hipError_t forward_layer(fvan_model* m, int l, int64_t rows, int nsamp, hipStrea
   const int H = c.n_heads, dh = D / H;
   const int ggrid = (c.n_spins + kGenRows - 1) / kGenRows * H * nsamp;
   if (dh == 16) {
-    hipLaunchKernelGGL((attn_fwd_mfma<KT, MODE>), dim3((c.n_spins + attn_rows(kFwdThreads) - 1) / attn_rows(kFwdThreads) * H * nsamp),
-                       dim3(kFwdThreads), 0, s,
-                       (const KT*)QKV, X, XM, LSE, c.n_spins, D, H, c.window, m->kg.P);
+    const dim3 agrid((c.n_spins + attn_rows(kFwdThreads) - 1) / attn_rows(kFwdThreads) * H * nsamp);
+    if constexpr (MODE == FVAN_BF16_SPLIT)
+      hipLaunchKernelGGL(attn_fwd_f16, agrid, dim3(kFwdThreads), 0, s, (const _Float16*)QKV, X, XM, LSE, c.n_spins, D,
+                         H, c.window, m->kg.P);
+    else
+      hipLaunchKernelGGL((attn_fwd_mfma<KT, MODE>), agrid, dim3(kFwdThreads), 0, s, (const KT*)QKV, X, XM, LSE,
+                         c.n_spins, D, H, c.window, m->kg.P);
   } else if (dh == 32) {
     hipLaunchKernelGGL((attn_fwd_gen<KT, 32>), dim3(ggrid), dim3(kGenThreads), 0, s, (const KT*)QKV, X, XM, LSE,
                        c.n_spins, D, H, c.window, m->kg.P);
