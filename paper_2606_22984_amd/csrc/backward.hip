@@ -21,6 +21,7 @@
 #include "passes.h"
 #include "row_kernels.h"
 #include "attn_mfma.h"
+#include "attn_f16.h"
 #include "attn_generic.h"
 
 namespace fvan {
@@ -777,14 +778,23 @@ static hipError_t backward_chunk_t(fvan_model* m, const void* seq, int nsamp, co
     // ---- attention backward (dO = dXM: the heads' output is added to the residual directly);
     // probabilities are recomputed from Q, K and the saved log-sum-exp
     if (D / H == 16) {
-      hipLaunchKernelGGL((attn_bwd_dq_mfma<KT, AT, MODE>), dim3((N + attn_rows(kDqThreads) - 1) / attn_rows(kDqThreads) * H * nsamp),
-                         dim3(kDqThreads), 0, s, QKV, X,
-                         XM, (const float*)f.dXM, LSE, f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window,
-                         m->kg.P);
-      hipLaunchKernelGGL((attn_bwd_dkv_mfma<KT, AT, MODE>), dim3((N + attn_rows(kDkvThreads) - 1) / attn_rows(kDkvThreads) * H * nsamp),
-                         dim3(kDkvThreads), 0, s, QKV,
-                         (const float*)f.dXM, LSE, (const float*)f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H,
-                         c.window, m->kg.P);
+      const dim3 qgrid((N + attn_rows(kDqThreads) - 1) / attn_rows(kDqThreads) * H * nsamp);
+      const dim3 kgrid((N + attn_rows(kDkvThreads) - 1) / attn_rows(kDkvThreads) * H * nsamp);
+      if constexpr (MODE == FVAN_BF16_SPLIT) {
+        hipLaunchKernelGGL(attn_bwd_dq_f16, qgrid, dim3(kDqThreads), 0, s, (const _Float16*)QKV, X, XM,
+                           (const float*)f.dXM, LSE, f.DELTA, (float*)f.dQKV, (float*)f.T_a, f.ldT, N, D, H, c.window,
+                           m->kg.P);
+        hipLaunchKernelGGL(attn_bwd_dkv_f16, kgrid, dim3(kDkvThreads), 0, s, (const _Float16*)QKV,
+                           (const float*)f.dXM, LSE, (const float*)f.DELTA, (float*)f.dQKV, (float*)f.T_a, f.ldT, N,
+                           D, H, c.window, m->kg.P);
+      } else {
+        hipLaunchKernelGGL((attn_bwd_dq_mfma<KT, AT, MODE>), qgrid, dim3(kDqThreads), 0, s, QKV, X, XM,
+                           (const float*)f.dXM, LSE, f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window,
+                           m->kg.P);
+        hipLaunchKernelGGL((attn_bwd_dkv_mfma<KT, AT, MODE>), kgrid, dim3(kDkvThreads), 0, s, QKV,
+                           (const float*)f.dXM, LSE, (const float*)f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H,
+                           c.window, m->kg.P);
+      }
     } else if (D / H == 32) {
       if ((err = attn_bwd_gen<KT, AT, 32>(m, QKV, X, XM, LSE, nsamp, s))) return err;
     } else {
