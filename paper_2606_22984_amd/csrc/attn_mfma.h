@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kFwdThreads) void attn_fwd_mfma(const KT* __restric
   __shared__ __align__(16) float Vf[kKeyChunk][20];
   __shared__ __align__(16) OT Ka[kKeyChunk][kAStride];        // K, A layout
   __shared__ __align__(16) OT Vb[16][kKeyChunk / 4 + 1];      // V^T as the A operand: [dim][key group]
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), g = lane >> 4, c = lane & 15;
   constexpr int R = attn_rows(kFwdThreads);
   const AttnItem it = attn_item((N + R - 1) / R, H);
   const int t0 = it.tile * R, h = it.h, b = it.b;
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(kDqThreads) void attn_bwd_dq_mfma(const KT* __restr
   __shared__ __align__(16) OT Ka[kKeyChunk][kAStride];
   __shared__ __align__(16) OT Va[kKeyChunk][kAStride];
   __shared__ __align__(16) OT Kb[16][kKeyChunk / 4 + 1];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), g = lane >> 4, c = lane & 15;
   constexpr int R = attn_rows(kDqThreads);
   const AttnItem it = attn_item((N + R - 1) / R, H);
   const int t0 = it.tile * R, h = it.h, b = it.b;
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(kDkvThreads) void attn_bwd_dkv_mfma(const KT* __res
   __shared__ __align__(16) OT Gb[16][QB / 4 + 1];   // dO, B layout (dV += P^T dO)
   __shared__ __align__(16) float Ls[QB];
   __shared__ __align__(16) float Ds[QB];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), g = lane >> 4, c = lane & 15;
   const AttnItem it = attn_item((N + QB - 1) / QB, H);
   const int h = it.h, j0 = it.tile * QB, b = it.b;
   const int j1 = min(j0 + QB, N);

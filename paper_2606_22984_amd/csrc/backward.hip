@@ -233,7 +233,7 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
   constexpr int VPL = 16 / (int)sizeof(AT);        // elements per 16-byte load
   __shared__ __attribute__((aligned(16))) ST As[NPL][M][PADK];
   __shared__ __attribute__((aligned(16))) ST Bs[NPL][NB][PADK];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wr = wave / WCG, wc = wave % WCG;
   // 1-D grid over (column block fastest, then row block, then K slice), dealt to
   // the XCDs in contiguous ranges: the workgroups of one K slice read the same
@@ -531,7 +531,7 @@ __global__ __launch_bounds__(256) void tok_grad_slices_kernel(const float* __res
     s0 += __shfl_xor(s0, o);
     s1 += __shfl_xor(s1, o);
   }
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if ((threadIdx.x & 63) == 0) { red[0][wave] = s0; red[1][wave] = s1; }
   __syncthreads();
   if (threadIdx.x < 2)
@@ -566,7 +566,7 @@ __global__ __launch_bounds__(256) void head_vocab_bwd_kernel(const float* __rest
   constexpr size_t LO1 = (size_t)VP * D / 8, LO2 = LO1;
   constexpr int LDZ = VP + 4;
   __shared__ __align__(16) float Zs[4][16][LDZ];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), g = lane >> 4, c = lane & 15;
   const int64_t rbase = (int64_t)blockIdx.x * kHbRows + wave * 16;
   if (rbase >= rows) return;                 // no block-wide barrier below
   FragA<MODE> fa[NC];

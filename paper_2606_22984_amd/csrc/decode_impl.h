@@ -142,7 +142,7 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK, KM>& sm, const DecodeUnit& 
   // 1/sqrt(DH) * log2(e)
   constexpr float kScaleLog2 = (DH == 16 ? 0.25f : DH == 32 ? 0.17677669529663688f : 0.125f) * 1.4426950408889634f;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int b0 = local_tile * KM;
   const int nb = min(KM, U.B - b0);
   const int N = U.N, P = U.P, R = U.R, S = U.S, nl = U.n_layers, dt = U.d_token;

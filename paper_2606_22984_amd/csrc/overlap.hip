@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kOvThreads) void overlap_kernel(const int8_t* __res
   extern __shared__ unsigned int hist[];   // n + 1 bins
   for (int k = threadIdx.x; k <= n; k += kOvThreads) hist[k] = 0u;
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), r = lane & 15, g = lane >> 4;
   const int nblk = (B + kOvBlock - 1) / kOvBlock;
   const int npairs = nblk * (nblk + 1) / 2;
   const bool vec8 = (n & 7) == 0;

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(const typename Mode<MODE
   constexpr int NC = K / KC;
   constexpr int NT = NOUT / 16;
   constexpr size_t LO = (size_t)NOUT * K / 8;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), g = lane >> 4, c = lane & 15;
   const int64_t rbase = (int64_t)blockIdx.x * kGemmRows + wave * 32;
   if (rbase >= rows) return;
   // clamp the A rows; stores are guarded (A is not read when the rows come from ln_x)
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256) void gemm_rows_staged_kernel(const typename Mo
   constexpr size_t LO = (size_t)NOUT * K / 8;
   __shared__ __align__(16) float Ev[R][68];                               // out / outT values
   __shared__ __align__(16) float Eh[EPI == EPI_STORE_KV ? 1 : R][68];     // GELU: hpre_out; GELU': hpre_in
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), g = lane >> 4, c = lane & 15;
   const int64_t r0 = (int64_t)blockIdx.x * R;
   FragA<MODE> fa[RT][NC];                    // the wave's A fragments (rows 16 RT w ..), converted once
 #pragma unroll
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(512, 4) void ffn_fused_kernel(const float* __restri
   constexpr int LDH = HC + 4;
   __shared__ __align__(16) uint4 Ws[NPL][SW];      // [W1 chunk | W2 chunk]
   __shared__ __align__(16) AT Hs[NW][16][LDH];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), g = lane >> 4, c = lane & 15;
   const int64_t rbase = (int64_t)blockIdx.x * kFfnRows + wave * 16;
   auto src = [&](int hc, int idx) -> const uint4* {
     const int pl = idx / SW, j = idx % SW;
@@ -597,7 +597,7 @@ __global__ __launch_bounds__(512) void ffn_bwd_fused_kernel(
   __shared__ __align__(16) float Hg[NW][16][LDH];
   __shared__ __align__(16) float Hd[NW][16][LDH];
   __shared__ float red[NW][2 * D];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), g = lane >> 4, c = lane & 15;
   const int64_t rbase = (int64_t)blockIdx.x * kFfnBwdRows + wave * 16;
   const bool full = rbase + 16 <= rows;
   // staged fragment idx (plane pl, slot j) -> its place in the packs
@@ -767,7 +767,7 @@ __global__ __launch_bounds__(512) void gemm_ln_bwd_kernel(const float* __restric
   static_assert(NPRE <= 6, "at most six staged fragments per thread");
   __shared__ __align__(16) uint4 Ws[NPL][SW];
   __shared__ float red[NW][2 * D];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), g = lane >> 4, c = lane & 15;
   const int64_t rbase = (int64_t)blockIdx.x * kGlbRows + wave * 16;
   const int64_t ra = std::min<int64_t>(rbase + c, rows - 1);
   // staged fragment idx (plane, tile t, chunk cc of the group, lane) -> its place in the pack
