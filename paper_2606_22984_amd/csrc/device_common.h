@@ -276,17 +276,36 @@ __device__ __forceinline__ float row_max16(float v) {
   return v;
 }
 
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_grad(float x) {
-  // d/dx [x Phi(x)] = Phi(x) + x phi(x)
-  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * __expf(-0.5f * x * x);
+// Normal CDF Phi(x) = (1 + erf(x / sqrt 2)) / 2 and the Gaussian factor exp(-x^2 / 2),
+// branch-free: erfc(z) for z = |x| / sqrt 2 >= 0 from the rational-times-Gaussian
+// form of Abramowitz & Stegun, Handbook of Mathematical Functions, 7.1.26
+// (Hastings), whose absolute error in erf is at most 1.5e-7; the Gaussian factor
+// exp(-z^2) is the same exp(-x^2 / 2) that GELU's derivative needs.
+__device__ __forceinline__ void phi_gauss(float x, float& cdf, float& gauss) {
+  const float z = fabsf(x) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, z, 1.0f));
+  const float poly =
+      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
+  gauss = __expf(-0.5f * x * x);
+  const float half_erfc = 0.5f * poly * gauss;        // (1 - erf(z)) / 2
+  cdf = x >= 0.f ? 1.0f - half_erfc : half_erfc;
 }
-
-// GELU(x) and its derivative from one evaluation of erf.
+__device__ __forceinline__ float gelu(float x) {
+  float cdf, gauss;
+  phi_gauss(x, cdf, gauss);
+  return x * cdf;
+}
+// GELU(x) = x Phi(x) and its derivative Phi(x) + x phi(x), phi(x) = exp(-x^2/2) / sqrt(2 pi).
 __device__ __forceinline__ void gelu_and_grad(float x, float& g, float& gp) {
-  const float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
+  float cdf, gauss;
+  phi_gauss(x, cdf, gauss);
   g = x * cdf;
-  gp = cdf + x * 0.39894228040143268f * __expf(-0.5f * x * x);
+  gp = fmaf(x * 0.39894228040143268f, gauss, cdf);
+}
+__device__ __forceinline__ float gelu_grad(float x) {
+  float g, gp;
+  gelu_and_grad(x, g, gp);
+  return gp;
 }
 
 // log(1 + exp(x)) without overflow.
