@@ -23,6 +23,11 @@
 // (a_h b_h + a_l b_h + a_h b_l; the dropped a_l b_l is below 2^-16 relative), where
 // [a_h | a_l] is the layout staged in LDS and {[b_h | b_h], [b_l | 0]} is built once
 // in registers (SplitDup), for a loop-invariant operand or one formed per tile.
+//
+// The 16x16x16 and 16x16x32 products never feed each other's accumulators: a
+// 16x16x32 result fed straight into a dependent 16x16x16 MFMA came out wrong with
+// this toolchain, so every score tile starts from a zero accumulator and every
+// accumulator chain uses one opcode.
 #pragma once
 
 #include "attn_mfma.h"

@@ -15,10 +15,10 @@
 // ([row][g]: four consecutive dims of a row) and the B layout ([dim][row group]:
 // four consecutive rows of a dim), so the tile loops only load and multiply.
 //
-// Precision of the tile products (mode = fvan_precision): FP32 MFMA
-// (16x16x4, four per tile) for FVAN_FP32, and for FVAN_BF16_SPLIT the three products hi*hi + lo*hi + hi*lo of hi/lo
-// BF16 operand splits (the dropped lo*lo term is below 2^-16 relative), issued
-// as two 16x16x32 MFMAs.
+// These kernels run the FP32 mode (FP32 MFMA, 16x16x4, four per tile); split mode
+// runs the FP16-MFMA kernels of attn_f16.h, which reuse the staging helpers, work
+// orders and masks defined here.  AOp<2> below is the BF16 hi/lo operand split
+// those kernels stage in LDS.
 #pragma once
 
 #include <algorithm>
@@ -65,21 +65,6 @@ template <> struct AOp<2> {
                         __uint_as_float(hw.y << 16), __uint_as_float(hw.y & 0xFFFF0000u)};
     t.l = __builtin_convertvector(v - hf, bf16x4);
     return t;
-  }
-  // The contraction index of a 16x16x32 MFMA runs over (part, dim): lane g's
-  // eight k slots hold dims 4g..4g+3 twice.  First [a_hi | a_lo] x [b_hi ; b_hi]
-  // = a_hi b_hi + a_lo b_hi, then [a_hi | a_hi] x [b_lo ; 0] = a_hi b_lo.  Both
-  // products use the same opcode: a 16x16x32 result fed straight into a
-  // dependent 16x16x16 MFMA was measured to come out wrong with this toolchain
-  // (missing wait states between the two opcodes), so that pairing is avoided.
-  static __device__ __forceinline__ floatx4 mma(const T& a, const T& b, floatx4 acc) {
-    const bf16x4 z = {(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
-    const bf16x8 a8 = __builtin_shufflevector(a.h, a.l, 0, 1, 2, 3, 4, 5, 6, 7);
-    const bf16x8 b8 = __builtin_shufflevector(b.h, b.h, 0, 1, 2, 3, 4, 5, 6, 7);
-    const bf16x8 a9 = __builtin_shufflevector(a.h, a.h, 0, 1, 2, 3, 4, 5, 6, 7);
-    const bf16x8 b9 = __builtin_shufflevector(b.l, z, 0, 1, 2, 3, 4, 5, 6, 7);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a8, b8, acc, 0, 0, 0);
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a9, b9, acc, 0, 0, 0);
   }
 };
 
