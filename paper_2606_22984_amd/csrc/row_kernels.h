@@ -559,8 +559,10 @@ __device__ __forceinline__ void ln_bwd_rows(floatx4 (&acc)[D / 16], const float*
 // partial sums of the LN2 gain and shift gradients (part[block][2D]).
 // 128 rows per workgroup, one 16-row MFMA tile per wave (8 waves).  The hidden
 // layer is walked 32 units at a time: the chunk's weight fragments (rows of W1
-// and W2^T, columns of W1^T) are staged in LDS once for all eight waves, the
-// next chunk's are fetched into registers meanwhile, and each wave's h, g and
+// and W2^T, columns of W1^T) are staged in LDS once for all eight waves, in two
+// alternating buffers so that the next chunk is committed while the current one
+// is read (one barrier per chunk), the chunk after it fetched into registers
+// meanwhile, and each wave's h, g and
 // dH go through a wave-private LDS tile; they reach HBM only as the two
 // feature-major weight-gradient operands.  (One wave loading every weight for
 // its own 16 rows made the kernel bound by L2 reads of the weights.)
@@ -593,7 +595,7 @@ __global__ __launch_bounds__(512) void ffn_bwd_fused_kernel(
   constexpr int SW = 2 * S1 + S3;
   constexpr int NPRE = (NPL * SW + 64 * NW - 1) / (64 * NW);   // staged fragments per thread
   constexpr int LDH = HC + 4;
-  __shared__ __align__(16) uint4 Ws[NPL][SW];      // [W1 chunk | W2^T chunk | W1^T chunk]
+  __shared__ __align__(16) uint4 Ws[2][NPL][SW];   // two stages of [W1 chunk | W2^T chunk | W1^T chunk]
   __shared__ __align__(16) float Hg[NW][16][LDH];
   __shared__ __align__(16) float Hd[NW][16][LDH];
   __shared__ float red[NW][2 * D];
@@ -622,9 +624,9 @@ __global__ __launch_bounds__(512) void ffn_bwd_fused_kernel(
     if (NPRE > 4 && i0 + 2048 < NPL * SW) p4 = *src(hc, i0 + 2048);                  \
     if (NPRE > 5 && i0 + 2560 < NPL * SW) p5 = *src(hc, i0 + 2560);                  \
   } while (0)
-#define FVAN_FB_COMMIT()                                                             \
+#define FVAN_FB_COMMIT(buf)                                                          \
   do {                                                                               \
-    uint4* w = &Ws[0][0];                                                            \
+    uint4* w = &Ws[buf][0][0];                                                       \
     if (NPRE > 0 && tid < NPL * SW) w[tid] = p0;                                     \
     if (NPRE > 1 && tid + 512 < NPL * SW) w[tid + 512] = p1r;                        \
     if (NPRE > 2 && tid + 1024 < NPL * SW) w[tid + 1024] = p2r;                      \
@@ -646,7 +648,7 @@ __global__ __launch_bounds__(512) void ffn_bwd_fused_kernel(
       *reinterpret_cast<float4*>(&af[i]) = *reinterpret_cast<const float4*>(dY + ra * D + cc * KC + g * LK + i);
     fy[cc].load(af);
   }
-  FVAN_FB_COMMIT();
+  FVAN_FB_COMMIT(0);
   __syncthreads();
   if (NH > 1) FVAN_FB_FETCH(1);
   floatx4 acc[NT2];
@@ -654,11 +656,11 @@ __global__ __launch_bounds__(512) void ffn_bwd_fused_kernel(
   for (int t = 0; t < NT2; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   float (*HG)[LDH] = Hg[wave];
   float (*HD)[LDH] = Hd[wave];
-  const uint4* W1s = &Ws[0][0];
-  const uint4* W2s = &Ws[0][S1];
-  const uint4* W3s = &Ws[0][2 * S1];
   constexpr int PLO = NPL > 1 ? SW : 0;      // hi-to-lo distance in the stage
   for (int hc = 0; hc < NH; ++hc) {
+    const uint4* W1s = &Ws[hc & 1][0][0];
+    const uint4* W2s = W1s + S1;
+    const uint4* W3s = W1s + 2 * S1;
 #pragma unroll
     for (int t = 0; t < NT1; ++t) {
       floatx4 ah = {0.f, 0.f, 0.f, 0.f}, ag = ah;
@@ -712,12 +714,12 @@ __global__ __launch_bounds__(512) void ffn_bwd_fused_kernel(
           }
       }
     }
-    __syncthreads();                         // every wave is done with this chunk's weights and tiles
-    if (hc + 1 < NH) {
-      FVAN_FB_COMMIT();
-      __syncthreads();
-      if (hc + 2 < NH) FVAN_FB_FETCH(hc + 2);
-    }
+    // the other stage was last read in chunk hc - 1, which every wave finished
+    // before the barrier that ended it
+    if (hc + 1 < NH) FVAN_FB_COMMIT((hc + 1) & 1);
+    __syncthreads();                         // chunk hc + 1 is staged; stage hc & 1 is free
+    // issued after the barrier, whose fence would otherwise wait for these loads
+    if (hc + 2 < NH) FVAN_FB_FETCH(hc + 2);
   }
   // LN2 backward on the wave's rows (the workgroup's partial sums below)
   ln_bwd_rows<D>(acc, X, dY, ln_g, ln_b, rbase, rows, g, c, out, At, dYt, ldT, red[wave]);
@@ -738,8 +740,8 @@ __global__ __launch_bounds__(512) void ffn_bwd_fused_kernel(
 //   At = LN1(x)^T                    (feature-major operand of the W_qkv gradient)
 // plus per-workgroup partial sums of the LN1 gain and shift gradients.  128 rows
 // per workgroup (8 waves x 16 rows); the weight fragments are staged in LDS for
-// all waves, CG K-chunks at a time, the next group fetched into registers
-// meanwhile.
+// all waves, CG K-chunks at a time, in two alternating buffers (one barrier per
+// group), the group after next fetched into registers meanwhile.
 constexpr int kGlbRows = 128;
 
 template <int MODE, int D, int K>
@@ -765,7 +767,7 @@ __global__ __launch_bounds__(512) void gemm_ln_bwd_kernel(const float* __restric
   constexpr int SW = NT * CG * 64;           // fragments per plane and stage
   constexpr int NPRE = (NPL * SW + 64 * NW - 1) / (64 * NW);
   static_assert(NPRE <= 6, "at most six staged fragments per thread");
-  __shared__ __align__(16) uint4 Ws[NPL][SW];
+  __shared__ __align__(16) uint4 Ws[2][NPL][SW];
   __shared__ float red[NW][2 * D];
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), g = lane >> 4, c = lane & 15;
   const int64_t rbase = (int64_t)blockIdx.x * kGlbRows + wave * 16;
@@ -785,9 +787,9 @@ __global__ __launch_bounds__(512) void gemm_ln_bwd_kernel(const float* __restric
     if (NPRE > 4 && tid + 2048 < NPL * SW) q4 = *src(grp, tid + 2048);               \
     if (NPRE > 5 && tid + 2560 < NPL * SW) q5 = *src(grp, tid + 2560);               \
   } while (0)
-#define FVAN_GL_COMMIT()                                                             \
+#define FVAN_GL_COMMIT(buf)                                                          \
   do {                                                                               \
-    uint4* w = &Ws[0][0];                                                            \
+    uint4* w = &Ws[buf][0][0];                                                       \
     if (NPRE > 0 && tid < NPL * SW) w[tid] = q0;                                     \
     if (NPRE > 1 && tid + 512 < NPL * SW) w[tid + 512] = q1;                         \
     if (NPRE > 2 && tid + 1024 < NPL * SW) w[tid + 1024] = q2;                       \
@@ -797,15 +799,15 @@ __global__ __launch_bounds__(512) void gemm_ln_bwd_kernel(const float* __restric
   } while (0)
   static_assert(64 * NW == 512, "staging strides assume 512 threads");
   FVAN_GL_FETCH(0);
-  FVAN_GL_COMMIT();
+  FVAN_GL_COMMIT(0);
   __syncthreads();
   if (NG > 1) FVAN_GL_FETCH(1);
   floatx4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   constexpr int PLO = NPL > 1 ? SW : 0;
-  const uint4* ws = &Ws[0][0];
   for (int grp = 0; grp < NG; ++grp) {
+    const uint4* ws = &Ws[grp & 1][0][0];
 #pragma unroll
     for (int cc = 0; cc < CG; ++cc) {
       FragA<MODE> fa;
@@ -822,12 +824,11 @@ __global__ __launch_bounds__(512) void gemm_ln_bwd_kernel(const float* __restric
         acc[t] = fa.mma(ws + f, ws + f + PLO, acc[t]);
       }
     }
-    __syncthreads();                         // every wave is done with this group's weights
-    if (grp + 1 < NG) {
-      FVAN_GL_COMMIT();
-      __syncthreads();
-      if (grp + 2 < NG) FVAN_GL_FETCH(grp + 2);
-    }
+    // the other stage was last read in group grp - 1, finished before the barrier that ended it
+    if (grp + 1 < NG) FVAN_GL_COMMIT((grp + 1) & 1);
+    __syncthreads();                         // group grp + 1 is staged; stage grp & 1 is free
+    // issued after the barrier, whose fence would otherwise wait for these loads
+    if (grp + 2 < NG) FVAN_GL_FETCH(grp + 2);
   }
 #undef FVAN_GL_FETCH
 #undef FVAN_GL_COMMIT
