@@ -88,42 +88,69 @@ __device__ __forceinline__ void ln_rows(DecodeSmem<D, MODE, TOK, KM>& sm, const 
   }
 }
 
-// acc0, acc1 (16 x 16 tile nt of rows 0..15 and 16..31) = A[16 NRT x K] (LDS, row
-// stride lda elements) . pack tile nt; each weight fragment is loaded once and
-// feeds the NRT (1 or 2) row tiles; acc1 is left zero when NRT = 1.
-// lo_u4: distance (in 16-byte units) from a split pack's hi part to its lo part.
-template <int MODE, int K, int NRT>
-__device__ __forceinline__ void mfma_rowtiles(const typename Mode<MODE>::ActT* A, int lda,
-                                              const uint4* __restrict__ pack, size_t lo_u4, int nt, int lane,
-                                              floatx4& acc0, floatx4& acc1) {
+// The output tiles nt = nt0, nt0 + step, ... < ntn of A[16 NRT x K] (LDS, row
+// stride lda) . pack, each finished tile handed to epi(nt, acc0, acc1).  The
+// weight fragments come G chunks per round, and the next round's (of this tile
+// or of the wave's next tile) are loaded while the current round multiplies, so
+// a phase exposes one L2 latency instead of one per round.  Per tile the chunks
+// are summed in order, as a single pass over the tile would; acc1 stays zero
+// when NRT = 1.
+template <int MODE, int K, int NRT, typename Epi>
+__device__ __forceinline__ void mfma_tiles(const typename Mode<MODE>::ActT* A, int lda,
+                                           const uint4* __restrict__ pack, size_t lo_u4, int nt0, int ntn, int step,
+                                           int lane, Epi&& epi) {
   constexpr int KC = Mode<MODE>::KC;
   constexpr int NC = K / KC;
-  acc0 = floatx4{0.f, 0.f, 0.f, 0.f};
-  acc1 = acc0;
-  const typename Mode<MODE>::ActT* arow = A + (lane & 15) * lda + (lane >> 4) * (KC / 4);
-  const typename Mode<MODE>::ActT* arow1 = arow + 16 * lda;
-  const uint4* bp = pack + (size_t)nt * NC * 64 + lane;
-  // the weight fragments of G chunks are loaded together, so one L2 latency
-  // is exposed per G chunks instead of per chunk
   constexpr int GM = Mode<MODE>::SPLIT ? 2 : 4;
   constexpr int G = NC < GM ? NC : GM;
   static_assert(NC % G == 0, "K chunks in groups of G");
-#pragma unroll 1
-  for (int c0 = 0; c0 < NC; c0 += G) {
-    uint4 bh[G], bl[G];
-#pragma unroll
-    for (int u = 0; u < G; ++u) {
-      bh[u] = bp[(c0 + u) * 64];
-      bl[u] = Mode<MODE>::SPLIT ? bp[(c0 + u) * 64 + lo_u4] : bh[u];
+  constexpr int R = NC / G;                 // rounds per tile
+  if (nt0 >= ntn) return;
+  const typename Mode<MODE>::ActT* arow = A + (lane & 15) * lda + (lane >> 4) * (KC / 4);
+  const typename Mode<MODE>::ActT* arow1 = arow + 16 * lda;
+  uint4 bh[G], bl[G], nh[G], nl[G];
+#define FVAN_DT_LOAD(T, RR, H, L)                                                              \
+  _Pragma("unroll") for (int u = 0; u < G; ++u) {                                            \
+    const uint4* bp_ = pack + (size_t)(T) * NC * 64 + (size_t)((RR) * G + u) * 64 + lane;    \
+    H[u] = bp_[0];                                                                           \
+    L[u] = Mode<MODE>::SPLIT ? bp_[lo_u4] : H[u];                                            \
+  }
+  FVAN_DT_LOAD(nt0, 0, bh, bl);
+  floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+  int nt = nt0, r = 0;
+  for (;;) {
+    int nn = nt, rn = r + 1;
+    if (rn == R) {
+      rn = 0;
+      nn = nt + step;
+    }
+    const bool more = nn < ntn;
+    if (more) {
+      FVAN_DT_LOAD(nn, rn, nh, nl);
     }
 #pragma unroll
     for (int u = 0; u < G; ++u) {
+      const int k = (r * G + u) * KC;
       if constexpr (NRT == 2)
-        Frag<MODE>::step2v(arow + (c0 + u) * KC, arow1 + (c0 + u) * KC, bh[u], bl[u], acc0, acc1);
+        Frag<MODE>::step2v(arow + k, arow1 + k, bh[u], bl[u], acc0, acc1);
       else
-        Frag<MODE>::step1v(arow + (c0 + u) * KC, bh[u], bl[u], acc0);
+        Frag<MODE>::step1v(arow + k, bh[u], bl[u], acc0);
+    }
+    if (r == R - 1) {
+      epi(nt, acc0, acc1);
+      acc0 = floatx4{0.f, 0.f, 0.f, 0.f};
+      acc1 = acc0;
+    }
+    if (!more) break;
+    nt = nn;
+    r = rn;
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      bh[u] = nh[u];
+      bl[u] = nl[u];
     }
   }
+#undef FVAN_DT_LOAD
 }
 
 template <int D, int MODE, int DH, bool TOK, int KM>
@@ -177,9 +204,9 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK, KM>& sm, const DecodeUnit& 
       // ---- QKV projection; k_t, v_t appended to the cache ----
       {
         const uint4* pk = reinterpret_cast<const uint4*>(wl + U.p_qkv);
-        for (int nt = wave; nt < 3 * D / 16; nt += kWaves) {
-          floatx4 acc[2];
-          mfma_rowtiles<MODE, D, NRT>(&sm.a[0][0], Sm::LDA, pk, (size_t)3 * D * D / 8, nt, lane, acc[0], acc[1]);
+        mfma_tiles<MODE, D, NRT>(&sm.a[0][0], Sm::LDA, pk, (size_t)3 * D * D / 8, wave, 3 * D / 16, kWaves, lane,
+                                 [&](int nt, const floatx4& a0, const floatx4& a1) {
+          const floatx4 acc[2] = {a0, a1};
           const int n = nt * 16 + (lane & 15);
           const float bias = lp[U.o_qkv_b + n];
 #pragma unroll
@@ -195,7 +222,7 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK, KM>& sm, const DecodeUnit& 
               *dst = from_f<T>(val);
             }
           }
-        }
+        });
       }
       __threadfence_block();
       __syncthreads();
@@ -308,28 +335,28 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK, KM>& sm, const DecodeUnit& 
       __syncthreads();
       {
         const uint4* p1 = reinterpret_cast<const uint4*>(wl + U.p_ffn1);
-        for (int nt = wave; nt < 4 * D / 16; nt += kWaves) {
-          floatx4 acc[2];
-          mfma_rowtiles<MODE, D, NRT>(&sm.a[0][0], Sm::LDA, p1, (size_t)4 * D * D / 8, nt, lane, acc[0], acc[1]);
+        mfma_tiles<MODE, D, NRT>(&sm.a[0][0], Sm::LDA, p1, (size_t)4 * D * D / 8, wave, 4 * D / 16, kWaves, lane,
+                                 [&](int nt, const floatx4& a0, const floatx4& a1) {
+          const floatx4 acc[2] = {a0, a1};
           const int n = nt * 16 + (lane & 15);
           const float bias = lp[U.o_ffn1_b + n];
 #pragma unroll
           for (int ri = 0; ri < 4 * NRT; ++ri)
             sm.u.hid[16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3)][n] =
                 from_f<typename Mode<MODE>::ActT>(gelu(acc[ri >> 2][ri & 3] + bias));
-        }
+        });
       }
       __syncthreads();
       {
         const uint4* p2 = reinterpret_cast<const uint4*>(wl + U.p_ffn2);
-        for (int nt = wave; nt < D / 16; nt += kWaves) {
-          floatx4 acc[2];
-          mfma_rowtiles<MODE, 4 * D, NRT>(&sm.u.hid[0][0], Sm::LDH, p2, (size_t)4 * D * D / 8, nt, lane, acc[0], acc[1]);
+        mfma_tiles<MODE, 4 * D, NRT>(&sm.u.hid[0][0], Sm::LDH, p2, (size_t)4 * D * D / 8, wave, D / 16, kWaves, lane,
+                                     [&](int nt, const floatx4& a0, const floatx4& a1) {
+          const floatx4 acc[2] = {a0, a1};
           const int n = nt * 16 + (lane & 15);
           const float bias = lp[U.o_ffn2_b + n];
 #pragma unroll
           for (int ri = 0; ri < 4 * NRT; ++ri) sm.h[16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3)][n] += acc[ri >> 2][ri & 3] + bias;
-        }
+        });
       }
       __syncthreads();
     }
