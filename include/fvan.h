@@ -18,11 +18,16 @@
  *    allocated and initialised by fvan_create_model from max_batch and freed
  *    by fvan_destroy_model.  No other call allocates device memory.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
- *    asynchronously on it and on no other stream; argument checks happen on
- *    the host, synchronously, before anything is enqueued.  A call that fails
- *    its checks enqueues nothing.  Only fvan_model_status and the training
- *    steps (which wait for the previous training step of their model, see
- *    fvan_train_step) synchronise with the device.
+ *    asynchronously on it; the backward (fvan_log_prob_backward, the token
+ *    backward and the training steps) also runs the layer weight gradients on a
+ *    stream the model owns, forked from `stream` and joined back to it with
+ *    events within each chunk of samples, so every kernel of a call is ordered
+ *    after the work already on `stream` and before the work enqueued on it
+ *    afterwards (under stream capture: one fork and join per chunk).  Argument
+ *    checks happen on the host, synchronously, before anything is enqueued.  A
+ *    call that fails its checks enqueues nothing.  Only fvan_model_status and
+ *    the training steps (which wait for the previous training step of their
+ *    model, see fvan_train_step) synchronise with the device.
  *  - Every call returns an fvan_status.  On failure fvan_last_error() returns
  *    a thread-local message.  No C++ exception crosses the ABI.
  *  - Non-finite values: the model calls (sampling, log q, backward, training

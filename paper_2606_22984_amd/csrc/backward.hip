@@ -394,10 +394,11 @@ __global__ __launch_bounds__(kRedOut * kRedGroups) void wgrad_reduce_kernel(cons
 
 template <int MODE, int M, int Nw>
 static hipError_t wgrad(fvan_model* m, const void* A, const void* B, int64_t K, float* gW, float* gb, hipStream_t s,
-                        int m_valid = M) {
+                        int m_valid = M, float* part = nullptr) {
   typedef typename Mode<MODE>::ActT AT;
   constexpr int NB = Nw + 16;
   auto& f = m->fw;
+  if (!part) part = f.part;
   const int KC = Mode<MODE>::KC;
   int S = (int)std::max<int64_t>(1, std::min<int64_t>(512, K / (8 * KC)));
   while ((size_t)S * M * NB > f.part_floats) --S;
@@ -411,10 +412,10 @@ static hipError_t wgrad(fvan_model* m, const void* A, const void* B, int64_t K, 
   constexpr int MS = M >= 512 ? M / 2 : M;
   constexpr int NBS = NB >= 512 && NB % 48 == 0 ? NB / 3 : NB;
   hipLaunchKernelGGL((wgrad_kernel<MODE, MS, NBS>), dim3(S * (M / MS) * (NB / NBS)), dim3(512), 0, s, (const AT*)A,
-                     f.ldT, (const AT*)B, f.ldT, K, kper, M, NB, M / MS, NB / NBS, f.part);
+                     f.ldT, (const AT*)B, f.ldT, K, kper, M, NB, M / MS, NB / NBS, part);
   const int total = M * (Nw + 1);
   hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((total + kRedOut - 1) / kRedOut), dim3(kRedOut * kRedGroups), 0, s,
-                     (const float*)f.part, S, M, NB, Nw, m_valid, gW, gb);
+                     (const float*)part, S, M, NB, Nw, m_valid, gW, gb);
   return hipGetLastError();
 }
 
@@ -696,9 +697,9 @@ static hipError_t attn_bwd_gen(fvan_model* m, const KT* QKV, const float* X, con
   const int N = c.n_spins, D = c.d_model, H = c.n_heads;
   const int grid = (N + kGenRows - 1) / kGenRows * H * nsamp;
   hipLaunchKernelGGL((attn_bwd_dq_gen<KT, AT, DH>), dim3(grid), dim3(kGenThreads), 0, s, QKV, X, XM,
-                     (const float*)f.dXM, LSE, f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window, m->kg.P);
+                     (const float*)f.dXM, LSE, f.DELTA, (AT*)f.dQKV, (AT*)f.T_e, f.ldT, N, D, H, c.window, m->kg.P);
   hipLaunchKernelGGL((attn_bwd_dkv_gen<KT, AT, DH>), dim3(grid), dim3(kGenThreads), 0, s, QKV, (const float*)f.dXM,
-                     LSE, (const float*)f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window, m->kg.P);
+                     LSE, (const float*)f.DELTA, (AT*)f.dQKV, (AT*)f.T_e, f.ldT, N, D, H, c.window, m->kg.P);
   return hipGetLastError();
 }
 
@@ -756,6 +757,14 @@ static hipError_t backward_chunk_t(fvan_model* m, const void* seq, int nsamp, co
     colsum_add(f.colpart, nsamp, 2 * D + 2, f.colpart2, G + m->po.head_w, s);
   }
 
+  // The layer weight gradients go to the side stream as soon as their operands
+  // are written, and run beside the attention backward and the next layer's FFN
+  // backward; a buffer they read is written again only after its "read" event.
+  // Every event waited on is recorded earlier in this chunk (the previous chunk
+  // joined the side stream back before returning), so the fork and join also
+  // hold under stream capture.
+  hipStream_t ss = f.side;
+  hipEvent_t ffn_ready = f.ev[0], ffn_read = f.ev[1], qkv_ready = f.ev[2], qkv_read = f.ev[3];
   for (int l = L - 1; l >= 0; --l) {
     const float* lp = m->params + m->po.layer0 + (int64_t)l * m->po.layer_stride;
     float* gl = G + m->po.layer0 + (int64_t)l * m->po.layer_stride;
@@ -767,32 +776,40 @@ static hipError_t backward_chunk_t(fvan_model* m, const void* seq, int nsamp, co
     // ---- FFN: one fused kernel recomputes LN2, the pre-activation and GELU,
     // differentiates through W2, GELU' and W1 and the LayerNorm, and leaves the
     // feature-major operands of the two weight gradients
+    if (l < L - 1 && (err = hipStreamWaitEvent(s, ffn_read, 0))) return err;   // recorded by layer l + 1
     hipLaunchKernelGGL((ffn_bwd_fused_kernel<MODE, D>), dim3((int)((rows + kFfnBwdRows - 1) / kFfnBwdRows)),
                        dim3(512), 0, s, XM, (const float*)f.dX, lp + m->po.ln2_g, lp + m->po.ln2_b, rows,
                        reinterpret_cast<const uint4*>(wl + m->pk.ffn1), reinterpret_cast<const uint4*>(wl + m->pk.ffn2T),
                        reinterpret_cast<const uint4*>(wl + m->pk.ffn1T), lp + m->po.ffn1_b, (AT*)f.T_b, (AT*)f.T_a,
                        (AT*)f.T_c, (AT*)f.T_d, f.ldT, f.dXM, f.colpart);
-    if ((err = wgrad<MODE, D, 4 * D>(m, f.T_d, f.T_b, rows, gl + m->po.ffn2_w, gl + m->po.ffn2_b, s))) return err;
-    if ((err = wgrad<MODE, 4 * D, D>(m, f.T_a, f.T_c, rows, gl + m->po.ffn1_w, gl + m->po.ffn1_b, s))) return err;
+    if ((err = hipEventRecord(ffn_ready, s))) return err;
+    if ((err = hipStreamWaitEvent(ss, ffn_ready, 0))) return err;
+    if ((err = wgrad<MODE, D, 4 * D>(m, f.T_d, f.T_b, rows, gl + m->po.ffn2_w, gl + m->po.ffn2_b, ss, D, f.part2)))
+      return err;
+    if ((err = wgrad<MODE, 4 * D, D>(m, f.T_a, f.T_c, rows, gl + m->po.ffn1_w, gl + m->po.ffn1_b, ss, 4 * D,
+                                     f.part2)))
+      return err;
+    if ((err = hipEventRecord(ffn_read, ss))) return err;
     colsum_add(f.colpart, (int)((rows + kFfnBwdRows - 1) / kFfnBwdRows), 2 * D, f.colpart2, gl + m->po.ln2_g, s);
     // ---- attention backward (dO = dXM: the heads' output is added to the residual directly);
     // probabilities are recomputed from Q, K and the saved log-sum-exp
+    if (l < L - 1 && (err = hipStreamWaitEvent(s, qkv_read, 0))) return err;   // recorded by layer l + 1
     if (D / H == 16) {
       const dim3 qgrid((N + attn_rows(kDqThreads) - 1) / attn_rows(kDqThreads) * H * nsamp);
       const dim3 kgrid((N + attn_rows(kDkvThreads) - 1) / attn_rows(kDkvThreads) * H * nsamp);
       if constexpr (MODE == FVAN_BF16_SPLIT) {
         hipLaunchKernelGGL(attn_bwd_dq_f16, qgrid, dim3(kDqThreads), 0, s, (const _Float16*)QKV, X, XM,
-                           (const float*)f.dXM, LSE, f.DELTA, (float*)f.dQKV, (float*)f.T_a, f.ldT, N, D, H, c.window,
+                           (const float*)f.dXM, LSE, f.DELTA, (float*)f.dQKV, (float*)f.T_e, f.ldT, N, D, H, c.window,
                            m->kg.P);
         hipLaunchKernelGGL(attn_bwd_dkv_f16, kgrid, dim3(kDkvThreads), 0, s, (const _Float16*)QKV,
-                           (const float*)f.dXM, LSE, (const float*)f.DELTA, (float*)f.dQKV, (float*)f.T_a, f.ldT, N,
+                           (const float*)f.dXM, LSE, (const float*)f.DELTA, (float*)f.dQKV, (float*)f.T_e, f.ldT, N,
                            D, H, c.window, m->kg.P);
       } else {
         hipLaunchKernelGGL((attn_bwd_dq_mfma<KT, AT, MODE>), qgrid, dim3(kDqThreads), 0, s, QKV, X, XM,
-                           (const float*)f.dXM, LSE, f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H, c.window,
+                           (const float*)f.dXM, LSE, f.DELTA, (AT*)f.dQKV, (AT*)f.T_e, f.ldT, N, D, H, c.window,
                            m->kg.P);
         hipLaunchKernelGGL((attn_bwd_dkv_mfma<KT, AT, MODE>), kgrid, dim3(kDkvThreads), 0, s, QKV,
-                           (const float*)f.dXM, LSE, (const float*)f.DELTA, (AT*)f.dQKV, (AT*)f.T_a, f.ldT, N, D, H,
+                           (const float*)f.dXM, LSE, (const float*)f.DELTA, (AT*)f.dQKV, (AT*)f.T_e, f.ldT, N, D, H,
                            c.window, m->kg.P);
       }
     } else if (D / H == 32) {
@@ -805,10 +822,16 @@ static hipError_t backward_chunk_t(fvan_model* m, const void* seq, int nsamp, co
     // also leaves LN1(x) feature-major for the W_qkv gradient
     hipLaunchKernelGGL((gemm_ln_bwd_kernel<MODE, D, 3 * D>), dim3((int)((rows + kGlbRows - 1) / kGlbRows)), dim3(512),
                        0, s, (const float*)f.dQKV, rows, reinterpret_cast<const uint4*>(wl + m->pk.qkvT), X,
-                       lp + m->po.ln1_g, lp + m->po.ln1_b, (const float*)f.dXM, f.dX, (float*)f.T_c, f.ldT, f.colpart);
-    if ((err = wgrad<MODE, 3 * D, D>(m, f.T_a, f.T_c, rows, gl + m->po.qkv_w, gl + m->po.qkv_b, s))) return err;
+                       lp + m->po.ln1_g, lp + m->po.ln1_b, (const float*)f.dXM, f.dX, (float*)f.T_f, f.ldT, f.colpart);
+    if ((err = hipEventRecord(qkv_ready, s))) return err;
+    if ((err = hipStreamWaitEvent(ss, qkv_ready, 0))) return err;
+    if ((err = wgrad<MODE, 3 * D, D>(m, f.T_e, f.T_f, rows, gl + m->po.qkv_w, gl + m->po.qkv_b, ss, 3 * D, f.part2)))
+      return err;
+    if ((err = hipEventRecord(qkv_read, ss))) return err;
     colsum_add(f.colpart, (int)((rows + kGlbRows - 1) / kGlbRows), 2 * D, f.colpart2, gl + m->po.ln1_g, s);
   }
+  // join: every side-stream kernel precedes what follows on the caller's stream
+  if ((err = hipStreamWaitEvent(s, qkv_read, 0))) return err;
   // embeddings
   const int64_t npos = (int64_t)N * (D - c.d_token);
   int slices = std::min(kPosSlices, nsamp);

@@ -39,22 +39,27 @@ struct fvan_model {
     float* XM = nullptr;           // [n_layers][rows][D] residual after attention
     float* LSE = nullptr;          // [n_layers][rows][H] log-sum-exp of the scores (base 2)
     float* DELTA = nullptr;        // [rows][H] dO . O per head (backward)
-    float* TMP = nullptr;          // [rows][D] LayerNorm-output gradients (backward)
     void* T_c = nullptr;           // [(D+16)][ldT] feature-major LN outputs (+ ones row) for weight gradients
     void* T_d = nullptr;           // [D][ldT] feature-major gradient at a block's output (left operand of dW2)
     int64_t ldT = 0;               // row stride of the feature-major buffers (rows rounded up to 64)
     void* QKV = nullptr;           // [n_layers][rows][3D] (K/V element type)
-    float* HPRE = nullptr;         // [rows][4D] FFN pre-activation (backward)
-    float* logp = nullptr;         // [rows] log p_t(s_t)
     // backward
     float* dX = nullptr;           // [rows][D]
     float* dXM = nullptr;          // [rows][D]
-    void* dH = nullptr;            // [rows][4D] gradient of the FFN pre-activation
     void* dQKV = nullptr;          // [rows][3D]
     void* T_a = nullptr;           // [4D][ldT] feature-major left operands of the weight gradients
     void* T_b = nullptr;           // [(4D+16)][ldT] feature-major GELU outputs (+ ones row)
+    void* T_e = nullptr;           // [3D][ldT] feature-major dQKV (left operand of the W_qkv gradient)
+    void* T_f = nullptr;           // [(D+16)][ldT] feature-major LN1 outputs (+ ones row) for the W_qkv gradient
     float* part = nullptr;         // split-K partial sums
+    float* part2 = nullptr;        // split-K partial sums of the weight gradients on the side stream
     size_t part_floats = 0;
+    // The layer weight gradients run on a stream of the model's own, forked from
+    // and joined back to the caller's stream with events, beside the next kernels
+    // of the backward: ev[0]/ev[1] = FFN operands ready / read, ev[2]/ev[3] =
+    // W_qkv operands ready / read.
+    hipStream_t side = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     float* colpart = nullptr;      // per-tile partial column sums (LN gains, head, embeddings)
     float* colpart2 = nullptr;     // second-level column sums [64][2D+2]
     size_t colpart_floats = 0;

@@ -53,14 +53,15 @@ static int allocate_fwd(fvan_model* m, hipStream_t s) {
   struct A { void** p; size_t bytes; const char* what; } allocs[] = {
       {(void**)&f.X, (size_t)(L + 1) * R * D * 4, "X"},   {(void**)&f.XM, (size_t)L * R * D * 4, "XM"},
       {(void**)&f.LSE, (size_t)L * R * H * 4, "LSE"},
-      {(void**)&f.DELTA, R * H * 4, "DELTA"},             {(void**)&f.TMP, R * D * 4, "TMP"},
-      {&f.QKV, (size_t)L * R * 3 * D * kt, "QKV"},       {(void**)&f.HPRE, R * 4 * D * 4, "HPRE"},
+      {(void**)&f.DELTA, R * H * 4, "DELTA"},
+      {&f.QKV, (size_t)L * R * 3 * D * kt, "QKV"},
       {(void**)&f.dX, R * D * 4, "dX"},                   {(void**)&f.dXM, R * D * 4, "dXM"},
-      {&f.dQKV, R * 3 * D * 4, "dQKV"},                   {&f.dH, R * 4 * D * 4, "dH"},
+      {&f.dQKV, R * 3 * D * 4, "dQKV"},
       {&f.T_a, 4 * D * ldT * 4, "T_a"},
       {&f.T_b, (4 * D + 16) * ldT * 4, "T_b"},            {&f.T_c, (D + 16) * ldT * 4, "T_c"},
       {&f.T_d, D * ldT * 4, "T_d"},
-      {(void**)&f.part, f.part_floats * 4, "partials"},   {(void**)&f.colpart, f.colpart_floats * 4, "column partials"},
+      {&f.T_e, 3 * D * ldT * 4, "T_e"},                   {&f.T_f, (D + 16) * ldT * 4, "T_f"},
+      {(void**)&f.part, f.part_floats * 4, "partials"},   {(void**)&f.part2, f.part_floats * 4, "side partials"},   {(void**)&f.colpart, f.colpart_floats * 4, "column partials"},
       {(void**)&f.colpart2, (size_t)64 * std::max<size_t>(2 * D + 2, (size_t)c.vocab * c.d_token) * 4,
        "column slices"},
   };
@@ -73,7 +74,20 @@ static int allocate_fwd(fvan_model* m, hipStream_t s) {
   if (e == hipSuccess) e = set_rows(f.T_b, f.ldT, 4 * D + 1, 15, f.ldT, 0.f, s);
   if (e == hipSuccess) e = set_rows(f.T_c, f.ldT, D, 1, f.ldT, 1.f, s);
   if (e == hipSuccess) e = set_rows(f.T_c, f.ldT, D + 1, 15, f.ldT, 0.f, s);
+  if (e == hipSuccess) e = set_rows(f.T_f, f.ldT, D, 1, f.ldT, 1.f, s);
+  if (e == hipSuccess) e = set_rows(f.T_f, f.ldT, D + 1, 15, f.ldT, 0.f, s);
   if (e != hipSuccess) return fail(FVAN_EDEVICE, std::string("workspace initialisation: ") + hipGetErrorString(e));
+  // the side stream of the layer weight gradients (default priority) and its events
+  if (hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking) != hipSuccess) {
+    f.side = nullptr;
+    return fail(FVAN_EDEVICE, "hipStreamCreate failed for the weight-gradient stream");
+  }
+  for (auto& ev : f.ev) {
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      ev = nullptr;
+      return fail(FVAN_EDEVICE, "hipEventCreate failed for the weight-gradient stream");
+    }
+  }
   return FVAN_OK;
 }
 
@@ -148,8 +162,15 @@ void model_free(fvan_model* m) {
 
 void model_free_fwd(fvan_model* m) {
   auto& f = m->fw;
-  dfree(f.X); dfree(f.XM); dfree(f.LSE); dfree(f.DELTA); dfree(f.TMP);
-  dfree(f.QKV); dfree(f.HPRE); dfree(f.logp); dfree(f.dX); dfree(f.dXM); dfree(f.dQKV); dfree(f.dH);
+  dfree(f.X); dfree(f.XM); dfree(f.LSE); dfree(f.DELTA);
+  dfree(f.QKV); dfree(f.dX); dfree(f.dXM); dfree(f.dQKV);
+  dfree(f.T_e); dfree(f.T_f); dfree(f.part2);
+  for (auto& ev : f.ev) {
+    if (ev) (void)hipEventDestroy(ev);
+    ev = nullptr;
+  }
+  if (f.side) (void)hipStreamDestroy(f.side);
+  f.side = nullptr;
   dfree(f.T_a); dfree(f.T_b); dfree(f.T_c); dfree(f.T_d); dfree(f.part); dfree(f.colpart); dfree(f.colpart2);
   m->fw = fvan_model::Fwd();
 }
