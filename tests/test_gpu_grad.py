@@ -202,3 +202,29 @@ def test_training_lowers_free_energy_sk16():
     assert abs(s - 1) < 1e-9
     assert Fq1 >= F - 1e-9
     assert Fq1 < Fq0 - 0.2 * (Fq0 - F)
+
+
+@pytest.mark.parametrize("prec", [FP32, SPLIT])
+def test_backward_on_a_caller_stream_matches_default_stream(prec):
+    """The backward forks its weight gradients onto a stream of the model and joins
+    it back: on a non-default caller stream, with calls queued back to back and a
+    gradient reset between them on that stream, the result is bitwise the
+    default-stream one (the reductions have a fixed order)."""
+    cfg = ModelConfig(40, 64, 3, 4).with_mask(6, 3)
+    m, theta = make_model(cfg, 24, prec, seed=21)
+    spins = torch.as_tensor(random_spins(24, 40, 5), device="cuda")
+    w = torch.linspace(-1, 1, 24, device="cuda")
+    m.grads.zero_()
+    m.log_prob_backward(spins, w)
+    torch.cuda.synchronize()
+    ref = m.grads.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            m.grads.zero_()
+            m.log_prob_backward(spins, w)
+        out = m.grads.clone()
+    torch.cuda.synchronize()
+    say(f"caller-stream backward, precision {prec}")
+    assert torch.equal(out, ref)
