@@ -31,6 +31,9 @@
 
 namespace fvan {
 
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 constexpr int kMaxVocab = 256;
@@ -59,18 +62,24 @@ struct DecodeSmem {
 __device__ __forceinline__ float reduce16(float v) { return row_sum16(v); }
 
 // LayerNorm of the KM residual rows into the MFMA operand buffer (16 lanes per row).
+// In split mode the output is written already split, once: each group of 8
+// consecutive elements of a row is a BF16 hi uint4 followed by its lo uint4 (the
+// same hi/lo as the GEMMs' own split of FP32 operands), so the QKV and FFN1
+// products read their A fragments without converting them per output tile.
 template <int D, int MODE, bool TOK, int KM>
 __device__ __forceinline__ void ln_rows(DecodeSmem<D, MODE, TOK, KM>& sm, const float* __restrict__ g,
                                         const float* __restrict__ b) {
   typedef typename Mode<MODE>::ActT T;
   constexpr int PER = D / 16;
+  constexpr bool SPLIT = Mode<MODE>::SPLIT;
   const int m = threadIdx.x >> 4, part = threadIdx.x & 15;
   if (m >= KM) return;
   float x[PER];
   float s = 0.f;
+  // split mode: PER consecutive elements per lane; otherwise strided by 16
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
-    x[i] = sm.h[m][part + 16 * i];
+    x[i] = sm.h[m][SPLIT ? part * PER + i : part + 16 * i];
     s += x[i];
   }
   const float mean = reduce16(s) * (1.0f / D);
@@ -81,10 +90,40 @@ __device__ __forceinline__ void ln_rows(DecodeSmem<D, MODE, TOK, KM>& sm, const 
     v += x[i] * x[i];
   }
   const float rstd = rsqrtf(reduce16(v) * (1.0f / D) + kLnEps);
+  if constexpr (SPLIT) {
+    static_assert(PER % 2 == 0 && 8 % PER == 0, "a lane's elements lie in one 8-element group");
+    float y[PER];
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int k = part + 16 * i;
-    sm.a[m][k] = from_f<T>(x[i] * rstd * g[k] + b[k]);
+    for (int i = 0; i < PER; ++i) {
+      const int k = part * PER + i;
+      y[i] = x[i] * rstd * g[k] + b[k];
+    }
+    // hi = bf16(y), lo = bf16(y - hi), two elements per 32-bit word
+    uint32_t hw[PER / 2], lw[PER / 2];
+#pragma unroll
+    for (int i = 0; i < PER; i += 2) {
+      const f32x2_t v2 = {y[i], y[i + 1]};
+      const bf16x2_t h2 = __builtin_convertvector(v2, bf16x2_t);
+      uint32_t hb;
+      __builtin_memcpy(&hb, &h2, 4);
+      const f32x2_t r2 = {y[i] - __uint_as_float(hb << 16), y[i + 1] - __uint_as_float(hb & 0xFFFF0000u)};
+      const bf16x2_t l2 = __builtin_convertvector(r2, bf16x2_t);
+      hw[i / 2] = hb;
+      __builtin_memcpy(&lw[i / 2], &l2, 4);
+    }
+    uint32_t* row = reinterpret_cast<uint32_t*>(&sm.a[m][0]);
+    const int j = part * PER / 8, o = (part * PER % 8) / 2;   // group, 32-bit word inside the group's uint4
+#pragma unroll
+    for (int w = 0; w < PER / 2; ++w) {
+      row[8 * j + o + w] = hw[w];
+      row[8 * j + 4 + o + w] = lw[w];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int k = part + 16 * i;
+      sm.a[m][k] = from_f<T>(x[i] * rstd * g[k] + b[k]);
+    }
   }
 }
 
@@ -95,7 +134,9 @@ __device__ __forceinline__ void ln_rows(DecodeSmem<D, MODE, TOK, KM>& sm, const 
 // a phase exposes one L2 latency instead of one per round.  Per tile the chunks
 // are summed in order, as a single pass over the tile would; acc1 stays zero
 // when NRT = 1.
-template <int MODE, int K, int NRT, typename Epi>
+// PRE: A holds split-mode operands written by ln_rows (per 8-element group a hi
+// uint4, then its lo uint4; row stride lda elements of Mode<2>::ActT).
+template <int MODE, int K, int NRT, typename Epi, bool PRE = false>
 __device__ __forceinline__ void mfma_tiles(const typename Mode<MODE>::ActT* A, int lda,
                                            const uint4* __restrict__ pack, size_t lo_u4, int nt0, int ntn, int step,
                                            int lane, Epi&& epi) {
@@ -106,8 +147,12 @@ __device__ __forceinline__ void mfma_tiles(const typename Mode<MODE>::ActT* A, i
   static_assert(NC % G == 0, "K chunks in groups of G");
   constexpr int R = NC / G;                 // rounds per tile
   if (nt0 >= ntn) return;
+  static_assert(!PRE || Mode<MODE>::SPLIT, "pre-split operands in split mode only");
   const typename Mode<MODE>::ActT* arow = A + (lane & 15) * lda + (lane >> 4) * (KC / 4);
   const typename Mode<MODE>::ActT* arow1 = arow + 16 * lda;
+  // pre-split: lane (g, c) takes group 4 kc + g of row c: uint4s 2 (4 kc + g) and + 1
+  const uint4* prow = reinterpret_cast<const uint4*>(A) + (lane & 15) * (lda * (int)sizeof(*A) / 16) + 2 * (lane >> 4);
+  const uint4* prow1 = prow + 16 * (lda * (int)sizeof(*A) / 16);
   uint4 bh[G], bl[G], nh[G], nl[G];
 #define FVAN_DT_LOAD(T, RR, H, L)                                                              \
   _Pragma("unroll") for (int u = 0; u < G; ++u) {                                            \
@@ -130,11 +175,31 @@ __device__ __forceinline__ void mfma_tiles(const typename Mode<MODE>::ActT* A, i
     }
 #pragma unroll
     for (int u = 0; u < G; ++u) {
-      const int k = (r * G + u) * KC;
-      if constexpr (NRT == 2)
-        Frag<MODE>::step2v(arow + k, arow1 + k, bh[u], bl[u], acc0, acc1);
-      else
-        Frag<MODE>::step1v(arow + k, bh[u], bl[u], acc0);
+      const int kc = r * G + u;
+      if constexpr (PRE) {
+        // the same three products in the same order as Frag<2>::step1v / step2v
+        static_assert(KC == 32, "four 8-element groups per K chunk");
+        const uint4 xh = prow[8 * kc], xl = prow[8 * kc + 1];
+        if constexpr (NRT == 2) {
+          const uint4 yh = prow1[8 * kc], yl = prow1[8 * kc + 1];
+          acc0 = mfma_bf16(xl, bh[u], acc0);
+          acc1 = mfma_bf16(yl, bh[u], acc1);
+          acc0 = mfma_bf16(xh, bl[u], acc0);
+          acc1 = mfma_bf16(yh, bl[u], acc1);
+          acc0 = mfma_bf16(xh, bh[u], acc0);
+          acc1 = mfma_bf16(yh, bh[u], acc1);
+        } else {
+          acc0 = mfma_bf16(xl, bh[u], acc0);
+          acc0 = mfma_bf16(xh, bl[u], acc0);
+          acc0 = mfma_bf16(xh, bh[u], acc0);
+        }
+      } else {
+        const int k = kc * KC;
+        if constexpr (NRT == 2)
+          Frag<MODE>::step2v(arow + k, arow1 + k, bh[u], bl[u], acc0, acc1);
+        else
+          Frag<MODE>::step1v(arow + k, bh[u], bl[u], acc0);
+      }
     }
     if (r == R - 1) {
       epi(nt, acc0, acc1);
@@ -204,8 +269,7 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK, KM>& sm, const DecodeUnit& 
       // ---- QKV projection; k_t, v_t appended to the cache ----
       {
         const uint4* pk = reinterpret_cast<const uint4*>(wl + U.p_qkv);
-        mfma_tiles<MODE, D, NRT>(&sm.a[0][0], Sm::LDA, pk, (size_t)3 * D * D / 8, wave, 3 * D / 16, kWaves, lane,
-                                 [&](int nt, const floatx4& a0, const floatx4& a1) {
+        auto qkv_epi = [&](int nt, const floatx4& a0, const floatx4& a1) {
           const floatx4 acc[2] = {a0, a1};
           const int n = nt * 16 + (lane & 15);
           const float bias = lp[U.o_qkv_b + n];
@@ -222,7 +286,9 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK, KM>& sm, const DecodeUnit& 
               *dst = from_f<T>(val);
             }
           }
-        });
+        };
+        mfma_tiles<MODE, D, NRT, decltype(qkv_epi)&, Mode<MODE>::SPLIT>(&sm.a[0][0], Sm::LDA, pk, (size_t)3 * D * D / 8,
+                                                                       wave, 3 * D / 16, kWaves, lane, qkv_epi);
       }
       __threadfence_block();
       __syncthreads();
@@ -335,8 +401,7 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK, KM>& sm, const DecodeUnit& 
       __syncthreads();
       {
         const uint4* p1 = reinterpret_cast<const uint4*>(wl + U.p_ffn1);
-        mfma_tiles<MODE, D, NRT>(&sm.a[0][0], Sm::LDA, p1, (size_t)4 * D * D / 8, wave, 4 * D / 16, kWaves, lane,
-                                 [&](int nt, const floatx4& a0, const floatx4& a1) {
+        auto ffn1_epi = [&](int nt, const floatx4& a0, const floatx4& a1) {
           const floatx4 acc[2] = {a0, a1};
           const int n = nt * 16 + (lane & 15);
           const float bias = lp[U.o_ffn1_b + n];
@@ -344,7 +409,9 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK, KM>& sm, const DecodeUnit& 
           for (int ri = 0; ri < 4 * NRT; ++ri)
             sm.u.hid[16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3)][n] =
                 from_f<typename Mode<MODE>::ActT>(gelu(acc[ri >> 2][ri & 3] + bias));
-        });
+        };
+        mfma_tiles<MODE, D, NRT, decltype(ffn1_epi)&, Mode<MODE>::SPLIT>(&sm.a[0][0], Sm::LDA, p1, (size_t)4 * D * D / 8,
+                                                                        wave, 4 * D / 16, kWaves, lane, ffn1_epi);
       }
       __syncthreads();
       {
