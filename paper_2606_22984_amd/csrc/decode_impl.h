@@ -401,14 +401,26 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK, KM>& sm, const DecodeUnit& 
       __syncthreads();
       {
         const uint4* p1 = reinterpret_cast<const uint4*>(wl + U.p_ffn1);
+        // split mode: GELU(h) goes to LDS already split, in the layout ln_rows
+        // writes (per 8-element group of a row: 8 hi BF16, then 8 lo), for FFN2
         auto ffn1_epi = [&](int nt, const floatx4& a0, const floatx4& a1) {
           const floatx4 acc[2] = {a0, a1};
           const int n = nt * 16 + (lane & 15);
           const float bias = lp[U.o_ffn1_b + n];
 #pragma unroll
-          for (int ri = 0; ri < 4 * NRT; ++ri)
-            sm.u.hid[16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3)][n] =
-                from_f<typename Mode<MODE>::ActT>(gelu(acc[ri >> 2][ri & 3] + bias));
+          for (int ri = 0; ri < 4 * NRT; ++ri) {
+            const int row = 16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3);
+            const float gv = gelu(acc[ri >> 2][ri & 3] + bias);
+            if constexpr (Mode<MODE>::SPLIT) {
+              const __bf16 hb = (__bf16)gv;
+              const __bf16 lb = (__bf16)(gv - (float)hb);
+              __bf16* hr = reinterpret_cast<__bf16*>(&sm.u.hid[row][0]) + (n >> 3) * 16 + (n & 7);
+              hr[0] = hb;
+              hr[8] = lb;
+            } else {
+              sm.u.hid[row][n] = from_f<typename Mode<MODE>::ActT>(gv);
+            }
+          }
         };
         mfma_tiles<MODE, D, NRT, decltype(ffn1_epi)&, Mode<MODE>::SPLIT>(&sm.a[0][0], Sm::LDA, p1, (size_t)4 * D * D / 8,
                                                                         wave, 4 * D / 16, kWaves, lane, ffn1_epi);
@@ -416,14 +428,16 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK, KM>& sm, const DecodeUnit& 
       __syncthreads();
       {
         const uint4* p2 = reinterpret_cast<const uint4*>(wl + U.p_ffn2);
-        mfma_tiles<MODE, 4 * D, NRT>(&sm.u.hid[0][0], Sm::LDH, p2, (size_t)4 * D * D / 8, wave, D / 16, kWaves, lane,
-                                     [&](int nt, const floatx4& a0, const floatx4& a1) {
+        auto ffn2_epi = [&](int nt, const floatx4& a0, const floatx4& a1) {
           const floatx4 acc[2] = {a0, a1};
           const int n = nt * 16 + (lane & 15);
           const float bias = lp[U.o_ffn2_b + n];
 #pragma unroll
           for (int ri = 0; ri < 4 * NRT; ++ri) sm.h[16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3)][n] += acc[ri >> 2][ri & 3] + bias;
-        });
+        };
+        mfma_tiles<MODE, 4 * D, NRT, decltype(ffn2_epi)&, Mode<MODE>::SPLIT>(&sm.u.hid[0][0], Sm::LDH, p2,
+                                                                            (size_t)4 * D * D / 8, wave, D / 16,
+                                                                            kWaves, lane, ffn2_epi);
       }
       __syncthreads();
     }
