@@ -411,8 +411,8 @@ typedef struct {
   double* stats;                    /* device [2] as fvan_free_energy */
 } fvan_group_unit;
 
-/* Build the device unit table and choose the launch shape (spec:
- * batched launches with tile shapes from an autotuner).  tile_samples: samples
+/* Build the device unit table and choose the launch shape (many instances,
+ * sizes and temperatures in one persistent launch).  tile_samples: samples
  * per work item and decode workgroup, 16 or 32, or 0 to let the autotuner
  * choose it.  The autotuner searches the tile and the persistent grid size
  * (1, 2 and 4 workgroups per compute unit, and the grid whose samples in
