@@ -56,6 +56,10 @@ struct DecodeSmem {
   } u;
   int tok[KM];
   int8_t sbuf[KM][64];
+  // FFN2 partial sums of the waves that take the upper K ranges in split mode
+  // when d < 128 (fewer output tiles than waves; FP32 mode measured no gain)
+  static constexpr int KP = Mode<MODE>::SPLIT && D / 16 < kWaves ? kWaves / (D / 16) - 1 : 0;
+  float kpart[KP > 0 ? KP : 1][KP > 0 ? KM : 1][KP > 0 ? D : 1];
 };
 
 
@@ -428,16 +432,55 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK, KM>& sm, const DecodeUnit& 
       __syncthreads();
       {
         const uint4* p2 = reinterpret_cast<const uint4*>(wl + U.p_ffn2);
-        auto ffn2_epi = [&](int nt, const floatx4& a0, const floatx4& a1) {
-          const floatx4 acc[2] = {a0, a1};
-          const int n = nt * 16 + (lane & 15);
-          const float bias = lp[U.o_ffn2_b + n];
+        constexpr int NT2 = D / 16;         // output tiles
+        if constexpr (Sm::KP == 0) {
+          auto ffn2_epi = [&](int nt, const floatx4& a0, const floatx4& a1) {
+            const floatx4 acc[2] = {a0, a1};
+            const int n = nt * 16 + (lane & 15);
+            const float bias = lp[U.o_ffn2_b + n];
 #pragma unroll
-          for (int ri = 0; ri < 4 * NRT; ++ri) sm.h[16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3)][n] += acc[ri >> 2][ri & 3] + bias;
-        };
-        mfma_tiles<MODE, 4 * D, NRT, decltype(ffn2_epi)&, Mode<MODE>::SPLIT>(&sm.u.hid[0][0], Sm::LDH, p2,
-                                                                            (size_t)4 * D * D / 8, wave, D / 16,
-                                                                            kWaves, lane, ffn2_epi);
+            for (int ri = 0; ri < 4 * NRT; ++ri)
+              sm.h[16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3)][n] += acc[ri >> 2][ri & 3] + bias;
+          };
+          mfma_tiles<MODE, 4 * D, NRT, decltype(ffn2_epi)&, Mode<MODE>::SPLIT>(&sm.u.hid[0][0], Sm::LDH, p2,
+                                                                              (size_t)4 * D * D / 8, wave, NT2,
+                                                                              kWaves, lane, ffn2_epi);
+        } else {
+          // fewer output tiles than waves: the SK waves of a tile take consecutive
+          // K ranges; the upper ranges' sums meet the lowest one's through LDS and
+          // are added in range order
+          constexpr int SK = Sm::KP + 1;
+          constexpr int KC = Mode<MODE>::KC;
+          constexpr int NC2 = 4 * D / KC, NCS = NC2 / SK;
+          static_assert(NC2 % SK == 0, "whole K chunks per range");
+          const int tile = wave % NT2, part = wave / NT2;
+          const int n = tile * 16 + (lane & 15);
+          floatx4 r[2];
+          auto keep = [&](int, const floatx4& a0, const floatx4& a1) {
+            r[0] = a0;
+            r[1] = a1;
+          };
+          mfma_tiles<MODE, 4 * D / SK, NRT, decltype(keep)&, Mode<MODE>::SPLIT>(
+              &sm.u.hid[0][0] + part * NCS * KC, Sm::LDH, p2 + ((size_t)tile * NC2 + (size_t)part * NCS) * 64,
+              (size_t)4 * D * D / 8, 0, 1, 1, lane, keep);
+          if (part > 0) {
+#pragma unroll
+            for (int ri = 0; ri < 4 * NRT; ++ri)
+              sm.kpart[part - 1][16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3)][n] = r[ri >> 2][ri & 3];
+          }
+          __syncthreads();
+          if (part == 0) {
+            const float bias = lp[U.o_ffn2_b + n];
+#pragma unroll
+            for (int ri = 0; ri < 4 * NRT; ++ri) {
+              const int row = 16 * (ri >> 2) + 4 * (lane >> 4) + (ri & 3);
+              float v = r[ri >> 2][ri & 3];
+#pragma unroll
+              for (int q = 0; q < Sm::KP; ++q) v += sm.kpart[q][row][n];
+              sm.h[row][n] += v + bias;
+            }
+          }
+        }
       }
       __syncthreads();
     }
