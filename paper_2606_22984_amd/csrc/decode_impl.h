@@ -164,18 +164,30 @@ __device__ __forceinline__ void mfma_tiles(const typename Mode<MODE>::ActT* A, i
     H[u] = bp_[0];                                                                           \
     L[u] = Mode<MODE>::SPLIT ? bp_[lo_u4] : H[u];                                            \
   }
+  // rounds are consumed in order; the loads of the next two rounds are in flight
+  // while a round multiplies
+  auto advance = [&](int& t, int& rr) {
+    if (++rr == R) {
+      rr = 0;
+      t += step;
+    }
+  };
+  uint4 mh[G], ml[G];
   FVAN_DT_LOAD(nt0, 0, bh, bl);
+  int nt1 = nt0, r1 = 0;
+  advance(nt1, r1);
+  bool more1 = nt1 < ntn;
+  if (more1) {
+    FVAN_DT_LOAD(nt1, r1, nh, nl);
+  }
   floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
   int nt = nt0, r = 0;
   for (;;) {
-    int nn = nt, rn = r + 1;
-    if (rn == R) {
-      rn = 0;
-      nn = nt + step;
-    }
-    const bool more = nn < ntn;
-    if (more) {
-      FVAN_DT_LOAD(nn, rn, nh, nl);
+    int nt2 = nt1, r2 = r1;
+    advance(nt2, r2);
+    const bool more2 = more1 && nt2 < ntn;
+    if (more2) {
+      FVAN_DT_LOAD(nt2, r2, mh, ml);
     }
 #pragma unroll
     for (int u = 0; u < G; ++u) {
@@ -210,13 +222,18 @@ __device__ __forceinline__ void mfma_tiles(const typename Mode<MODE>::ActT* A, i
       acc0 = floatx4{0.f, 0.f, 0.f, 0.f};
       acc1 = acc0;
     }
-    if (!more) break;
-    nt = nn;
-    r = rn;
+    if (!more1) break;
+    nt = nt1;
+    r = r1;
+    nt1 = nt2;
+    r1 = r2;
+    more1 = more2;
 #pragma unroll
     for (int u = 0; u < G; ++u) {
       bh[u] = nh[u];
       bl[u] = nl[u];
+      nh[u] = mh[u];
+      nl[u] = ml[u];
     }
   }
 #undef FVAN_DT_LOAD
