@@ -312,13 +312,17 @@ static __global__ __launch_bounds__(kDqThreads) void attn_bwd_dq_f16(const _Floa
       const half4_t ka = *reinterpret_cast<const half4_t*>(&Kh[kb + c][4 * g]);
       const floatx4 sa = __builtin_amdgcn_mfma_f32_16x16x16f16(ka, qh, floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
       const floatx4 pa = mma_hl_dup(Va[kb + c][g], gB, floatx4{0.f, 0.f, 0.f, 0.f});   // dP^T[key 4g+i][query c]
-      float ds[4];
+      float p[4], ds[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        float p = __builtin_amdgcn_exp2f(fmaf(sa[i], kScaleLog2, -lse));
-        if (!full) p = vis(vb + 4 * g + i) ? p : 0.f;
-        ds[i] = p * (pa[i] - delta);
+      for (int i = 0; i < 4; ++i) p[i] = __builtin_amdgcn_exp2f(fmaf(sa[i], kScaleLog2, -lse));
+      // one branch on the wave-uniform class around all four masks: per element the
+      // compiler would turn the test into selects computed for full tiles too
+      if (!full) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) p[i] = vis(vb + 4 * g + i) ? p[i] : 0.f;
       }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ds[i] = p[i] * (pa[i] - delta);
       // dQ[query][dim] += dS[query][key] K[key][dim]; the lane's dS is the A layout of dS
       dq = mma_dup_hl(split_dup(ds[0], ds[1], ds[2], ds[3]), Kb[c][kb / 4 + g], dq);
     }
@@ -433,11 +437,13 @@ static __global__ __launch_bounds__(kDkvThreads) void attn_bwd_dkv_f16(const _Fl
       const float lq[4] = {l4.x, l4.y, l4.z, l4.w}, dl[4] = {d4.x, d4.y, d4.z, d4.w};
       float p[4], ds[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        p[i] = __builtin_amdgcn_exp2f(fmaf(sa[i], kScaleLog2, -lq[i]));
-        if (!full) p[i] = (unsigned)(iq0 + 4 * g + i - jk) < (unsigned)qw ? p[i] : 0.f;
-        ds[i] = p[i] * (pa[i] - dl[i]);
+      for (int i = 0; i < 4; ++i) p[i] = __builtin_amdgcn_exp2f(fmaf(sa[i], kScaleLog2, -lq[i]));
+      if (!full) {   // one uniform branch around all four masks, as in the dQ kernel
+#pragma unroll
+        for (int i = 0; i < 4; ++i) p[i] = (unsigned)(iq0 + 4 * g + i - jk) < (unsigned)qw ? p[i] : 0.f;
       }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ds[i] = p[i] * (pa[i] - dl[i]);
       dv = mma_dup_hl(split_dup(p[0], p[1], p[2], p[3]), Gb[c][q0 / 4 + g], dv);      // dV += P^T dO
       dk = mma_dup_hl(split_dup(ds[0], ds[1], ds[2], ds[3]), Qb[c][q0 / 4 + g], dk);  // dK += dS^T Q
     }
