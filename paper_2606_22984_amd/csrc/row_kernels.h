@@ -562,9 +562,10 @@ __device__ __forceinline__ void ln_bwd_rows(floatx4 (&acc)[D / 16], const float*
 // and W2^T, columns of W1^T) are staged in LDS once for all eight waves, in two
 // alternating buffers so that the next chunk is committed while the current one
 // is read (one barrier per chunk), the chunk after it fetched into registers
-// meanwhile, and each wave's h, g and
-// dH go through a wave-private LDS tile; they reach HBM only as the two
-// feature-major weight-gradient operands.  (One wave loading every weight for
+// meanwhile.  g and dH reach HBM only as the two feature-major weight-gradient
+// operands, stored straight from the accumulator layout (a lane holds four
+// consecutive rows of one hidden unit); dH also goes through a wave-private LDS
+// tile, where the dA product reads it in the A layout.  (One wave loading every weight for
 // its own 16 rows made the kernel bound by L2 reads of the weights.)
 // p1: W1 [4D x D] pack; p2t: W2^T [4D x D] pack; p1t: W1^T [D x 4D] pack.
 constexpr int kFfnBwdRows = 128;
@@ -596,7 +597,6 @@ __global__ __launch_bounds__(512) void ffn_bwd_fused_kernel(
   constexpr int NPRE = (NPL * SW + 64 * NW - 1) / (64 * NW);   // staged fragments per thread
   constexpr int LDH = HC + 4;
   __shared__ __align__(16) uint4 Ws[2][NPL][SW];   // two stages of [W1 chunk | W2^T chunk | W1^T chunk]
-  __shared__ __align__(16) float Hg[NW][16][LDH];
   __shared__ __align__(16) float Hd[NW][16][LDH];
   __shared__ float red[NW][2 * D];
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), g = lane >> 4, c = lane & 15;
@@ -654,7 +654,6 @@ __global__ __launch_bounds__(512) void ffn_bwd_fused_kernel(
   floatx4 acc[NT2];
 #pragma unroll
   for (int t = 0; t < NT2; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  float (*HG)[LDH] = Hg[wave];
   float (*HD)[LDH] = Hd[wave];
   constexpr int PLO = NPL > 1 ? SW : 0;      // hi-to-lo distance in the stage
   for (int hc = 0; hc < NH; ++hc) {
@@ -671,12 +670,28 @@ __global__ __launch_bounds__(512) void ffn_bwd_fused_kernel(
         ag = fy[cc].mma(W2s + f, W2s + f + PLO, ag);
       }
       const float bias = b1[hc * HC + t * 16 + c];
+      float gv[4], dh[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        float gv, gp;
-        gelu_and_grad(ah[i] + bias, gv, gp);
-        HG[4 * g + i][16 * t + c] = gv;
-        HD[4 * g + i][16 * t + c] = ag[i] * gp;
+        float gpr;
+        gelu_and_grad(ah[i] + bias, gv[i], gpr);
+        dh[i] = ag[i] * gpr;
+        HD[4 * g + i][16 * t + c] = dh[i];
+      }
+      // feature-major g and dH: hidden unit hc HC + 16 t + c, rows rbase + 4 g ..
+      const int64_t n = (int64_t)hc * HC + 16 * t + c;
+      AT* gq = Gt + n * ldT + rbase + 4 * g;
+      AT* dq = dHt + n * ldT + rbase + 4 * g;
+      if (full) {
+        *reinterpret_cast<float4*>(gq) = make_float4(gv[0], gv[1], gv[2], gv[3]);
+        *reinterpret_cast<float4*>(dq) = make_float4(dh[0], dh[1], dh[2], dh[3]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (rbase + 4 * g + i < rows) {
+            gq[i] = gv[i];
+            dq[i] = dh[i];
+          }
       }
     }
     wave_lds_sync();
@@ -689,29 +704,6 @@ __global__ __launch_bounds__(512) void ffn_bwd_fused_kernel(
       for (int t = 0; t < NT2; ++t) {
         const int f = (t * NC2H + cc) * 64 + lane;
         acc[t] = hd.mma(W3s + f, W3s + f + PLO, acc[t]);
-      }
-    }
-    // feature-major g and dH: lane -> (hidden unit lane % 32, rows 8 (lane / 32) .. +7)
-    {
-      const int u = lane & 31, q0 = (lane >> 5) * 8;
-      const int64_t n = (int64_t)hc * HC + u;
-      AT* gp = Gt + n * ldT + rbase + q0;
-      AT* dp = dHt + n * ldT + rbase + q0;
-      if (full) {
-#pragma unroll
-        for (int q = 0; q < 8; q += 4) {
-          *reinterpret_cast<float4*>(gp + q) =
-              make_float4(HG[q0 + q][u], HG[q0 + q + 1][u], HG[q0 + q + 2][u], HG[q0 + q + 3][u]);
-          *reinterpret_cast<float4*>(dp + q) =
-              make_float4(HD[q0 + q][u], HD[q0 + q + 1][u], HD[q0 + q + 2][u], HD[q0 + q + 3][u]);
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (rbase + q0 + q < rows) {
-            gp[q] = HG[q0 + q][u];
-            dp[q] = HD[q0 + q][u];
-          }
       }
     }
     // the other stage was last read in chunk hc - 1, which every wave finished
