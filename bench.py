@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 --pmc runs, each scaled by the same counter's reading for a 1 GiB copy);
 # the record with the commands is profiles/decode_ea3d_L10_hbm_counters.md.
 # Set to None whenever decode_kernel changes until the counters are taken again.
-DECODE_TRAFFIC_BYTES = 12353904600480
+DECODE_TRAFFIC_BYTES = 12385239098720
 # learning rate: the paper's eta = 1e-3 reached by a linear warm-up over 300 steps
 # (Methods, model configurations and training settings); the timed steps sit at
 # the start of the warm-up

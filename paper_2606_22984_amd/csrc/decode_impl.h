@@ -65,6 +65,15 @@ struct DecodeSmem {
 
 __device__ __forceinline__ float reduce16(float v) { return row_sum16(v); }
 
+// 16-byte load of the K/V stream, marked non-temporal so that it does not push
+// the layer weights out of L2
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ uint4 stream_load16(const T* p) {
+  const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // LayerNorm of the KM residual rows into the MFMA operand buffer (16 lanes per row).
 // In split mode the output is written already split, once: each group of 8
 // consecutive elements of a row is a BF16 hi uint4 followed by its lo uint4 (the
@@ -337,8 +346,8 @@ __device__ void decode_tile(DecodeSmem<D, MODE, TOK, KM>& sm, const DecodeUnit& 
             kk[u] = make_uint4(0u, 0u, 0u, 0u);
             vv[u] = kk[u];
             if (s < nvis) {
-              kk[u] = *reinterpret_cast<const uint4*>(Kb + (size_t)s * D + lcol);
-              vv[u] = *reinterpret_cast<const uint4*>(Kb + plane + (size_t)s * D + lcol);
+              kk[u] = stream_load16(Kb + (size_t)s * D + lcol);
+              vv[u] = stream_load16(Kb + plane + (size_t)s * D + lcol);
             }
           }
         };
