@@ -14,6 +14,14 @@ constexpr float kLnEps = 1e-5f;
 
 typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
 
+// 16-byte non-temporal load of row data that a kernel reads exactly once, so that
+// the stream does not push the weights other workgroups re-read out of L2.
+typedef float f32x4nt_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 load_nt4(const float* p) {
+  const f32x4nt_t v = __builtin_nontemporal_load(reinterpret_cast<const f32x4nt_t*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // Precision modes (fvan_precision: 0 and 2).  KvT: K/V cache element; ActT: stored GEMM
 // A operand (activations); WT: packed weight element; KC: K consumed per
 // 16x16 MFMA fragment step; SPLIT: weights and activations are carried as

@@ -60,8 +60,10 @@ __global__ __launch_bounds__(256) void ln_kernel(const float* __restrict__ X, in
 // A fragments of one 16-row tile computed as LayerNorm(X row) (affine g, b;
 // population variance, eps kLnEps): lane (g, c) holds row c's elements
 // cc*KC + g*LK .. +LK for every chunk cc, so the four lanes of a row together
-// hold it whole and the row statistics are two pair reductions.
-template <int MODE, int K>
+// hold it whole and the row statistics are two pair reductions.  NT: the rows are
+// read with non-temporal loads (for a kernel that reads each row once, long after
+// it was written, while L2 serves it re-read weights).
+template <int MODE, int K, bool NT = false>
 __device__ __forceinline__ void load_ln_frags(const float* __restrict__ X, int64_t row,
                                               const float* __restrict__ gam, const float* __restrict__ bet, int g,
                                               FragA<MODE>* fa) {
@@ -73,7 +75,8 @@ __device__ __forceinline__ void load_ln_frags(const float* __restrict__ X, int64
   for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
     for (int i = 0; i < LK; i += 4) {
-      const float4 v = *reinterpret_cast<const float4*>(X + row * K + cc * KC + g * LK + i);
+      const float* xp = X + row * K + cc * KC + g * LK + i;
+      const float4 v = NT ? load_nt4(xp) : *reinterpret_cast<const float4*>(xp);
       x[cc][i] = v.x; x[cc][i + 1] = v.y; x[cc][i + 2] = v.z; x[cc][i + 3] = v.w;
       s += (v.x + v.y) + (v.z + v.w);
     }
@@ -639,13 +642,13 @@ __global__ __launch_bounds__(512) void ffn_bwd_fused_kernel(
   // A fragments of the wave's rows (clamped; every output below is guarded)
   const int64_t ra = std::min<int64_t>(rbase + c, rows - 1);
   FragA<MODE> fa[NC1], fy[NC1];
-  load_ln_frags<MODE, D>(X, ra, ln_g, ln_b, g, fa);
+  load_ln_frags<MODE, D, true>(X, ra, ln_g, ln_b, g, fa);
 #pragma unroll
   for (int cc = 0; cc < NC1; ++cc) {
     alignas(16) AT af[LK];
 #pragma unroll
     for (int i = 0; i < LK; i += 4)
-      *reinterpret_cast<float4*>(&af[i]) = *reinterpret_cast<const float4*>(dY + ra * D + cc * KC + g * LK + i);
+      *reinterpret_cast<float4*>(&af[i]) = load_nt4(dY + ra * D + cc * KC + g * LK + i);
     fy[cc].load(af);
   }
   FVAN_FB_COMMIT(0);
