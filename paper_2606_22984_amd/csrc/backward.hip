@@ -217,6 +217,11 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
                                                     const typename Mode<MODE>::ActT* __restrict__ B, int64_t ldb,
                                                     int64_t K, int64_t kper, int m_total, int n_total,
                                                     int nsplit_m, int nsplit_n, float* __restrict__ part) {
+  // in split mode an operand no other workgroup of this K slice re-reads (A when
+  // the output's columns are not split, B when its rows are not) is streamed with
+  // non-temporal loads, so that it does not evict what the co-running attention
+  // backward re-reads from L2 (FP32 mode measured no gain)
+  const bool nt_a = Mode<MODE>::SPLIT && nsplit_n == 1, nt_b = Mode<MODE>::SPLIT && nsplit_m == 1;
   typedef typename Mode<MODE>::ActT AT;
   // split mode stages each operand already split into BF16 hi and lo planes, so a
   // K chunk is converted once instead of once per wave that multiplies it
@@ -264,7 +269,12 @@ __global__ __launch_bounds__(512) void wgrad_kernel(const typename Mode<MODE>::A
         const AT* src = row < M ? A + (int64_t)row * lda : B + (int64_t)(row - M) * ldb;
         const int64_t kk = k + piece * VPL;
         if (full) {
-          pre[u] = *reinterpret_cast<const uint4*>(src + kk);
+          if (row < M ? nt_a : nt_b) {
+            const float4 f = load_nt4(reinterpret_cast<const float*>(src + kk));
+            pre[u] = make_uint4(__float_as_uint(f.x), __float_as_uint(f.y), __float_as_uint(f.z), __float_as_uint(f.w));
+          } else {
+            pre[u] = *reinterpret_cast<const uint4*>(src + kk);
+          }
         } else {
           alignas(16) AT tmp[VPL];
 #pragma unroll
